@@ -1,0 +1,211 @@
+/*
+ * mgct — preconditioned multigrid Landweber reconstruction for cone-beam CT
+ * on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Myers et al., "Rapidly-converging multigrid reconstruction of
+ * cone-beam tomographic data" (arXiv 2103.10329).  Data model: Beer-Lambert,
+ * b = ln(I0/I) = P mu (Sec. 2, eq. 1).  Iterations: Landweber / SIRT (eq. 2),
+ * preconditioned Landweber (eq. 4, with the 3^3 kernel of eq. 5 or an
+ * isotropic Fourier-space deconvolution filter, Sec. 3), OS-EMTR (eq. 3),
+ * and the recursive multigrid of Algorithm 1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns an int status: MGCT_OK (0) or a negative mgct_status.
+ *   mgct_status_string() describes a code.  On error nothing is launched.
+ * - Buffers: every array argument named "device" is device memory owned by
+ *   the caller (the library never frees it).  Arrays named "host" are host
+ *   memory, read (or written) before the call returns.
+ * - Stream ordering: work is enqueued on `stream` (0 = the null stream); the
+ *   outputs are valid once the stream has been synchronised.  Calls that
+ *   return a host scalar (residual norms, step sizes, histories) synchronise
+ *   the stream themselves.  Outputs are overwritten, never accumulated
+ *   (except mgct_prolong_add, whose purpose is to add).
+ * - Layouts: a volume is [nz][ny][nx] with x fastest; a detector stack is
+ *   [n_views][nv][nu] with u (detector column) fastest.  Geometry is in
+ *   physical units; voxel (i,j,k) is centred at
+ *   origin + ((i,j,k) - (n-1)/2) * voxel, and pixel (a,b) of view v at
+ *   d + (a-(nu-1)/2) u + (b-(nv-1)/2) v.
+ * - Grid levels: level g (0 = finest) halves every volume and detector size
+ *   g times and doubles the voxel size and the pixel steps g times, with the
+ *   same source and detector-centre positions (Algorithm 1 shares the
+ *   trajectory between grids).  Sizes must be divisible by 2^g.
+ * - A context serialises nothing: calls on one context must not overlap in
+ *   time on different streams (they share workspace).
+ */
+#ifndef MGCT_H
+#define MGCT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MGCT_OK = 0,
+    MGCT_ERR_INVALID_ARG = -1,          /* null pointer, bad size, bad enum value */
+    MGCT_ERR_UNSUPPORTED_GEOMETRY = -2, /* a ray whose largest direction component is along z */
+    MGCT_ERR_SIZE_NOT_DIVISIBLE = -3,   /* a size not divisible by 2^level */
+    MGCT_ERR_OOM = -4,                  /* device allocation failed */
+    MGCT_ERR_HIP = -5,                  /* a HIP runtime call failed */
+    MGCT_ERR_DIVERGED = -6,             /* the residual grew: step size too large */
+    MGCT_ERR_NOT_IMPLEMENTED = -7,      /* combination not provided (e.g. radial filter on non-power-of-2 grid) */
+    MGCT_ERR_NO_GEOMETRY = -8           /* mgct_set_geometry has not been called */
+} mgct_status;
+
+typedef enum { MGCT_F32 = 0, MGCT_F16 = 1, MGCT_BF16 = 2 } mgct_dtype;
+
+typedef enum {
+    MGCT_FILTER_IDENTITY = 0,  /* p = delta: plain Landweber / SIRT, eq. 2 */
+    MGCT_FILTER_STENCIL27 = 1, /* circular 3^3 convolution, eq. 5 taps (or any 27 taps) */
+    MGCT_FILTER_RADIAL = 2     /* circular convolution applied in Fourier space: H(rho) */
+} mgct_filter_kind;
+
+/*
+ * Preconditioning kernel p of eq. 4.
+ * STENCIL27: taps[(dz+1)*9 + (dy+1)*3 + (dx+1)]; out[z,y,x] = sum taps[d] in[(z,y,x)-d],
+ *   indices wrapped (circular).  mgct_filter_eq5() fills in eq. 5.
+ * RADIAL: the 3-D DFT of the volume (sized to the grid, circular) is
+ *   multiplied by H(rho), rho = 2 sqrt(sum_a (k_a/N_a)^2) with signed
+ *   frequencies k_a in [-N_a/2, N_a/2), and H is linear interpolation of
+ *   `radial_table` (host, n_table >= 2 samples uniformly on [0, rho_max],
+ *   clamped beyond).  Every grid edge must be a power of two, 2..1024.
+ */
+typedef struct {
+    int kind;
+    float taps[27];
+    const float *radial_table;
+    int n_table;
+    float rho_max;
+} mgct_filter;
+
+/* Parameters of Algorithm 1 (mgct_multigrid_solve). */
+typedef struct {
+    int levels;            /* L >= 1; grid L-1 is solved by OS-EMTR when L >= 2 */
+    int n_outer;           /* full multigrid iterations */
+    mgct_filter filter;    /* preconditioner on every Landweber grid */
+    double alpha[8];       /* step of grid g (g < L-1, or g = 0 when L = 1); <= 0: 1/lambda_max */
+    int power_iters;       /* power iterations for automatic steps (e.g. 30) */
+    uint64_t power_seed;   /* SplitMix64 seed of the power-iteration start vector */
+    double lambda;         /* soft threshold (0 = off) */
+    int bilateral_on;      /* bilateral filter after every Landweber step */
+    double sigma_s;        /* spatial sigma, voxels */
+    double sigma_r;        /* range sigma, attenuation units */
+    int coarse_subsets;    /* OS-EMTR subsets M (views i with i mod M == m) */
+    int coarse_passes;     /* OS-EMTR passes over all subsets per coarse solve */
+} mgct_mg_params;
+
+const char *mgct_status_string(int status);
+
+/* Fill `f` with eq. 5's kernel (taps /64, the printed matrices as z-slices). */
+int mgct_filter_eq5(mgct_filter *f);
+
+/* Create a context on HIP device `device` (made current by every call). */
+int mgct_create(int device, void **ctx_out);
+int mgct_destroy(void *ctx);
+
+/*
+ * Geometry of the scan (paper Sec. 2, eq. 1: the projection operator is set
+ * by the volume grid and the source/detector positions Theta).
+ * views: host, n_views x 12 doubles per view: s[3], d[3], u[3], v[3].
+ * The library copies what it needs.  Rejects (UNSUPPORTED_GEOMETRY) any
+ * geometry with a ray whose largest |direction component| is along z, and
+ * any geometry whose source lies within one voxel of the volume box.
+ */
+int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const double origin[3],
+                      int nu, int nv, int n_views, const double *views);
+
+/*
+ * proj = A vol on grid `level` (Sec. 2, eq. 1's P): Joseph's method — every
+ * ray is sampled on the voxel-centre planes of its major axis between source
+ * and pixel, with bilinear interpolation (zero outside the grid), times the
+ * sample spacing.  vol: device, vol_dtype F32 or BF16.  proj: device,
+ * proj_dtype F32 or F16.  Accumulation is FP32.
+ */
+int mgct_project(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype,
+                 hipStream_t stream);
+
+/*
+ * vol = A^T proj on grid `level` (Sec. 2.1: B is the adjoint of P): exact
+ * transpose of mgct_project, evaluated voxel by voxel (a gather; no atomics,
+ * so results are bit-identical from run to run).  proj: device, F32 or F16;
+ * vol: device, F32 or BF16.  FP32 accumulation over views.
+ */
+int mgct_backproject(void *ctx, int level, const void *proj, int proj_dtype, void *vol, int vol_dtype,
+                     hipStream_t stream);
+
+/* out = p * in on grid `level` (eq. 4's convolution).  in, out: device F32 volumes (may alias). */
+int mgct_precondition(void *ctx, int level, const float *in, float *out, const mgct_filter *f,
+                      hipStream_t stream);
+
+/*
+ * Step size for eq. 2 / eq. 4 on grid `level`: alpha = 1/lambda with lambda
+ * the largest eigenvalue of x -> p * A^T A x, from `iters` power iterations
+ * started at SplitMix64 uniforms (output k: state seed + (k+1) * golden
+ * gamma).  alpha: host, written.  f may be NULL (identity).
+ */
+int mgct_estimate_step(void *ctx, int level, const mgct_filter *f, int iters, uint64_t seed,
+                       double *alpha, hipStream_t stream);
+
+/*
+ * One Landweber step on grid `level`: vol += alpha * p * A^T (b - A vol)
+ * (eq. 4; f NULL or IDENTITY gives SIRT, eq. 2).  vol: device F32, updated in
+ * place.  b: device stack of that grid, F32 or F16.  resid_norm: host, may be
+ * NULL; receives ||b - A vol|| of the input volume (FP64 reduction).
+ */
+int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_dtype, double alpha,
+                        const mgct_filter *f, double *resid_norm, hipStream_t stream);
+
+/* Restrict (Algorithm 1): coarse = 2x2x2 block mean of fine (grid level -> level+1). */
+int mgct_restrict_volume(void *ctx, int level, const float *fine, float *coarse, hipStream_t stream);
+
+/* Restrict (Algorithm 1) of the data: coarse stack = 2x2 pixel mean of b (grid level -> level+1). */
+int mgct_restrict_stack(void *ctx, int level, const float *fine, float *coarse, hipStream_t stream);
+
+/*
+ * Prolongate and correct (Algorithm 1): fine += P(coarse_new - coarse_old),
+ * P cell-centred trilinear (weights 3/4, 1/4; edges clamped).  fine on grid
+ * `level`, coarse arrays on grid level+1.
+ */
+int mgct_prolong_add(void *ctx, int level, const float *coarse_new, const float *coarse_old, float *fine,
+                     hipStream_t stream);
+
+/* SoftThreshold (Algorithm 1): vol = sign(vol) max(|vol| - lambda, 0), in place. */
+int mgct_soft_threshold(void *ctx, int level, float *vol, double lambda, hipStream_t stream);
+
+/*
+ * BilateralFilter (Algorithm 1): out = normalised 3^3 bilateral filter of in
+ * (spatial weight exp(-|d|^2/2 sigma_s^2), range weight
+ * exp(-(in_n - in)^2 / 2 sigma_r^2), neighbours outside the grid left out).
+ * in and out must not alias.
+ */
+int mgct_bilateral(void *ctx, int level, const float *in, float *out, double sigma_s, double sigma_r,
+                   hipStream_t stream);
+
+/*
+ * OS-EMTR (eq. 3) on grid `level`: `passes` passes over M = `subsets`
+ * interleaved view subsets; per subset
+ * vol += A_m^T(e - exp(-b)) / A_m^T(e * A1), e = exp(-A_m vol),
+ * where A1 is A applied to a volume of ones (support = the grid); voxels with
+ * denominator <= 1e-6 * max(denominator) are left unchanged.
+ * vol: device F32, in place; b: device F32 stack of that grid.
+ */
+int mgct_osemtr(void *ctx, int level, float *vol, const float *b, int subsets, int passes, hipStream_t stream);
+
+/*
+ * Algorithm 1, `p->n_outer` full iterations starting from vol (device F32,
+ * in place, finest grid).  b: device stack of the finest grid (F32 or F16).
+ * resid_hist: host, may be NULL, n_outer x levels doubles: entry [n][g] is
+ * ||b_g - A_g mu|| before grid g's Landweber step (g < L-1) and, for
+ * g = L-1, before the coarse OS-EMTR solve.
+ */
+int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, const mgct_mg_params *p,
+                         double *resid_hist, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGCT_H */

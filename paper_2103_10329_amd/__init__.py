@@ -1,0 +1,307 @@
+"""Python binding of libmgct (the C ABI declared in include/mgct.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of libmgct.so.  The raw entry points are exposed under their C
+names (``mgct_project`` ...); ``Context`` wraps them for torch tensors that
+live on the GPU.  Importing this package does not need a GPU; loading the
+library does, and fails loudly if it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgct.so")
+
+MGCT_OK = 0
+MGCT_ERR_INVALID_ARG = -1
+MGCT_ERR_UNSUPPORTED_GEOMETRY = -2
+MGCT_ERR_SIZE_NOT_DIVISIBLE = -3
+MGCT_ERR_OOM = -4
+MGCT_ERR_HIP = -5
+MGCT_ERR_DIVERGED = -6
+MGCT_ERR_NOT_IMPLEMENTED = -7
+MGCT_ERR_NO_GEOMETRY = -8
+
+MGCT_F32, MGCT_F16, MGCT_BF16 = 0, 1, 2
+MGCT_FILTER_IDENTITY, MGCT_FILTER_STENCIL27, MGCT_FILTER_RADIAL = 0, 1, 2
+
+
+class mgct_filter(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("taps", ctypes.c_float * 27),
+        ("radial_table", ctypes.POINTER(ctypes.c_float)),
+        ("n_table", ctypes.c_int),
+        ("rho_max", ctypes.c_float),
+    ]
+
+
+class mgct_mg_params(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int),
+        ("n_outer", ctypes.c_int),
+        ("filter", mgct_filter),
+        ("alpha", ctypes.c_double * 8),
+        ("power_iters", ctypes.c_int),
+        ("power_seed", ctypes.c_uint64),
+        ("lambda_", ctypes.c_double),
+        ("bilateral_on", ctypes.c_int),
+        ("sigma_s", ctypes.c_double),
+        ("sigma_r", ctypes.c_double),
+        ("coarse_subsets", ctypes.c_int),
+        ("coarse_passes", ctypes.c_int),
+    ]
+
+
+# name -> (restype, argtypes); mirrors include/mgct.h
+_vp, _ci, _cd, _u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(mgct_filter)
+SIGNATURES = {
+    "mgct_status_string": (ctypes.c_char_p, [_ci]),
+    "mgct_filter_eq5": (_ci, [_fp]),
+    "mgct_create": (_ci, [_ci, ctypes.POINTER(_vp)]),
+    "mgct_destroy": (_ci, [_vp]),
+    "mgct_set_geometry": (_ci, [_vp, _ci, _ci, _ci, _cd, _dp, _ci, _ci, _ci, _dp]),
+    "mgct_project": (_ci, [_vp, _ci, _vp, _ci, _vp, _ci, _vp]),
+    "mgct_backproject": (_ci, [_vp, _ci, _vp, _ci, _vp, _ci, _vp]),
+    "mgct_precondition": (_ci, [_vp, _ci, _vp, _vp, _fp, _vp]),
+    "mgct_estimate_step": (_ci, [_vp, _ci, _fp, _ci, _u64, _dp, _vp]),
+    "mgct_landweber_step": (_ci, [_vp, _ci, _vp, _vp, _ci, _cd, _fp, _dp, _vp]),
+    "mgct_restrict_volume": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "mgct_restrict_stack": (_ci, [_vp, _ci, _vp, _vp, _vp]),
+    "mgct_prolong_add": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
+    "mgct_soft_threshold": (_ci, [_vp, _ci, _vp, _cd, _vp]),
+    "mgct_bilateral": (_ci, [_vp, _ci, _vp, _vp, _cd, _cd, _vp]),
+    "mgct_osemtr": (_ci, [_vp, _ci, _vp, _vp, _ci, _ci, _vp]),
+    "mgct_multigrid_solve": (_ci, [_vp, _vp, _vp, _ci, ctypes.POINTER(mgct_mg_params), _dp, _vp]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmgct.so (built by ``python -m paper_2103_10329_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmgct.so is not built (%s); run python -m paper_2103_10329_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+        globals()[name] = fn
+    _lib = lib
+    return lib
+
+
+class MgctError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        load_library()
+        msg = mgct_status_string(code).decode()  # noqa: F821
+        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+        self.code = code
+
+
+def check(code: int, where: str = "mgct"):
+    if code != MGCT_OK:
+        raise MgctError(code, where)
+
+
+# --------------------------------------------------------------- filters ---
+
+def filter_identity() -> mgct_filter:
+    f = mgct_filter()
+    f.kind = MGCT_FILTER_IDENTITY
+    return f
+
+
+def filter_eq5() -> mgct_filter:
+    load_library()
+    f = mgct_filter()
+    check(mgct_filter_eq5(ctypes.byref(f)), "mgct_filter_eq5")  # noqa: F821
+    return f
+
+
+def filter_stencil27(taps) -> mgct_filter:
+    f = mgct_filter()
+    f.kind = MGCT_FILTER_STENCIL27
+    t = np.asarray(taps, dtype=np.float32).reshape(27)
+    for i in range(27):
+        f.taps[i] = float(t[i])
+    return f
+
+
+def filter_radial(table, rho_max: float) -> mgct_filter:
+    """Radial Fourier filter from a sampled profile (the array is kept alive
+    on the returned structure)."""
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float32))
+    f = mgct_filter()
+    f.kind = MGCT_FILTER_RADIAL
+    f.radial_table = t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    f.n_table = t.size
+    f.rho_max = float(rho_max)
+    f._keep = t
+    return f
+
+
+def ramp_table(n: int, n_table: int = 4097, rho_max: float = math.sqrt(3.0)):
+    """Samples of the isotropic ramp H(rho) = max(rho, 2/n) on [0, rho_max]."""
+    rho = np.linspace(0.0, rho_max, n_table)
+    return np.maximum(rho, 2.0 / n).astype(np.float32), rho_max
+
+
+# --------------------------------------------------------------- context ---
+
+_DT = {"float32": MGCT_F32, "float16": MGCT_F16, "bfloat16": MGCT_BF16}
+
+
+def _dtype_code(t) -> int:
+    name = str(t.dtype).replace("torch.", "")
+    if name not in _DT:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return _DT[name]
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libmgct context bound to one device and one scan geometry."""
+
+    def __init__(self, device: int = 0):
+        load_library()
+        h = ctypes.c_void_p()
+        check(mgct_create(device, ctypes.byref(h)), "mgct_create")  # noqa: F821
+        self.handle = h
+        self.device = device
+        self.geom = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            mgct_destroy(self.handle)  # noqa: F821
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, nx, ny, nz, voxel, origin, nu, nv, views):
+        views = np.ascontiguousarray(np.asarray(views, dtype=np.float64).reshape(-1, 12))
+        org = np.ascontiguousarray(np.asarray(origin, dtype=np.float64).reshape(3))
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(mgct_set_geometry(self.handle, nx, ny, nz, float(voxel), org.ctypes.data_as(dp), nu, nv,  # noqa: F821
+                                views.shape[0], views.ctypes.data_as(dp)), "mgct_set_geometry")
+        self.geom = dict(nx=nx, ny=ny, nz=nz, nu=nu, nv=nv, n_views=views.shape[0], voxel=voxel)
+
+    def shapes(self, level: int = 0):
+        g = self.geom
+        f = 2 ** level
+        return (g["nz"] // f, g["ny"] // f, g["nx"] // f), (g["n_views"], g["nv"] // f, g["nu"] // f)
+
+    # ---- operators
+    def project(self, vol, out=None, level: int = 0, out_dtype=None):
+        import torch
+        vs, ss = self.shapes(level)
+        if out is None:
+            out = torch.empty(ss, dtype=out_dtype or torch.float32, device=vol.device)
+        check(mgct_project(self.handle, level, _ptr(vol), _dtype_code(vol), _ptr(out), _dtype_code(out),  # noqa: F821
+                           _stream()), "mgct_project")
+        return out
+
+    def backproject(self, proj, out=None, level: int = 0, out_dtype=None):
+        import torch
+        vs, ss = self.shapes(level)
+        if out is None:
+            out = torch.empty(vs, dtype=out_dtype or torch.float32, device=proj.device)
+        check(mgct_backproject(self.handle, level, _ptr(proj), _dtype_code(proj), _ptr(out), _dtype_code(out),  # noqa: F821
+                               _stream()), "mgct_backproject")
+        return out
+
+    def precondition(self, x, filt, out=None, level: int = 0):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        check(mgct_precondition(self.handle, level, _ptr(x), _ptr(out), ctypes.byref(filt), _stream()),  # noqa: F821
+              "mgct_precondition")
+        return out
+
+    def estimate_step(self, filt=None, level: int = 0, iters: int = 30, seed: int = 0) -> float:
+        a = ctypes.c_double()
+        fp = ctypes.byref(filt) if filt is not None else None
+        check(mgct_estimate_step(self.handle, level, fp, iters, seed, ctypes.byref(a), _stream()),  # noqa: F821
+              "mgct_estimate_step")
+        return a.value
+
+    def landweber_step(self, vol, b, alpha, filt=None, level: int = 0, want_norm: bool = True):
+        r = ctypes.c_double()
+        fp = ctypes.byref(filt) if filt is not None else None
+        check(mgct_landweber_step(self.handle, level, _ptr(vol), _ptr(b), _dtype_code(b), float(alpha), fp,  # noqa: F821
+                                  ctypes.byref(r) if want_norm else None, _stream()), "mgct_landweber_step")
+        return r.value if want_norm else None
+
+    def restrict_volume(self, fine, coarse, level: int = 0):
+        check(mgct_restrict_volume(self.handle, level, _ptr(fine), _ptr(coarse), _stream()),  # noqa: F821
+              "mgct_restrict_volume")
+
+    def restrict_stack(self, fine, coarse, level: int = 0):
+        check(mgct_restrict_stack(self.handle, level, _ptr(fine), _ptr(coarse), _stream()),  # noqa: F821
+              "mgct_restrict_stack")
+
+    def prolong_add(self, cnew, cold, fine, level: int = 0):
+        check(mgct_prolong_add(self.handle, level, _ptr(cnew), _ptr(cold), _ptr(fine), _stream()),  # noqa: F821
+              "mgct_prolong_add")
+
+    def soft_threshold(self, vol, lam, level: int = 0):
+        check(mgct_soft_threshold(self.handle, level, _ptr(vol), float(lam), _stream()),  # noqa: F821
+              "mgct_soft_threshold")
+
+    def bilateral(self, x, out, sigma_s, sigma_r, level: int = 0):
+        check(mgct_bilateral(self.handle, level, _ptr(x), _ptr(out), float(sigma_s), float(sigma_r),  # noqa: F821
+                             _stream()), "mgct_bilateral")
+
+    def osemtr(self, vol, b, subsets=8, passes=2, level: int = 0):
+        check(mgct_osemtr(self.handle, level, _ptr(vol), _ptr(b), subsets, passes, _stream()),  # noqa: F821
+              "mgct_osemtr")
+
+    def multigrid_solve(self, vol, b, levels, n_outer, filt, alphas=None, power_iters=30, power_seed=0,
+                        lam=0.0, bilateral=None, coarse_subsets=8, coarse_passes=2, want_hist=True):
+        p = mgct_mg_params()
+        p.levels = levels
+        p.n_outer = n_outer
+        p.filter = filt
+        for i in range(8):
+            p.alpha[i] = 0.0
+        if alphas is not None:
+            for i, a in enumerate(alphas):
+                p.alpha[i] = float(a)
+        p.power_iters = power_iters
+        p.power_seed = power_seed
+        p.lambda_ = lam
+        p.bilateral_on = 1 if bilateral else 0
+        p.sigma_s, p.sigma_r = bilateral if bilateral else (1.0, 1.0)
+        p.coarse_subsets = coarse_subsets
+        p.coarse_passes = coarse_passes
+        hist = np.zeros(max(n_outer * levels, 1))
+        hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_hist else None
+        check(mgct_multigrid_solve(self.handle, _ptr(vol), _ptr(b), _dtype_code(b), ctypes.byref(p), hp,  # noqa: F821
+                                   _stream()), "mgct_multigrid_solve")
+        return hist[: n_outer * levels].reshape(n_outer, levels) if want_hist else None

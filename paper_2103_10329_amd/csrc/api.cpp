@@ -1,0 +1,552 @@
+// C-ABI entry points and the host-side orchestration of the iterations
+// (Landweber / SIRT, OS-EMTR, power iteration, Algorithm 1).  Every
+// arithmetic step runs in the HIP kernels; this file validates arguments,
+// manages workspaces and enqueues kernels on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <functional>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mgct_internal.h"
+
+using namespace mgct;
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return MGCT_ERR_HIP; \
+    } while (0)
+#define MGCHK(x)                 \
+    do {                         \
+        int r_ = (x);            \
+        if (r_ != MGCT_OK) return r_; \
+    } while (0)
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+
+Ctx *as_ctx(void *p) { return static_cast<Ctx *>(p); }
+
+void *workspace(Ctx &c, const std::string &name, size_t bytes, bool zero = false) {
+    if (bytes == 0) bytes = 1;
+    auto it = c.ws.find(name);
+    if (it != c.ws.end()) {
+        if (it->second.second >= bytes) return it->second.first;
+        (void)hipFree(it->second.first);
+        c.ws.erase(it);
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (zero && hipMemset(p, 0, bytes) != hipSuccess) {
+        (void)hipFree(p);
+        return nullptr;
+    }
+    c.ws[name] = {p, bytes};
+    return p;
+}
+
+#define WS(var, type, name, bytes, zero)                                   \
+    type *var = static_cast<type *>(workspace(c, (name), (bytes), (zero))); \
+    if (!var) return MGCT_ERR_OOM
+
+int get_level(Ctx &c, int g, Level **out) {
+    if (!c.has_geom) return MGCT_ERR_NO_GEOMETRY;
+    if (g < 0 || g > 10) return MGCT_ERR_INVALID_ARG;
+    if ((int)c.levels.size() <= g) c.levels.resize(g + 1);
+    Level &L = c.levels[g];
+    if (L.nx == 0) {
+        int r = build_level(c, g, L);
+        if (r != MGCT_OK) {
+            free_level(L);
+            L = Level();
+            return r;
+        }
+    }
+    *out = &L;
+    return MGCT_OK;
+}
+
+std::string lvl(const char *name, int g) { return std::string(name) + "@" + std::to_string(g); }
+
+bool vol_dtype_ok(int d) { return d == MGCT_F32 || d == MGCT_BF16; }
+bool stack_dtype_ok(int d) { return d == MGCT_F32 || d == MGCT_F16; }
+
+// ---- projector and transpose on a subset of views (view0 + k*step, k < nsub)
+int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *proj, int proj_dtype, int view0,
+               int step, int nsub, hipStream_t s) {
+    const int vt_dtype = vol_dtype;
+    const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
+    void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es, true);
+    if (!vt) return MGCT_ERR_OOM;
+    HIPCHK(launch_transpose_volume(vol, vol_dtype, vt, vt_dtype, L, s));
+    HIPCHK(launch_project(vt, vt_dtype, proj, proj_dtype, L, view0, step, nsub, s));
+    return MGCT_OK;
+}
+
+int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, void *vol, int vol_dtype, int view0,
+                   int step, int nsub, hipStream_t s) {
+    if (!L.separable) return MGCT_ERR_NOT_IMPLEMENTED;
+    WS(pt, float, lvl("pt", g), (size_t)nsub * L.nu * L.nv * 4, false);
+    HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, L, view0, step, nsub, s));
+    HIPCHK(launch_backproject(pt, vol, vol_dtype, L, view0, step, nsub, s));
+    return MGCT_OK;
+}
+
+int check_filter(const mgct_filter *f, const Level &L) {
+    if (!f) return MGCT_OK;
+    if (f->kind == MGCT_FILTER_IDENTITY || f->kind == MGCT_FILTER_STENCIL27) return MGCT_OK;
+    if (f->kind == MGCT_FILTER_RADIAL) {
+        if (!f->radial_table || f->n_table < 2 || !(f->rho_max > 0.f)) return MGCT_ERR_INVALID_ARG;
+        if (!fft_size_ok(L.nx) || !fft_size_ok(L.ny) || !fft_size_ok(L.nz)) return MGCT_ERR_NOT_IMPLEMENTED;
+        return MGCT_OK;
+    }
+    return MGCT_ERR_INVALID_ARG;
+}
+
+int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const mgct_filter *f, hipStream_t s) {
+    MGCHK(check_filter(f, L));
+    const size_t n = L.vox();
+    if (!f || f->kind == MGCT_FILTER_IDENTITY) {
+        if (in != out) HIPCHK(launch_copy(in, out, n, s));
+        return MGCT_OK;
+    }
+    if (f->kind == MGCT_FILTER_STENCIL27) {
+        WS(taps, float, "taps27", 27 * 4, false);
+        HIPCHK(hipMemcpyAsync(taps, f->taps, 27 * 4, hipMemcpyHostToDevice, s));
+        const float *src = in;
+        if (in == out) {
+            WS(tmp, float, lvl("st_tmp", g), n * 4, false);
+            HIPCHK(launch_copy(in, tmp, n, s));
+            src = tmp;
+        }
+        HIPCHK(launch_stencil27(src, out, L.nx, L.ny, L.nz, taps, s));
+        return MGCT_OK;
+    }
+    // RADIAL
+    WS(table, float, "radial_table", (size_t)f->n_table * 4, false);
+    HIPCHK(hipMemcpyAsync(table, f->radial_table, (size_t)f->n_table * 4, hipMemcpyHostToDevice, s));
+    const size_t ntw = L.nx / 2 + L.ny / 2 + L.nz / 2;
+    std::string twname = "tw_" + std::to_string(L.nx) + "_" + std::to_string(L.ny) + "_" + std::to_string(L.nz);
+    bool fresh = c.ws.find(twname) == c.ws.end();
+    WS(tw, float2, twname, ntw * sizeof(float2), false);
+    if (fresh) {
+        std::vector<float2> all, t;
+        host_twiddles(L.nx, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.nx / 2);
+        host_twiddles(L.ny, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.ny / 2);
+        host_twiddles(L.nz, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.nz / 2);
+        HIPCHK(hipMemcpy(tw, all.data(), ntw * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    WS(work, float2, "fft_work", n * sizeof(float2), false);
+    HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, table, f->n_table, f->rho_max, tw, s));
+    return MGCT_OK;
+}
+
+// norm2_out: device double receiving ||b - A vol||^2 (may be null)
+int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype, double alpha, const mgct_filter *f,
+                 double *norm2_out, hipStream_t s) {
+    WS(ax, float, lvl("lw_ax", g), L.rays() * 4, false);
+    WS(r, float, lvl("lw_r", g), L.rays() * 4, false);
+    WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
+    WS(part, double, "red_partials", kRedBlocks * 8, false);
+    WS(nrm, double, "red_scratch", 8, false);
+    MGCHK(do_project(c, L, g, vol, MGCT_F32, ax, MGCT_F32, 0, 1, L.nviews, s));
+    HIPCHK(launch_residual(b, b_dtype, ax, r, L.rays(), part, kRedBlocks, s));
+    HIPCHK(launch_finish_sum(part, kRedBlocks, norm2_out ? norm2_out : nrm, s));
+    MGCHK(do_backproject(c, L, g, r, MGCT_F32, grad, MGCT_F32, 0, 1, L.nviews, s));
+    MGCHK(do_precondition(c, L, g, grad, grad, f, s));
+    HIPCHK(launch_axpy(vol, grad, alpha, L.vox(), s));
+    return MGCT_OK;
+}
+
+int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out, hipStream_t s) {
+    WS(ax, float, lvl("lw_ax", g), L.rays() * 4, false);
+    WS(r, float, lvl("lw_r", g), L.rays() * 4, false);
+    WS(part, double, "red_partials", kRedBlocks * 8, false);
+    MGCHK(do_project(c, L, g, vol, MGCT_F32, ax, MGCT_F32, 0, 1, L.nviews, s));
+    HIPCHK(launch_residual(b, MGCT_F32, ax, r, L.rays(), part, kRedBlocks, s));
+    HIPCHK(launch_finish_sum(part, kRedBlocks, norm2_out, s));
+    return MGCT_OK;
+}
+
+int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int passes, hipStream_t s) {
+    const size_t n = L.vox(), per = (size_t)L.nu * L.nv;
+    const int maxsub = (L.nviews + M - 1) / M;
+    WS(ones, float, lvl("emtr_ones", g), n * 4, false);
+    WS(pi, float, lvl("emtr_pi", g), L.rays() * 4, false);
+    WS(l, float, lvl("emtr_l", g), maxsub * per * 4, false);
+    WS(nsrc, float, lvl("emtr_ns", g), maxsub * per * 4, false);
+    WS(dsrc, float, lvl("emtr_ds", g), maxsub * per * 4, false);
+    WS(pt1, float, lvl("emtr_pt1", g), maxsub * per * 4, false);
+    WS(num, float, lvl("emtr_num", g), n * 4, false);
+    WS(den, float, lvl("emtr_den", g), n * 4, false);
+    WS(mx, unsigned, "emtr_max", 4, false);
+    WS(pt0, float, lvl("pt", g), (size_t)L.nviews * per * 4, false);
+    // support projection A 1 (support = the whole grid)
+    HIPCHK(launch_fill(ones, n, 1.f, s));
+    MGCHK(do_project(c, L, g, ones, MGCT_F32, pi, MGCT_F32, 0, 1, L.nviews, s));
+    for (int p = 0; p < passes; ++p) {
+        for (int m = 0; m < M && m < L.nviews; ++m) {
+            const int nsub = (L.nviews - m + M - 1) / M;
+            MGCHK(do_project(c, L, g, vol, MGCT_F32, l, MGCT_F32, m, M, nsub, s));
+            HIPCHK(launch_emtr_terms(l, b, pi, nsrc, dsrc, L, m, M, nsub, s));
+            HIPCHK(launch_scale_transpose_stack(nsrc, MGCT_F32, pt0, L, m, M, nsub, s));
+            HIPCHK(launch_scale_transpose_stack(dsrc, MGCT_F32, pt1, L, m, M, nsub, s));
+            HIPCHK(launch_backproject2(pt0, pt1, num, den, L, m, M, nsub, s));
+            HIPCHK(launch_max_reset(mx, s));
+            HIPCHK(launch_max_reduce(den, n, mx, s));
+            HIPCHK(launch_emtr_update(vol, num, den, n, mx, s));
+        }
+    }
+    return MGCT_OK;
+}
+
+std::string filter_key(const mgct_filter *f) {
+    std::ostringstream o;
+    if (!f || f->kind == MGCT_FILTER_IDENTITY) return "id";
+    o << f->kind << ":";
+    if (f->kind == MGCT_FILTER_STENCIL27)
+        for (int i = 0; i < 27; ++i) o << f->taps[i] << ",";
+    else {
+        o << f->n_table << "," << f->rho_max << ",";
+        uint64_t hsh = 1469598103934665603ull;
+        const unsigned char *p = (const unsigned char *)f->radial_table;
+        for (size_t i = 0; i < (size_t)f->n_table * 4; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
+        o << hsh;
+    }
+    return o.str();
+}
+
+int do_estimate(Ctx &c, Level &L, int g, const mgct_filter *f, int iters, uint64_t seed, double *alpha,
+                hipStream_t s) {
+    MGCHK(check_filter(f, L));
+    const size_t n = L.vox();
+    WS(x, float, lvl("pw_x", g), n * 4, false);
+    WS(y, float, lvl("pw_y", g), n * 4, false);
+    WS(p, float, lvl("pw_p", g), L.rays() * 4, false);
+    WS(part, double, "red_partials", kRedBlocks * 8, false);
+    WS(d, double, "pw_scalars", 16, false);
+    HIPCHK(launch_splitmix_uniform(x, n, seed, s));
+    HIPCHK(launch_sumsq(x, n, part, kRedBlocks, s));
+    HIPCHK(launch_finish_sum(part, kRedBlocks, d, s));
+    HIPCHK(launch_scale_by_inv_sqrt(x, n, d, nullptr, s));
+    for (int it = 0; it < iters; ++it) {
+        MGCHK(do_project(c, L, g, x, MGCT_F32, p, MGCT_F32, 0, 1, L.nviews, s));
+        MGCHK(do_backproject(c, L, g, p, MGCT_F32, y, MGCT_F32, 0, 1, L.nviews, s));
+        MGCHK(do_precondition(c, L, g, y, y, f, s));
+        HIPCHK(launch_sumsq(y, n, part, kRedBlocks, s));
+        HIPCHK(launch_finish_sum(part, kRedBlocks, d, s));
+        HIPCHK(launch_scale_by_inv_sqrt(y, n, d, d + 1, s));
+        float *t = x;
+        x = y;
+        y = t;
+    }
+    double lam = 0.0;
+    HIPCHK(hipMemcpyAsync(&lam, d + 1, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (iters <= 0 || !(lam > 0.0) || !isfinite(lam)) return MGCT_ERR_DIVERGED;
+    *alpha = 1.0 / lam;
+    return MGCT_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+extern "C" {
+
+const char *mgct_status_string(int st) {
+    switch (st) {
+        case MGCT_OK: return "ok";
+        case MGCT_ERR_INVALID_ARG: return "invalid argument";
+        case MGCT_ERR_UNSUPPORTED_GEOMETRY: return "unsupported geometry (z-major ray or source inside the volume)";
+        case MGCT_ERR_SIZE_NOT_DIVISIBLE: return "size not divisible by 2^level";
+        case MGCT_ERR_OOM: return "device allocation failed";
+        case MGCT_ERR_HIP: return "HIP runtime error";
+        case MGCT_ERR_DIVERGED: return "iteration diverged (non-positive or non-finite spectrum estimate)";
+        case MGCT_ERR_NOT_IMPLEMENTED: return "not implemented for these arguments";
+        case MGCT_ERR_NO_GEOMETRY: return "no geometry set";
+        default: return "unknown status";
+    }
+}
+
+int mgct_filter_eq5(mgct_filter *f) {
+    if (!f) return MGCT_ERR_INVALID_ARG;
+    static const float outer[9] = {-1, -1, -1, -1, 0, -1, -1, -1, -1};
+    static const float middle[9] = {-8, -4, -8, -4, 64, -4, -8, -4, -8};
+    memset(f, 0, sizeof(*f));
+    f->kind = MGCT_FILTER_STENCIL27;
+    for (int i = 0; i < 9; ++i) {
+        f->taps[i] = outer[i] / 64.f;
+        f->taps[9 + i] = middle[i] / 64.f;
+        f->taps[18 + i] = outer[i] / 64.f;
+    }
+    return MGCT_OK;
+}
+
+int mgct_create(int device, void **ctx_out) {
+    if (!ctx_out) return MGCT_ERR_INVALID_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MGCT_ERR_INVALID_ARG;
+    HIPCHK(hipSetDevice(device));
+    Ctx *c = new Ctx();
+    c->device = device;
+    *ctx_out = c;
+    return MGCT_OK;
+}
+
+int mgct_destroy(void *ctx) {
+    if (!ctx) return MGCT_ERR_INVALID_ARG;
+    Ctx *c = as_ctx(ctx);
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->ws) (void)hipFree(kv.second.first);
+    for (auto &L : c->levels) free_level(L);
+    delete c;
+    return MGCT_OK;
+}
+
+int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const double origin[3], int nu, int nv,
+                      int n_views, const double *views) {
+    if (!ctx) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    MGCHK(check_geometry(nx, ny, nz, voxel, origin, nu, nv, n_views, views));
+    HIPCHK(hipDeviceSynchronize());
+    for (auto &L : c.levels) free_level(L);
+    c.levels.clear();
+    c.alpha_cache.clear();
+    c.nx = nx; c.ny = ny; c.nz = nz; c.nu = nu; c.nv = nv; c.nviews = n_views;
+    c.h = voxel;
+    for (int k = 0; k < 3; ++k) c.origin[k] = origin[k];
+    c.views.assign(views, views + (size_t)n_views * 12);
+    c.has_geom = true;
+    Level *L = nullptr;
+    int r = get_level(c, 0, &L);
+    if (r != MGCT_OK) c.has_geom = false;
+    return r;
+}
+
+int mgct_project(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype, hipStream_t s) {
+    if (!ctx || !vol || !proj || !vol_dtype_ok(vol_dtype) || !stack_dtype_ok(proj_dtype)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    return do_project(c, *L, level, vol, vol_dtype, proj, proj_dtype, 0, 1, L->nviews, s);
+}
+
+int mgct_backproject(void *ctx, int level, const void *proj, int proj_dtype, void *vol, int vol_dtype,
+                     hipStream_t s) {
+    if (!ctx || !vol || !proj || !vol_dtype_ok(vol_dtype) || !stack_dtype_ok(proj_dtype)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    return do_backproject(c, *L, level, proj, proj_dtype, vol, vol_dtype, 0, 1, L->nviews, s);
+}
+
+int mgct_precondition(void *ctx, int level, const float *in, float *out, const mgct_filter *f, hipStream_t s) {
+    if (!ctx || !in || !out) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    return do_precondition(c, *L, level, in, out, f, s);
+}
+
+int mgct_estimate_step(void *ctx, int level, const mgct_filter *f, int iters, uint64_t seed, double *alpha,
+                       hipStream_t s) {
+    if (!ctx || !alpha || iters < 1) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    return do_estimate(c, *L, level, f, iters, seed, alpha, s);
+}
+
+int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_dtype, double alpha,
+                        const mgct_filter *f, double *resid_norm, hipStream_t s) {
+    if (!ctx || !vol || !b || !stack_dtype_ok(b_dtype) || !isfinite(alpha)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    MGCHK(check_filter(f, *L));
+    WS(d, double, "lw_norm2", 8, false);
+    MGCHK(do_landweber(c, *L, level, vol, b, b_dtype, alpha, f, d, s));
+    if (resid_norm) {
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, d, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *resid_norm = sqrt(v);
+    }
+    return MGCT_OK;
+}
+
+int mgct_restrict_volume(void *ctx, int level, const float *fine, float *coarse, hipStream_t s) {
+    if (!ctx || !fine || !coarse) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L, *Lc;
+    MGCHK(get_level(c, level, &L));
+    MGCHK(get_level(c, level + 1, &Lc));
+    HIPCHK(launch_restrict_volume(fine, coarse, L->nx, L->ny, L->nz, s));
+    return MGCT_OK;
+}
+
+int mgct_restrict_stack(void *ctx, int level, const float *fine, float *coarse, hipStream_t s) {
+    if (!ctx || !fine || !coarse) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L, *Lc;
+    MGCHK(get_level(c, level, &L));
+    MGCHK(get_level(c, level + 1, &Lc));
+    HIPCHK(launch_restrict_stack(fine, coarse, L->nviews, L->nv, L->nu, s));
+    return MGCT_OK;
+}
+
+int mgct_prolong_add(void *ctx, int level, const float *coarse_new, const float *coarse_old, float *fine,
+                     hipStream_t s) {
+    if (!ctx || !coarse_new || !coarse_old || !fine) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L, *Lc;
+    MGCHK(get_level(c, level, &L));
+    MGCHK(get_level(c, level + 1, &Lc));
+    HIPCHK(launch_prolong_add(coarse_new, coarse_old, fine, L->nx, L->ny, L->nz, s));
+    return MGCT_OK;
+}
+
+int mgct_soft_threshold(void *ctx, int level, float *vol, double lambda, hipStream_t s) {
+    if (!ctx || !vol || !(lambda >= 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    HIPCHK(launch_soft_threshold(vol, L->vox(), (float)lambda, s));
+    return MGCT_OK;
+}
+
+int mgct_bilateral(void *ctx, int level, const float *in, float *out, double sigma_s, double sigma_r,
+                   hipStream_t s) {
+    if (!ctx || !in || !out || in == out || !(sigma_s > 0.0) || !(sigma_r > 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    HIPCHK(launch_bilateral(in, out, L->nx, L->ny, L->nz, (float)sigma_s, (float)sigma_r, s));
+    return MGCT_OK;
+}
+
+int mgct_osemtr(void *ctx, int level, float *vol, const float *b, int subsets, int passes, hipStream_t s) {
+    if (!ctx || !vol || !b || subsets < 1 || passes < 0) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    if (!L->separable) return MGCT_ERR_NOT_IMPLEMENTED;
+    return do_osemtr(c, *L, level, vol, b, subsets, passes, s);
+}
+
+int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, const mgct_mg_params *p,
+                         double *resid_hist, hipStream_t s) {
+    if (!ctx || !vol || !b || !p || !stack_dtype_ok(b_dtype)) return MGCT_ERR_INVALID_ARG;
+    if (p->levels < 1 || p->levels > 8 || p->n_outer < 0) return MGCT_ERR_INVALID_ARG;
+    if (p->levels >= 2 && (p->coarse_subsets < 1 || p->coarse_passes < 0)) return MGCT_ERR_INVALID_ARG;
+    if (p->lambda < 0.0 || (p->bilateral_on && !(p->sigma_s > 0.0 && p->sigma_r > 0.0))) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    const int NL = p->levels;
+    std::vector<Level *> Ls(NL);
+    for (int g = 0; g < NL; ++g) MGCHK(get_level(c, g, &Ls[g]));
+    for (int g = 0; g < NL; ++g)
+        if (!Ls[g]->separable) return MGCT_ERR_NOT_IMPLEMENTED;
+    const int nland = NL == 1 ? 1 : NL - 1;  // grids with a Landweber step
+    for (int g = 0; g < nland; ++g) MGCHK(check_filter(&p->filter, *Ls[g]));
+
+    // step sizes
+    std::vector<double> alpha(nland);
+    for (int g = 0; g < nland; ++g) {
+        if (p->alpha[g] > 0.0) {
+            alpha[g] = p->alpha[g];
+            continue;
+        }
+        std::string key = std::to_string(g) + "|" + filter_key(&p->filter) + "|" + std::to_string(p->power_iters) +
+                          "|" + std::to_string(p->power_seed);
+        auto it = c.alpha_cache.find(key);
+        if (it != c.alpha_cache.end()) {
+            alpha[g] = it->second;
+        } else {
+            if (p->power_iters < 1) return MGCT_ERR_INVALID_ARG;
+            MGCHK(do_estimate(c, *Ls[g], g, &p->filter, p->power_iters, p->power_seed, &alpha[g], s));
+            c.alpha_cache[key] = alpha[g];
+        }
+    }
+
+    // data pyramid (FP32)
+    std::vector<const float *> data(NL);
+    if (b_dtype == MGCT_F32) {
+        data[0] = (const float *)b;
+    } else {
+        WS(b0, float, "mg_b0", Ls[0]->rays() * 4, false);
+        HIPCHK(launch_convert_to_f32(b, b_dtype, b0, Ls[0]->rays(), s));
+        data[0] = b0;
+    }
+    for (int g = 1; g < NL; ++g) {
+        WS(bg, float, lvl("mg_b", g), Ls[g]->rays() * 4, false);
+        HIPCHK(launch_restrict_stack(data[g - 1], bg, Ls[g - 1]->nviews, Ls[g - 1]->nv, Ls[g - 1]->nu, s));
+        data[g] = bg;
+    }
+    std::vector<float *> mu(NL), c0(NL);
+    mu[0] = vol;
+    for (int g = 1; g < NL; ++g) {
+        WS(m, float, lvl("mg_mu", g), Ls[g]->vox() * 4, false);
+        WS(o, float, lvl("mg_c0", g), Ls[g]->vox() * 4, false);
+        mu[g] = m;
+        c0[g] = o;
+    }
+    const int nh = p->n_outer * NL;
+    WS(dh, double, "mg_hist", (size_t)(nh > 0 ? nh : 1) * 8, false);
+
+    const float lam = (float)p->lambda;
+    std::function<int(int, int)> mg = [&](int g, int n) -> int {
+        Level &L = *Ls[g];
+        if (g + 1 < NL) {
+            Level &Lc = *Ls[g + 1];
+            HIPCHK(launch_restrict_volume(mu[g], c0[g + 1], L.nx, L.ny, L.nz, s));
+            HIPCHK(launch_copy(c0[g + 1], mu[g + 1], Lc.vox(), s));
+            if (g + 1 < NL - 1) {
+                MGCHK(mg(g + 1, n));
+            } else {
+                if (resid_hist) MGCHK(do_residual_norm2(c, Lc, g + 1, mu[g + 1], data[g + 1], dh + n * NL + g + 1, s));
+                MGCHK(do_osemtr(c, Lc, g + 1, mu[g + 1], data[g + 1], p->coarse_subsets, p->coarse_passes, s));
+            }
+            HIPCHK(launch_prolong_add(mu[g + 1], c0[g + 1], mu[g], L.nx, L.ny, L.nz, s));
+        }
+        MGCHK(do_landweber(c, L, g, mu[g], data[g], MGCT_F32, alpha[g], &p->filter, dh + n * NL + g, s));
+        if (lam > 0.f) HIPCHK(launch_soft_threshold(mu[g], L.vox(), lam, s));
+        if (p->bilateral_on) {
+            WS(tmp, float, lvl("bf_tmp", g), L.vox() * 4, false);
+            HIPCHK(launch_bilateral(mu[g], tmp, L.nx, L.ny, L.nz, (float)p->sigma_s, (float)p->sigma_r, s));
+            HIPCHK(launch_copy(tmp, mu[g], L.vox(), s));
+        }
+        return MGCT_OK;
+    };
+    for (int n = 0; n < p->n_outer; ++n) MGCHK(mg(0, n));
+    if (resid_hist && nh > 0) {
+        std::vector<double> h(nh);
+        HIPCHK(hipMemcpyAsync(h.data(), dh, nh * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < nh; ++i) resid_hist[i] = sqrt(h[i]);
+    }
+    return MGCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Fourier-space preconditioner: out = IDFT3(DFT3(in) * H(rho)), with the
+// 3-D DFT sized to the grid (circular convolution), for power-of-two edges.
+//
+// Five passes over the volume, each batching whole lines of one axis in LDS
+// (radix-2 Stockham, ping-pong buffers, 4096 complex values per block):
+//   1. along x: real input -> complex work array (forward)
+//   2. along y: forward
+//   3. along z: forward, multiply by H, inverse (same lines, one kernel)
+//   4. along y: inverse
+//   5. along x: inverse -> real output, scaled by 1/(nx ny nz)
+// Lines along y and z are strided in memory; a block takes consecutive x so
+// that global loads and stores stay coalesced.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <vector>
+
+#include "mgct_internal.h"
+
+namespace mgct {
+
+constexpr int kFftElems = 4096;  // complex values per block
+
+bool fft_size_ok(int n) { return n >= 2 && n <= 1024 && (n & (n - 1)) == 0; }
+
+void host_twiddles(int n, std::vector<float2> &tw) {
+    tw.resize(n / 2 > 0 ? n / 2 : 1);
+    for (int k = 0; k < n / 2; ++k) {
+        double ang = -2.0 * M_PI * (double)k / (double)n;
+        tw[k] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-LDS radix-2 Stockham FFT of B lines of length N = 2^logN.  dir = +1
+// forward (exp(-2 pi i ...)), -1 inverse (unscaled).  Returns the buffer
+// holding the result.
+__device__ float2 *fft_lines(float2 *src, float2 *dst, int logN, int B, const float2 *__restrict__ tw, int dir) {
+    const int N = 1 << logN, half = N >> 1;
+    for (int Ns = 1, ls = 0; Ns < N; Ns <<= 1, ++ls) {
+        for (int q = threadIdx.x; q < B * half; q += blockDim.x) {
+            const int l = q >> (logN - 1);
+            const int j = q & (half - 1);
+            const float2 a = src[l * N + j];
+            float2 b = src[l * N + j + half];
+            const int k = j & (Ns - 1);
+            float2 w = tw[k << (logN - 1 - ls)];
+            if (dir < 0) w.y = -w.y;
+            b = cmul(b, w);
+            const int idx = ((j - k) << 1) + k;
+            dst[l * N + idx] = make_float2(a.x + b.x, a.y + b.y);
+            dst[l * N + idx + Ns] = make_float2(a.x - b.x, a.y - b.y);
+        }
+        __syncthreads();
+        float2 *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+struct LineMap {
+    long es;           // element stride
+    long inner_count;  // lines are (outer, inner); base = outer*outer_stride + inner*inner_stride
+    long inner_stride;
+    long outer_stride;
+    __device__ long base(long L) const { return (L / inner_count) * outer_stride + (L % inner_count) * inner_stride; }
+};
+
+struct RadialH {
+    const float *table;
+    int n_table;
+    float rho_max;
+    int nx, ny, nz;
+};
+
+__device__ __forceinline__ float radial_gain(const RadialH &R, int ex, int ey, int ez) {
+    const int kx = ex < R.nx / 2 ? ex : ex - R.nx;
+    const int ky = ey < R.ny / 2 ? ey : ey - R.ny;
+    const int kz = ez < R.nz / 2 ? ez : ez - R.nz;
+    const float fx = (float)kx / R.nx, fy = (float)ky / R.ny, fz = (float)kz / R.nz;
+    const float rho = 2.f * sqrtf(fx * fx + fy * fy + fz * fz);
+    float t = rho / R.rho_max * (float)(R.n_table - 1);
+    if (t >= (float)(R.n_table - 1)) return R.table[R.n_table - 1];
+    const int i0 = (int)t;
+    const float w = t - (float)i0;
+    return fmaf(w, R.table[i0 + 1] - R.table[i0], R.table[i0]);
+}
+
+template <bool CONTIG, bool IN_REAL, bool OUT_REAL, bool MUL_H>
+__global__ __launch_bounds__(256) void k_fft_pass(const float *__restrict__ in_r, const float2 *in_c,
+                                                  float *__restrict__ out_r, float2 *out_c, int logN,
+                                                  int logB, LineMap map, const float2 *__restrict__ tw, int dir,
+                                                  float scale, RadialH R) {
+    extern __shared__ float2 lds[];
+    const int N = 1 << logN, B = 1 << logB, total = B * N;
+    float2 *buf0 = lds, *buf1 = lds + total;
+    const long L0 = (long)blockIdx.x * B;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int l, e;
+        if (CONTIG) { e = q & (N - 1); l = q >> logN; }
+        else        { l = q & (B - 1); e = q >> logB; }
+        const long g = map.base(L0 + l) + (long)e * map.es;
+        buf0[l * N + e] = IN_REAL ? make_float2(in_r[g], 0.f) : in_c[g];
+    }
+    __syncthreads();
+    float2 *res = fft_lines(buf0, buf1, logN, B, tw, dir);
+    if (MUL_H) {
+        // this pass runs along z: line L is (y, x) = (L / nx, L % nx)
+        for (int q = threadIdx.x; q < total; q += blockDim.x) {
+            const int l = q >> logN, e = q & (N - 1);
+            const long L = L0 + l;
+            const int ex = (int)(L % R.nx), ey = (int)(L / R.nx);
+            const float hgain = radial_gain(R, ex, ey, e);
+            res[q] = make_float2(res[q].x * hgain, res[q].y * hgain);
+        }
+        __syncthreads();
+        float2 *other = (res == buf0) ? buf1 : buf0;
+        res = fft_lines(res, other, logN, B, tw, -dir);
+    }
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int l, e;
+        if (CONTIG) { e = q & (N - 1); l = q >> logN; }
+        else        { l = q & (B - 1); e = q >> logB; }
+        const long g = map.base(L0 + l) + (long)e * map.es;
+        const float2 v = res[l * N + e];
+        if (OUT_REAL) out_r[g] = v.x * scale;
+        else out_c[g] = v;
+    }
+}
+
+static int ilog2(long n) {
+    int l = 0;
+    while ((1L << l) < n) ++l;
+    return l;
+}
+
+hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int nx, int ny, int nz, const float *table,
+                                int n_table, float rho_max, const float2 *tw_all, hipStream_t s) {
+    // tw_all holds the twiddles for nx, then ny, then nz (nx/2 + ny/2 + nz/2 entries)
+    const float2 *twx = tw_all, *twy = tw_all + nx / 2, *twz = tw_all + nx / 2 + ny / 2;
+    RadialH R{table, n_table, rho_max, nx, ny, nz};
+    RadialH none{nullptr, 0, 1.f, nx, ny, nz};
+    const long nvox = (long)nx * ny * nz;
+    auto pick_B = [&](int n, long lines) {
+        long B = kFftElems / n;
+        if (B > lines) B = lines;
+        if (B < 1) B = 1;
+        return ilog2(B);
+    };
+    const size_t lds = 2 * (size_t)kFftElems * sizeof(float2);
+    // pass 1: x, real -> complex
+    {
+        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz);
+        LineMap m{1, 1L << 40, nx, 0};
+        const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
+        k_fft_pass<true, true, false, false>
+            <<<grid, 256, lds, s>>>(in, nullptr, nullptr, work, logN, logB, m, twx, +1, 1.f, none);
+    }
+    // pass 2: y forward
+    {
+        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz);
+        LineMap m{nx, nx, 1, (long)nx * ny};
+        const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
+        k_fft_pass<false, false, false, false>
+            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twy, +1, 1.f, none);
+    }
+    // pass 3: z forward, * H, z inverse
+    {
+        const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny);
+        LineMap m{(long)nx * ny, 1L << 40, 1, 0};
+        const unsigned grid = (unsigned)(((long)nx * ny) >> logB);
+        k_fft_pass<false, false, false, true>
+            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twz, +1, 1.f, R);
+    }
+    // pass 4: y inverse
+    {
+        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz);
+        LineMap m{nx, nx, 1, (long)nx * ny};
+        const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
+        k_fft_pass<false, false, false, false>
+            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twy, -1, 1.f, none);
+    }
+    // pass 5: x inverse -> real, scaled
+    {
+        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz);
+        LineMap m{1, 1L << 40, nx, 0};
+        const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
+        k_fft_pass<true, false, true, false>
+            <<<grid, 256, lds, s>>>(nullptr, work, out, nullptr, logN, logB, m, twx, -1, (float)(1.0 / (double)nvox), none);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mgct

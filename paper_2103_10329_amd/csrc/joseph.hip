@@ -1,0 +1,392 @@
+// Joseph cone-beam projector A and its transpose A^T for gfx950.
+//
+// Forward (ray-driven): one lane per detector pixel, lanes of a wavefront
+// are 64 consecutive detector rows of one column.  The volume is first copied
+// into a zero-padded, z-fastest layout vt[x][y][z], so that for the x- and
+// y-major rays of a column (whose z coordinate at a plane grows with the
+// row) the two bilinear taps along z are adjacent and the 64 lanes of a wave
+// touch a few contiguous cache lines per plane.  Sampling positions are
+// affine in the plane index; the per-ray set-up (plane range, slopes, the
+// spacing factor h|D|/|D_m|) is done in FP64, the sampling loop in FP32.
+//
+// Transpose (voxel-driven gather, no atomics): one lane per voxel, lanes of a
+// wavefront are consecutive z of one (x, y) column.  For the geometry in
+// which the detector columns are horizontal and the rows vertical, the
+// detector column hit by a ray through (x, y, .) does not depend on z, so
+// the candidate columns of every view are wave-uniform (scalar loop, scalar
+// loads of the per-column table); each lane then walks only the handful of
+// rows whose sample on the voxel's plane lies within one voxel of it in z.
+// The data are first scaled by each ray's spacing factor and transposed to
+// [view][column][row] so that those row reads are contiguous across lanes.
+#include <hip/hip_runtime.h>
+
+#include "mgct_internal.h"
+
+namespace mgct {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                     // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T> __device__ __forceinline__ float load_f(const T *p, long i);
+template <> __device__ __forceinline__ float load_f<float>(const float *p, long i) { return p[i]; }
+template <> __device__ __forceinline__ float load_f<uint16_t>(const uint16_t *p, long i) { return bf16_to_f32(p[i]); }
+template <> __device__ __forceinline__ float load_f<_Float16>(const _Float16 *p, long i) { return (float)p[i]; }
+
+template <typename T> __device__ __forceinline__ void store_f(T *p, long i, float x);
+template <> __device__ __forceinline__ void store_f<float>(float *p, long i, float x) { p[i] = x; }
+template <> __device__ __forceinline__ void store_f<uint16_t>(uint16_t *p, long i, float x) { p[i] = f32_to_bf16(x); }
+template <> __device__ __forceinline__ void store_f<_Float16>(_Float16 *p, long i, float x) { p[i] = (_Float16)x; }
+
+// ---------------------------------------------------------------- set-up --
+
+// Spacing factor h |D| / |D_m| of ray (a, b) of view V and its direction D
+// (voxel-index units).  Shared by the projector and the data pre-scaling of
+// the transpose so that both use bit-identical factors.
+__device__ __forceinline__ double ray_setup(const ViewIdx &V, int nu, int nv, int a, int b, double D[3]) {
+    double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) D[k] = (V.d[k] + ca * V.u[k] + cb * V.v[k]) - V.s[k];
+    return sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+}
+
+// Restrict [lo, hi] to the planes l with A + l*B inside [bmin, bmax].
+__device__ __forceinline__ void clip_range(double &lo, double &hi, double A, double B, double bmin, double bmax) {
+    if (B > 0.0) {
+        lo = fmax(lo, ceil((bmin - A) / B));
+        hi = fmin(hi, floor((bmax - A) / B));
+    } else if (B < 0.0) {
+        lo = fmax(lo, ceil((bmax - A) / B));
+        hi = fmin(hi, floor((bmin - A) / B));
+    } else if (A < bmin || A > bmax) {
+        hi = lo - 1.0;
+    }
+}
+
+// ------------------------------------------------------ volume transpose --
+
+// vol[z][y][x] -> vt[x+P][y+P][z+P] (P = kVolPad); the padding stays zero.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_transpose_volume(const TI *__restrict__ vol, TO *__restrict__ vt, int nx,
+                                                          int ny, int nz) {
+    __shared__ float tile[64][65];
+    const int x0 = blockIdx.x * 64, z0 = blockIdx.y * 64, y = blockIdx.z;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int zl = (t >> 6) + 4 * r, xl = t & 63;
+        int z = z0 + zl, x = x0 + xl;
+        float v = 0.f;
+        if (z < nz && x < nx) v = load_f(vol, ((long)z * ny + y) * nx + x);
+        tile[zl][xl] = v;
+    }
+    __syncthreads();
+    const long PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int xl = (t >> 6) + 4 * r, zl = t & 63;
+        int z = z0 + zl, x = x0 + xl;
+        if (z < nz && x < nx) store_f(vt, ((long)(x + kVolPad) * PY + (y + kVolPad)) * PZ + (z + kVolPad), tile[zl][xl]);
+    }
+}
+
+hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int vt_dtype, const Level &L,
+                                   hipStream_t s) {
+    dim3 grid((L.nx + 63) / 64, (L.nz + 63) / 64, L.ny);
+    if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_F32)
+        k_transpose_volume<float, float><<<grid, 256, 0, s>>>((const float *)vol, (float *)vt, L.nx, L.ny, L.nz);
+    else if (vol_dtype == MGCT_BF16 && vt_dtype == MGCT_BF16)
+        k_transpose_volume<uint16_t, uint16_t>
+            <<<grid, 256, 0, s>>>((const uint16_t *)vol, (uint16_t *)vt, L.nx, L.ny, L.nz);
+    else if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_BF16)
+        k_transpose_volume<float, uint16_t><<<grid, 256, 0, s>>>((const float *)vol, (uint16_t *)vt, L.nx, L.ny, L.nz);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- projector --
+
+template <typename VT, typename PT>
+__global__ __launch_bounds__(256) void k_project(const VT *__restrict__ vt, PT *__restrict__ proj,
+                                                 const ViewIdx *__restrict__ views, const uint8_t *__restrict__ axis,
+                                                 long axis_view_stride, long axis_row_stride, int nx, int ny, int nz,
+                                                 int nu, int nv, double h, int view0, int view_step) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = blockIdx.x * 4 + w;
+    const int b = blockIdx.y * 64 + lane;
+    const int vl = blockIdx.z;
+    const int v = view0 + vl * view_step;
+    if (a >= nu || b >= nv) return;  // no barrier below
+
+    const ViewIdx &V = views[v];
+    double D[3];
+    const double len = ray_setup(V, nu, nv, a, b, D);
+    const int m = axis[v * axis_view_stride + b * axis_row_stride + a];  // 0: x-major, 1: y-major
+    const int ia = (m == 0) ? 1 : 0;
+    const double Dm = D[m], Da = D[ia], Dz = D[2];
+    const double sm = V.s[m], sa = V.s[ia], sz = V.s[2];
+    // sample on plane l: (in-plane a, z) = (Aa + l Ba, Az + l Bz)
+    const double Ba = Da / Dm, Bz = Dz / Dm;
+    const double Aa = sa - sm * Ba, Az = sz - sm * Bz;
+    const int n_m = (m == 0) ? nx : ny, n_a = (m == 0) ? ny : nx;
+    // planes between source (t = 0) and pixel (t = 1)
+    double lo = fmax(0.0, ceil(fmin(sm, sm + Dm)));
+    double hi = fmin((double)(n_m - 1), floor(fmax(sm, sm + Dm)));
+    // samples whose bilinear footprint can touch the grid, with half a voxel
+    // of margin inside the 2-voxel zero padding
+    clip_range(lo, hi, Aa, Ba, -1.5, n_a + 0.5);
+    clip_range(lo, hi, Az, Bz, -1.5, nz + 0.5);
+    // a degenerate ray (pixel at the source) contributes nothing
+    if (!(fabs(Dm) > 0.0) || !isfinite(Aa) || !isfinite(Az) || !isfinite(Ba) || !isfinite(Bz)) hi = lo - 1.0;
+    const float scale = (float)(h * len / fabs(Dm));
+
+    float acc = 0.f;
+    if (lo <= hi) {
+        const int l0 = (int)lo, l1 = (int)hi;
+        const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+        const int Sm = (m == 0) ? PY * PZ : PZ;
+        const int Sa = (m == 0) ? PZ : PY * PZ;
+        const float Baf = (float)Ba, Bzf = (float)Bz;
+        const float Aaf = (float)(Aa + kVolPad), Azf = (float)(Az + kVolPad);
+        int off_m = (l0 + kVolPad) * Sm;
+        for (int l = l0; l <= l1; ++l, off_m += Sm) {
+            const float lf = (float)l;
+            const float fa = fmaf(lf, Baf, Aaf), fz = fmaf(lf, Bzf, Azf);
+            const float ga = floorf(fa), gz = floorf(fz);
+            const float wa = fa - ga, wz = fz - gz;
+            const int off = off_m + (int)ga * Sa + (int)gz;
+            const float p00 = load_f(vt, off), p01 = load_f(vt, off + 1);
+            const float p10 = load_f(vt, off + Sa), p11 = load_f(vt, off + Sa + 1);
+            const float q0 = fmaf(wz, p01 - p00, p00), q1 = fmaf(wz, p11 - p10, p10);
+            acc += fmaf(wa, q1 - q0, q0);
+        }
+    }
+    store_f(proj, ((long)vl * nv + b) * nu + a, acc * scale);
+}
+
+hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
+                          int view_step, int nviews_sub, hipStream_t s) {
+    dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
+    const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
+    const long ars = L.axis_row_stride;
+#define MGCT_PROJ(VT, PT)                                                                                       \
+    k_project<VT, PT><<<grid, 256, 0, s>>>((const VT *)vt, (PT *)proj, L.d_views, L.d_axis, avs, ars, L.nx, L.ny, \
+                                           L.nz, L.nu, L.nv, L.h, view0, view_step)
+    if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F32) MGCT_PROJ(float, float);
+    else if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F16) MGCT_PROJ(float, _Float16);
+    else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F32) MGCT_PROJ(uint16_t, float);
+    else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F16) MGCT_PROJ(uint16_t, _Float16);
+    else return hipErrorInvalidValue;
+#undef MGCT_PROJ
+    return hipGetLastError();
+}
+
+// ------------------------------------------- data pre-scale and transpose --
+
+// pt[vl][a][b] = proj[vl][b][a] * h|D|/|D_m| of ray (view0 + vl*step, a, b).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_scale_transpose(const PT *__restrict__ proj, float *__restrict__ pt,
+                                                         const ViewIdx *__restrict__ views,
+                                                         const uint8_t *__restrict__ axis, long axis_view_stride,
+                                                         long axis_row_stride, int nu, int nv, double h, int view0,
+                                                         int view_step) {
+    __shared__ float tile[64][65];
+    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64, vl = blockIdx.z;
+    const int v = view0 + vl * view_step;
+    const ViewIdx &V = views[v];
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+        int bl = (t >> 6) + 4 * r, al = t & 63;
+        int b = b0 + bl, a = a0 + al;
+        float val = 0.f;
+        if (a < nu && b < nv) {
+            double D[3];
+            double len = ray_setup(V, nu, nv, a, b, D);
+            int m = axis[v * axis_view_stride + b * axis_row_stride + a];
+            float scale = (float)(h * len / fabs(D[m]));
+            val = load_f(proj, ((long)vl * nv + b) * nu + a) * scale;
+        }
+        tile[bl][al] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int al = (t >> 6) + 4 * r, bl = t & 63;
+        int b = b0 + bl, a = a0 + al;
+        if (a < nu && b < nv) pt[((long)vl * nu + a) * nv + b] = tile[bl][al];
+    }
+}
+
+hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, float *pt, const Level &L, int view0,
+                                        int view_step, int nviews_sub, hipStream_t s) {
+    dim3 grid((L.nu + 63) / 64, (L.nv + 63) / 64, nviews_sub);
+    const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
+    if (proj_dtype == MGCT_F32)
+        k_scale_transpose<float><<<grid, 256, 0, s>>>((const float *)proj, pt, L.d_views, L.d_axis, avs,
+                                                      L.axis_row_stride, L.nu, L.nv, L.h, view0, view_step);
+    else if (proj_dtype == MGCT_F16)
+        k_scale_transpose<_Float16><<<grid, 256, 0, s>>>((const _Float16 *)proj, pt, L.d_views, L.d_axis, avs,
+                                                         L.axis_row_stride, L.nu, L.nv, L.h, view0, view_step);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- back-projector --
+
+__device__ __forceinline__ float column_coord(const SepView &S, float px, float py) {
+    return (S.an0 + S.an1 * px + S.an2 * py) / (S.ad0 + S.ad1 * px + S.ad2 * py);
+}
+
+// Sum over the rows of one column whose sample (zc + tz*b) lies within one
+// voxel of k, of hat(zc + tz*b - k) * data[b].
+template <int NP>
+__device__ __forceinline__ void column_rows(const float *const *col, float zc, float tz, float rtz, int nb, int nv,
+                                            float k, float out[NP]) {
+    const float bc = (k - zc) * rtz;
+    const float hw = fabsf(rtz);
+    int bs = (int)ceilf(bc - hw);
+    bs = max(0, min(bs, nv - nb));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) out[p] = 0.f;
+    for (int t = 0; t < nb; ++t) {
+        const int b = bs + t;
+        const float fz = fmaf(tz, (float)b, zc);
+        const float wgt = fmaxf(0.f, 1.f - fabsf(fz - k));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) out[p] = fmaf(wgt, col[p][b], out[p]);
+    }
+}
+
+template <int KZ, int NP, typename OT>
+__global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict__ pt0, const float *__restrict__ pt1,
+                                                         OT *__restrict__ vol0, OT *__restrict__ vol1,
+                                                         const SepView *__restrict__ sep,
+                                                         const float4 *__restrict__ cols,
+                                                         const uint8_t *__restrict__ axis, int nx, int ny, int nz,
+                                                         int nu, int nv, int nviews_sub, int view0, int view_step) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
+    const int zc_id = wave % zchunks;
+    const int ij = wave / zchunks;
+    const int i = ij % nx, j = ij / nx;
+    if (j >= ny) return;  // whole wave; no barrier below
+    const float fi = (float)i, fj = (float)j;
+    float kf[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) kf[q] = (float)(zc_id * 64 * KZ + q * 64 + lane);
+    float acc[NP][KZ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) acc[p][q] = 0.f;
+
+    for (int vl = 0; vl < nviews_sub; ++vl) {
+        const int v = view0 + vl * view_step;
+        const SepView S = sep[v];
+        const float4 *cv = cols + (long)v * nu;
+        const uint8_t *av = axis + (long)v * nu;
+        const float *base0 = pt0 + (long)vl * nu * nv;
+        const float *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            // part 0: x-major rays sampled on plane x = i, in-plane offset in y;
+            // part 1: y-major rays sampled on plane y = j, in-plane offset in x.
+            float c1, c2;
+            if (part == 0) {
+                c1 = column_coord(S, fi, fj - 1.f);
+                c2 = column_coord(S, fi, fj + 1.f);
+            } else {
+                c1 = column_coord(S, fi - 1.f, fj);
+                c2 = column_coord(S, fi + 1.f, fj);
+            }
+            int alo = (int)floorf(fminf(c1, c2) - 0.01f);
+            int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
+            alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
+            ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+            for (int a = alo; a <= ahi; ++a) {
+                if (av[a] != part) continue;
+                const float4 C = cv[a];
+                float tau, wp;
+                if (part == 0) {
+                    tau = (fi - S.sx) * C.z;
+                    wp = 1.f - fabsf(fmaf(tau, C.y, S.sy) - fj);
+                } else {
+                    tau = (fj - S.sy) * C.w;
+                    wp = 1.f - fabsf(fmaf(tau, C.x, S.sx) - fi);
+                }
+                if (!(wp > 0.f) || tau < 0.f || tau > 1.f) continue;
+                const float tz = tau * S.vz;
+                if (!(fabsf(tz) > 1e-20f)) continue;
+                const float zc = fmaf(tau, S.dz0, S.sz);
+                const float rtz = 1.f / tz;
+                // rows whose sample lies within one voxel of k: at most floor(2/|tz|) + 1
+                const int nb = (int)fminf(2.f * fabsf(rtz) + 1.f, (float)nv);
+                const float *col[NP];
+                col[0] = base0 + (long)a * nv;
+                if (NP > 1) col[NP - 1] = base1 + (long)a * nv;
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) {
+                    float r[NP];
+                    column_rows<NP>(col, zc, tz, rtz, nb, nv, kf[q], r);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) acc[p][q] = fmaf(wp, r[p], acc[p][q]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        const int k = zc_id * 64 * KZ + q * 64 + lane;
+        if (k < nz) {
+            const long o = ((long)k * ny + j) * nx + i;
+            store_f(vol0, o, acc[0][q]);
+            if (NP > 1) store_f(vol1, o, acc[NP - 1][q]);
+        }
+    }
+}
+
+template <int NP, typename OT>
+static hipError_t launch_bp(const float *pt0, const float *pt1, OT *vol0, OT *vol1, const Level &L, int view0,
+                            int view_step, int nviews_sub, hipStream_t s) {
+    if (!L.separable) return hipErrorNotSupported;
+    int KZ = 1;
+    while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
+    const long zchunks = (L.nz + 64 * KZ - 1) / (64 * KZ);
+    const long waves = zchunks * L.nx * L.ny;
+    dim3 grid((unsigned)((waves + 3) / 4));
+#define MGCT_BP(K)                                                                                                \
+    k_backproject_sep<K, NP, OT><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, L.d_sep, L.d_cols, L.d_axis, L.nx, L.ny, \
+                                                      L.nz, L.nu, L.nv, nviews_sub, view0, view_step)
+    switch (KZ) {
+        case 1: MGCT_BP(1); break;
+        case 2: MGCT_BP(2); break;
+        case 4: MGCT_BP(4); break;
+        default: MGCT_BP(8); break;
+    }
+#undef MGCT_BP
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(const float *pt, void *vol, int vol_dtype, const Level &L, int view0, int view_step,
+                              int nviews_sub, hipStream_t s) {
+    if (vol_dtype == MGCT_F32)
+        return launch_bp<1, float>(pt, nullptr, (float *)vol, nullptr, L, view0, view_step, nviews_sub, s);
+    if (vol_dtype == MGCT_BF16)
+        return launch_bp<1, uint16_t>(pt, nullptr, (uint16_t *)vol, nullptr, L, view0, view_step, nviews_sub, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, const Level &L,
+                               int view0, int view_step, int nviews_sub, hipStream_t s) {
+    return launch_bp<2, float>(pt0, pt1, vol0, vol1, L, view0, view_step, nviews_sub, s);
+}
+
+}  // namespace mgct

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host driver and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mgct.h"
+
+namespace mgct {
+
+// Per-view geometry in voxel-index coordinates of one grid level: a point P
+// (physical) maps to (P - origin)/h + (n-1)/2, so voxel (i,j,k) sits at
+// integer coordinates (i,j,k).  Vectors scale by 1/h.
+struct ViewIdx {
+    double s[3], d[3], u[3], v[3];
+};
+
+// Per-view constants of the separable back-projector (geometry with the
+// detector columns horizontal and the rows along z): the ray of pixel (a,b)
+// has direction (Dx(a), Dy(a), dz0 + b*vz); the detector column hit by the
+// ray through (px, py, .) is (an0 + an1 px + an2 py)/(ad0 + ad1 px + ad2 py).
+struct SepView {
+    float sx, sy, sz, dz0;
+    float vz, an0, an1, an2;
+    float ad0, ad1, ad2, pad;
+};
+
+// Padding (voxels) around the transposed volume copy read by the projector.
+constexpr int kVolPad = 2;
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0, nu = 0, nv = 0, nviews = 0;
+    double h = 0.0;
+    bool separable = false;
+    // device tables
+    ViewIdx *d_views = nullptr;      // [view]
+    SepView *d_sep = nullptr;        // [view]       (separable only)
+    float4 *d_cols = nullptr;        // [view][nu]: Dx, Dy, 1/Dx, 1/Dy (separable only)
+    uint8_t *d_axis = nullptr;       // [view][nu] (separable) or [view][nv][nu]: 0 = x, 1 = y
+    long axis_row_stride = 0;        // 0 (separable) or nu
+    size_t vox() const { return (size_t)nx * ny * nz; }
+    size_t rays() const { return (size_t)nviews * nu * nv; }
+    size_t padded_vox() const {
+        return (size_t)(nx + 2 * kVolPad) * (ny + 2 * kVolPad) * (nz + 2 * kVolPad);
+    }
+};
+
+struct Ctx {
+    int device = 0;
+    bool has_geom = false;
+    // finest-grid geometry as given
+    int nx = 0, ny = 0, nz = 0, nu = 0, nv = 0, nviews = 0;
+    double h = 0.0, origin[3] = {0, 0, 0};
+    std::vector<double> views;  // n_views x 12
+    std::vector<Level> levels;  // built on demand
+    // named device workspaces, grown on demand and kept
+    std::map<std::string, std::pair<void *, size_t>> ws;
+    // cached step sizes keyed by a description of (level, filter, iters, seed)
+    std::map<std::string, double> alpha_cache;
+};
+
+// ----- host helpers (api.cpp / geometry.cpp)
+int build_level(Ctx &c, int g, Level &out);  // fills host+device tables
+void free_level(Level &L);
+int check_geometry(int nx, int ny, int nz, double h, const double *origin, int nu, int nv, int nviews,
+                   const double *views);
+
+// ----- kernel launchers (return hipError_t as int)
+// Joseph projector / back-projector (joseph.hip)
+hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int vt_dtype, const Level &L,
+                                   hipStream_t s);
+hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L,
+                          int view0, int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, float *pt, const Level &L,
+                                        int view0, int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_backproject(const float *pt, void *vol, int vol_dtype, const Level &L, int view0,
+                              int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, const Level &L,
+                               int view0, int view_step, int nviews_sub, hipStream_t s);
+
+// Volume / stack operations (volume_ops.hip)
+hipError_t launch_fill(float *x, size_t n, float value, hipStream_t s);
+hipError_t launch_copy(const float *x, float *y, size_t n, hipStream_t s);
+hipError_t launch_convert_to_f32(const void *x, int dtype, float *y, size_t n, hipStream_t s);
+hipError_t launch_residual(const void *b, int b_dtype, const float *ax, float *r, size_t n, double *partials,
+                           int nblocks, hipStream_t s);
+hipError_t launch_sumsq(const float *x, size_t n, double *partials, int nblocks, hipStream_t s);
+hipError_t launch_finish_sum(const double *partials, int n, double *out, hipStream_t s);
+hipError_t launch_axpy(float *y, const float *x, double alpha, size_t n, hipStream_t s);
+hipError_t launch_scale_by_inv_sqrt(float *x, size_t n, const double *sumsq, double *lambda_out,
+                                    hipStream_t s);
+hipError_t launch_soft_threshold(float *x, size_t n, float lambda, hipStream_t s);
+hipError_t launch_stencil27(const float *in, float *out, int nx, int ny, int nz, const float *taps,
+                            hipStream_t s);
+hipError_t launch_bilateral(const float *in, float *out, int nx, int ny, int nz, float sigma_s, float sigma_r,
+                            hipStream_t s);
+hipError_t launch_restrict_volume(const float *fine, float *coarse, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_restrict_stack(const float *fine, float *coarse, int nviews, int nv, int nu, hipStream_t s);
+hipError_t launch_prolong_add(const float *cnew, const float *cold, float *fine, int nx, int ny, int nz,
+                              hipStream_t s);
+hipError_t launch_emtr_terms(const float *l, const float *b, const float *pi, float *num_src, float *den_src,
+                             const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_emtr_update(float *vol, const float *num, const float *den, size_t n, unsigned *maxbits,
+                              hipStream_t s);
+hipError_t launch_max_reset(unsigned *maxbits, hipStream_t s);
+hipError_t launch_max_reduce(const float *x, size_t n, unsigned *maxbits, hipStream_t s);
+hipError_t launch_splitmix_uniform(float *x, size_t n, uint64_t seed, hipStream_t s);
+
+// FFT preconditioner (fft.hip)
+bool fft_size_ok(int n);
+hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int nx, int ny, int nz,
+                                const float *table, int n_table, float rho_max, const float2 *tw,
+                                hipStream_t s);
+void host_twiddles(int n, std::vector<float2> &tw);  // exp(-2 pi i k / n), k < n/2
+
+}  // namespace mgct

@@ -1,0 +1,115 @@
+"""GPU parity of the projector A and its transpose against the FP64 oracle.
+
+Bar: relative L2 error <= 1e-5 for FP32 arithmetic (full outputs at sizes
+the oracle finishes in seconds; sampled rays / voxels at the full workload
+sizes), adjoint identity <= 1e-6, bit-identical repeat runs.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import context, rel_l2, say, to_dev, to_host, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _ragged_geom():
+    # odd, unequal sizes: several tiles plus ragged tails on every axis
+    views = synth.trajectory(37, 8, 1.6)
+    views[:, 3:6] *= 0.9  # detector 190 from the source
+    return oracle.Geom(37, 29, 70, 0.45, (0.3, -0.2, 0.1), 53, 71, views)
+
+
+CASES = {
+    "c0": lambda: workload("c0"),
+    "ragged": _ragged_geom,
+    "c1_level2": lambda: workload("c1").level(2),
+    "c1_level1": lambda: workload("c1").level(1),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_project_matches_oracle(case):
+    g = CASES[case]()
+    say("project parity", case, g.vol_shape, g.stack_shape)
+    rng = np.random.Generator(np.random.PCG64(7))
+    x = rng.random(g.vol_shape)
+    ref = oracle.project(g, x)
+    ctx = context(g)
+    out = to_host(ctx.project(to_dev(x)))
+    err = rel_l2(out, ref)
+    say("  rel L2", err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_backproject_matches_oracle(case):
+    g = CASES[case]()
+    say("backproject parity", case, g.vol_shape, g.stack_shape)
+    rng = np.random.Generator(np.random.PCG64(8))
+    y = rng.random(g.stack_shape)
+    ref = oracle.backproject(g, y)
+    ctx = context(g)
+    out = to_host(ctx.backproject(to_dev(y)))
+    err = rel_l2(out, ref)
+    say("  rel L2", err)
+    assert err <= TOL
+
+
+def test_phantom_projection_c0_close_to_analytic():
+    d = synth.make_dataset("c0")
+    g = workload("c0")
+    ctx = context(g)
+    p = to_host(ctx.project(to_dev(d["mu"])))
+    ref = oracle.project(g, d["mu"])
+    assert rel_l2(p, ref) <= TOL
+    # discretisation error against the exact chords of the phantom (not parity)
+    assert rel_l2(p, d["b_true"]) < 0.05
+
+
+def test_full_size_c1_sampled_rays_and_voxels():
+    g = workload("c1")
+    say("c1 sampled parity", g.vol_shape, g.stack_shape)
+    rng = np.random.Generator(np.random.PCG64(11))
+    x = rng.random(g.vol_shape, dtype=np.float32).astype(np.float64)
+    y = rng.random(g.stack_shape, dtype=np.float32).astype(np.float64)
+    ctx = context(g)
+    Ax = to_host(ctx.project(to_dev(x)))
+    Aty = to_host(ctx.backproject(to_dev(y)))
+    rays = np.stack([rng.integers(0, g.n_views, 3000), rng.integers(0, g.nu, 3000), rng.integers(0, g.nv, 3000)], 1)
+    ref_r = oracle.project_rays(g, x, rays)
+    got_r = Ax[rays[:, 0], rays[:, 2], rays[:, 1]]
+    e1 = rel_l2(got_r, ref_r)
+    vox = np.stack([rng.integers(0, g.nx, 200), rng.integers(0, g.ny, 200), rng.integers(0, g.nz, 200)], 1)
+    ref_v = oracle.backproject_voxels(g, y, vox)
+    got_v = Aty[vox[:, 2], vox[:, 1], vox[:, 0]]
+    e2 = rel_l2(got_v, ref_v)
+    # adjoint identity of the GPU pair, in FP64 on the host
+    dot1 = float(np.vdot(Ax, y))
+    dot2 = float(np.vdot(x, Aty))
+    e3 = abs(dot1 - dot2) / (np.linalg.norm(Ax) * np.linalg.norm(y))
+    say("  rays rel L2", e1, " voxels rel L2", e2, " adjoint", e3)
+    assert e1 <= TOL and e2 <= TOL and e3 <= 1e-6
+
+
+def test_backprojection_is_deterministic():
+    g = workload("c1").level(1)
+    rng = np.random.Generator(np.random.PCG64(3))
+    ctx = context(g)
+    y = to_dev(rng.random(g.stack_shape))
+    a = to_host(ctx.backproject(y))
+    b = to_host(ctx.backproject(y))
+    assert np.array_equal(a, b)
+
+
+def test_zero_volume_and_empty_rays():
+    g = workload("c0")
+    ctx = context(g)
+    out = to_host(ctx.project(to_dev(np.zeros(g.vol_shape))))
+    assert np.all(out == 0)
+    out = to_host(ctx.backproject(to_dev(np.zeros(g.stack_shape))))
+    assert np.all(out == 0)
