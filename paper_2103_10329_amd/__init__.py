@@ -93,6 +93,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libmgct.so is not built (%s); run python -m paper_2103_10329_amd.build" % path)
+    # torch carries its own HIP runtime (same soname as the system one); load
+    # it first so that the library binds to that copy and the process holds a
+    # single runtime shared by torch's allocator/streams and our kernels.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -56,8 +56,7 @@ void *workspace(Ctx &c, const std::string &name, size_t bytes, bool zero = false
 
 int get_level(Ctx &c, int g, Level **out) {
     if (!c.has_geom) return MGCT_ERR_NO_GEOMETRY;
-    if (g < 0 || g > 10) return MGCT_ERR_INVALID_ARG;
-    if ((int)c.levels.size() <= g) c.levels.resize(g + 1);
+    if (g < 0 || g >= Ctx::kMaxLevels) return MGCT_ERR_INVALID_ARG;
     Level &L = c.levels[g];
     if (L.nx == 0) {
         int r = build_level(c, g, L);
@@ -319,8 +318,10 @@ int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const dou
     HIPCHK(hipSetDevice(c.device));
     MGCHK(check_geometry(nx, ny, nz, voxel, origin, nu, nv, n_views, views));
     HIPCHK(hipDeviceSynchronize());
-    for (auto &L : c.levels) free_level(L);
-    c.levels.clear();
+    for (auto &L : c.levels) {
+        free_level(L);
+        L = Level();
+    }
     c.alpha_cache.clear();
     c.nx = nx; c.ny = ny; c.nz = nz; c.nu = nu; c.nv = nv; c.nviews = n_views;
     c.h = voxel;

@@ -56,7 +56,10 @@ struct Ctx {
     int nx = 0, ny = 0, nz = 0, nu = 0, nv = 0, nviews = 0;
     double h = 0.0, origin[3] = {0, 0, 0};
     std::vector<double> views;  // n_views x 12
-    std::vector<Level> levels;  // built on demand
+    // grid levels, built on demand; a fixed array so that pointers to a
+    // level stay valid while other levels are built
+    static constexpr int kMaxLevels = 11;
+    Level levels[kMaxLevels];
     // named device workspaces, grown on demand and kept
     std::map<std::string, std::pair<void *, size_t>> ws;
     // cached step sizes keyed by a description of (level, filter, iters, seed)

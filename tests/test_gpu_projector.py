@@ -67,8 +67,9 @@ def test_phantom_projection_c0_close_to_analytic():
     p = to_host(ctx.project(to_dev(d["mu"])))
     ref = oracle.project(g, d["mu"])
     assert rel_l2(p, ref) <= TOL
-    # discretisation error against the exact chords of the phantom (not parity)
-    assert rel_l2(p, d["b_true"]) < 0.05
+    # discretisation error against the exact chords of the phantom (not
+    # parity; the smallest ellipsoids are 2 voxels across)
+    assert rel_l2(p, d["b_true"]) < 0.08
 
 
 def test_full_size_c1_sampled_rays_and_voxels():
