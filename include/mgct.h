@@ -204,6 +204,26 @@ int mgct_osemtr(void *ctx, int level, float *vol, const float *b, int subsets, i
 int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, const mgct_mg_params *p,
                          double *resid_hist, hipStream_t stream);
 
+/*
+ * Kernel timing (instrumentation).  While enabled, every launch of the
+ * kernels below is bracketed by HIP events recorded on the launch's stream.
+ * mgct_kernel_timing(ctx, 1) enables and clears the records, (ctx, 0)
+ * disables (records are kept).  mgct_kernel_time() synchronises on the
+ * recorded events and returns the summed duration (ms, host) and the number
+ * of launches of kernel `op` on grid `level` (level -1: all grids).
+ */
+typedef enum {
+    MGCT_OP_PROJECT = 0,          /* ray-driven projector kernel */
+    MGCT_OP_BACKPROJECT = 1,      /* voxel-driven transpose kernel */
+    MGCT_OP_PRECONDITION = 2,     /* stencil or Fourier filter (all passes) */
+    MGCT_OP_VOLUME_TRANSPOSE = 3, /* volume copy into the projector's layout */
+    MGCT_OP_DATA_PRESCALE = 4,    /* data scaling/transposition before A^T */
+    MGCT_OP_COUNT = 5
+} mgct_op;
+
+int mgct_kernel_timing(void *ctx, int enable);
+int mgct_kernel_time(void *ctx, int op, int level, double *total_ms, int *launches);
+
 #ifdef __cplusplus
 }
 #endif

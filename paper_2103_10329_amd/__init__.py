@@ -81,7 +81,12 @@ SIGNATURES = {
     "mgct_bilateral": (_ci, [_vp, _ci, _vp, _vp, _cd, _cd, _vp]),
     "mgct_osemtr": (_ci, [_vp, _ci, _vp, _vp, _ci, _ci, _vp]),
     "mgct_multigrid_solve": (_ci, [_vp, _vp, _vp, _ci, ctypes.POINTER(mgct_mg_params), _dp, _vp]),
+    "mgct_kernel_timing": (_ci, [_vp, _ci]),
+    "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
 }
+
+MGCT_OP_PROJECT, MGCT_OP_BACKPROJECT, MGCT_OP_PRECONDITION = 0, 1, 2
+MGCT_OP_VOLUME_TRANSPOSE, MGCT_OP_DATA_PRESCALE = 3, 4
 
 _lib = None
 
@@ -288,6 +293,16 @@ class Context:
     def osemtr(self, vol, b, subsets=8, passes=2, level: int = 0):
         check(mgct_osemtr(self.handle, level, _ptr(vol), _ptr(b), subsets, passes, _stream()),  # noqa: F821
               "mgct_osemtr")
+
+    def kernel_timing(self, enable: bool):
+        check(mgct_kernel_timing(self.handle, 1 if enable else 0), "mgct_kernel_timing")  # noqa: F821
+
+    def kernel_time(self, op: int, level: int = -1):
+        """(total milliseconds, number of launches) of kernel `op` since timing was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        check(mgct_kernel_time(self.handle, op, level, ctypes.byref(ms), ctypes.byref(n)), "mgct_kernel_time")  # noqa: F821
+        return ms.value, n.value
 
     def multigrid_solve(self, vol, b, levels, n_outer, filt, alphas=None, power_iters=30, power_seed=0,
                         lam=0.0, bilateral=None, coarse_subsets=8, coarse_passes=2, want_hist=True):

@@ -26,6 +26,34 @@ using namespace mgct;
         if (r_ != MGCT_OK) return r_; \
     } while (0)
 
+namespace mgct {
+
+static hipEvent_t take_event(Ctx &c) {
+    if (!c.event_pool.empty()) {
+        hipEvent_t e = c.event_pool.back();
+        c.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+KernelTimer::KernelTimer(Ctx &c_, int op_, int level_, hipStream_t s_) : c(c_), op(op_), level(level_), s(s_) {
+    if (!c.timing) return;
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) (void)hipEventRecord(e0, s);
+}
+
+KernelTimer::~KernelTimer() {
+    if (!e0 || !e1) return;
+    (void)hipEventRecord(e1, s);
+    c.timed.push_back({op, level, e0, e1});
+}
+
+}  // namespace mgct
+
 namespace {
 
 constexpr int kRedBlocks = 1024;
@@ -82,7 +110,11 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
     const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
     void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es, true);
     if (!vt) return MGCT_ERR_OOM;
-    HIPCHK(launch_transpose_volume(vol, vol_dtype, vt, vt_dtype, L, s));
+    {
+        KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
+        HIPCHK(launch_transpose_volume(vol, vol_dtype, vt, vt_dtype, L, s));
+    }
+    KernelTimer t(c, MGCT_OP_PROJECT, g, s);
     HIPCHK(launch_project(vt, vt_dtype, proj, proj_dtype, L, view0, step, nsub, s));
     return MGCT_OK;
 }
@@ -91,7 +123,11 @@ int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, vo
                    int step, int nsub, hipStream_t s) {
     if (!L.separable) return MGCT_ERR_NOT_IMPLEMENTED;
     WS(pt, float, lvl("pt", g), (size_t)nsub * L.nu * L.nv * 4, false);
-    HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, L, view0, step, nsub, s));
+    {
+        KernelTimer t(c, MGCT_OP_DATA_PRESCALE, g, s);
+        HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, L, view0, step, nsub, s));
+    }
+    KernelTimer t(c, MGCT_OP_BACKPROJECT, g, s);
     HIPCHK(launch_backproject(pt, vol, vol_dtype, L, view0, step, nsub, s));
     return MGCT_OK;
 }
@@ -117,6 +153,7 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
     if (f->kind == MGCT_FILTER_STENCIL27) {
         WS(taps, float, "taps27", 27 * 4, false);
         HIPCHK(hipMemcpyAsync(taps, f->taps, 27 * 4, hipMemcpyHostToDevice, s));
+        KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
         const float *src = in;
         if (in == out) {
             WS(tmp, float, lvl("st_tmp", g), n * 4, false);
@@ -144,6 +181,7 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
         HIPCHK(hipMemcpy(tw, all.data(), ntw * sizeof(float2), hipMemcpyHostToDevice));
     }
     WS(work, float2, "fft_work", n * sizeof(float2), false);
+    KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
     HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, table, f->n_table, f->rho_max, tw, s));
     return MGCT_OK;
 }
@@ -300,11 +338,52 @@ int mgct_create(int device, void **ctx_out) {
     return MGCT_OK;
 }
 
+static void release_events(Ctx &c) {
+    for (auto &r : c.timed) {
+        c.event_pool.push_back(r.start);
+        c.event_pool.push_back(r.stop);
+    }
+    c.timed.clear();
+}
+
+int mgct_kernel_timing(void *ctx, int enable) {
+    if (!ctx) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    if (enable) {
+        HIPCHK(hipDeviceSynchronize());
+        release_events(c);
+    }
+    c.timing = enable != 0;
+    return MGCT_OK;
+}
+
+int mgct_kernel_time(void *ctx, int op, int level, double *total_ms, int *launches) {
+    if (!ctx || !total_ms || op < 0 || op >= MGCT_OP_COUNT) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    double tot = 0.0;
+    int n = 0;
+    for (auto &r : c.timed) {
+        if (r.op != op || (level >= 0 && r.level != level)) continue;
+        HIPCHK(hipEventSynchronize(r.stop));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.start, r.stop));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    if (launches) *launches = n;
+    return MGCT_OK;
+}
+
 int mgct_destroy(void *ctx) {
     if (!ctx) return MGCT_ERR_INVALID_ARG;
     Ctx *c = as_ctx(ctx);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    release_events(*c);
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
     for (auto &kv : c->ws) (void)hipFree(kv.second.first);
     for (auto &L : c->levels) free_level(L);
     delete c;

@@ -282,13 +282,19 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
     float kf[KZ];
 #pragma unroll
     for (int q = 0; q < KZ; ++q) kf[q] = (float)(zc_id * 64 * KZ + q * 64 + lane);
-    float acc[NP][KZ];
+    // per-view partial sums in FP32, summed over views in FP64
+    double acc[NP][KZ];
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int q = 0; q < KZ; ++q) acc[p][q] = 0.f;
+        for (int q = 0; q < KZ; ++q) acc[p][q] = 0.0;
 
     for (int vl = 0; vl < nviews_sub; ++vl) {
+        float pv[NP][KZ];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) pv[p][q] = 0.f;
         const int v = view0 + vl * view_step;
         const SepView S = sep[v];
         const float4 *cv = cols + (long)v * nu;
@@ -337,18 +343,22 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
                     float r[NP];
                     column_rows<NP>(col, zc, tz, rtz, nb, nv, kf[q], r);
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) acc[p][q] = fmaf(wp, r[p], acc[p][q]);
+                    for (int p = 0; p < NP; ++p) pv[p][q] = fmaf(wp, r[p], pv[p][q]);
                 }
             }
         }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) acc[p][q] += (double)pv[p][q];
     }
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
         const int k = zc_id * 64 * KZ + q * 64 + lane;
         if (k < nz) {
             const long o = ((long)k * ny + j) * nx + i;
-            store_f(vol0, o, acc[0][q]);
-            if (NP > 1) store_f(vol1, o, acc[NP - 1][q]);
+            store_f(vol0, o, (float)acc[0][q]);
+            if (NP > 1) store_f(vol1, o, (float)acc[NP - 1][q]);
         }
     }
 }

@@ -64,6 +64,24 @@ struct Ctx {
     std::map<std::string, std::pair<void *, size_t>> ws;
     // cached step sizes keyed by a description of (level, filter, iters, seed)
     std::map<std::string, double> alpha_cache;
+    // kernel timing records (start/stop events per launch)
+    struct TimedLaunch {
+        int op, level;
+        hipEvent_t start, stop;
+    };
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// Brackets one kernel launch with events when timing is enabled.
+struct KernelTimer {
+    Ctx &c;
+    int op, level;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KernelTimer(Ctx &c_, int op_, int level_, hipStream_t s_);
+    ~KernelTimer();
 };
 
 // ----- host helpers (api.cpp / geometry.cpp)

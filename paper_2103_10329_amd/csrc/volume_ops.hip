@@ -143,7 +143,9 @@ __global__ __launch_bounds__(256) void k_stencil27(const float *in, float *out, 
     const size_t n = (size_t)nx * ny * nz;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
         const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((size_t)nx * ny));
-        float acc = 0.f;
+        // FP64 accumulation: a zero-DC kernel applied to a smooth field is a
+        // difference of nearly equal sums, so FP32 would lose digits here.
+        double acc = 0.0;
 #pragma unroll
         for (int dz = -1; dz <= 1; ++dz) {
             const int zz = (z - dz + nz) % nz;
@@ -155,11 +157,11 @@ __global__ __launch_bounds__(256) void k_stencil27(const float *in, float *out, 
                 for (int dx = -1; dx <= 1; ++dx) {
                     const float w = taps[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
                     const int xx = (x - dx + nx) % nx;
-                    acc = fmaf(w, row[xx], acc);
+                    acc = fma((double)w, (double)row[xx], acc);
                 }
             }
         }
-        out[idx] = acc;
+        out[idx] = (float)acc;
     }
 }
 hipError_t launch_stencil27(const float *in, float *out, int nx, int ny, int nz, const float *taps, hipStream_t s) {
