@@ -130,18 +130,18 @@ int build_level(Ctx &c, int g, Level &L) {
     }
 
     std::vector<SepView> sv;
-    std::vector<float4> cols;
+    std::vector<ColD> cols;
     if (sep) {
         sv.resize(V);
         cols.resize((size_t)V * nu);
         for (int v = 0; v < V; ++v) {
             const ViewIdx &q = vi[v];
             SepView &o = sv[v];
-            o.sx = (float)q.s[0];
-            o.sy = (float)q.s[1];
-            o.sz = (float)q.s[2];
-            o.dz0 = (float)(q.d[2] - 0.5 * (nv - 1) * q.v[2] - q.s[2]);
-            o.vz = (float)q.v[2];
+            o.sx = q.s[0];
+            o.sy = q.s[1];
+            o.sz = q.s[2];
+            o.dz0 = q.d[2] - 0.5 * (nv - 1) * q.v[2] - q.s[2];
+            o.vz = q.v[2];
             // column hit by the ray from s through (px, py): with e = s - d and
             // w = P - s, alpha = (e x w) / (u x w) (2-D cross products), and
             // a = alpha + (nu-1)/2.  Written as a ratio of affine functions of P.
@@ -156,12 +156,11 @@ int build_level(Ctx &c, int g, Level &L) {
             o.ad0 = (float)ad0;
             o.ad1 = (float)ad1;
             o.ad2 = (float)ad2;
-            o.pad = 0.f;
             for (int a = 0; a < nu; ++a) {
                 double ca = a - 0.5 * (nu - 1);
                 double Dx = q.d[0] + ca * q.u[0] - q.s[0];
                 double Dy = q.d[1] + ca * q.u[1] - q.s[1];
-                cols[(size_t)v * nu + a] = make_float4((float)Dx, (float)Dy, (float)(1.0 / Dx), (float)(1.0 / Dy));
+                cols[(size_t)v * nu + a] = ColD{Dx, Dy, 1.0 / Dx, 1.0 / Dy};
             }
         }
     }
@@ -176,8 +175,8 @@ int build_level(Ctx &c, int g, Level &L) {
         if (hipMalloc(&L.d_sep, sizeof(SepView) * V) != hipSuccess) return MGCT_ERR_OOM;
         if (hipMemcpy(L.d_sep, sv.data(), sizeof(SepView) * V, hipMemcpyHostToDevice) != hipSuccess)
             return MGCT_ERR_HIP;
-        if (hipMalloc(&L.d_cols, sizeof(float4) * cols.size()) != hipSuccess) return MGCT_ERR_OOM;
-        if (hipMemcpy(L.d_cols, cols.data(), sizeof(float4) * cols.size(), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMalloc(&L.d_cols, sizeof(ColD) * cols.size()) != hipSuccess) return MGCT_ERR_OOM;
+        if (hipMemcpy(L.d_cols, cols.data(), sizeof(ColD) * cols.size(), hipMemcpyHostToDevice) != hipSuccess)
             return MGCT_ERR_HIP;
     }
     return MGCT_OK;

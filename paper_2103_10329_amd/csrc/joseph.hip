@@ -151,14 +151,15 @@ __global__ __launch_bounds__(256) void k_project(const VT *__restrict__ vt, PT *
         const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
         const int Sm = (m == 0) ? PY * PZ : PZ;
         const int Sa = (m == 0) ? PZ : PY * PZ;
-        const float Baf = (float)Ba, Bzf = (float)Bz;
-        const float Aaf = (float)(Aa + kVolPad), Azf = (float)(Az + kVolPad);
+        // Sample coordinates stay in FP64 (full-rate FMA on this GPU): their
+        // absolute error then stays far below the FP32 rounding of the weights.
+        const double Aap = Aa + kVolPad, Azp = Az + kVolPad;
         int off_m = (l0 + kVolPad) * Sm;
         for (int l = l0; l <= l1; ++l, off_m += Sm) {
-            const float lf = (float)l;
-            const float fa = fmaf(lf, Baf, Aaf), fz = fmaf(lf, Bzf, Azf);
-            const float ga = floorf(fa), gz = floorf(fz);
-            const float wa = fa - ga, wz = fz - gz;
+            const double lf = (double)l;
+            const double fa = fma(lf, Ba, Aap), fz = fma(lf, Bz, Azp);
+            const double ga = floor(fa), gz = floor(fz);
+            const float wa = (float)(fa - ga), wz = (float)(fz - gz);
             const int off = off_m + (int)ga * Sa + (int)gz;
             const float p00 = load_f(vt, off), p01 = load_f(vt, off + 1);
             const float p10 = load_f(vt, off + Sa), p11 = load_f(vt, off + Sa + 1);
@@ -247,18 +248,19 @@ __device__ __forceinline__ float column_coord(const SepView &S, float px, float 
 // Sum over the rows of one column whose sample (zc + tz*b) lies within one
 // voxel of k, of hat(zc + tz*b - k) * data[b].
 template <int NP>
-__device__ __forceinline__ void column_rows(const float *const *col, float zc, float tz, float rtz, int nb, int nv,
-                                            float k, float out[NP]) {
-    const float bc = (k - zc) * rtz;
-    const float hw = fabsf(rtz);
-    int bs = (int)ceilf(bc - hw);
+__device__ __forceinline__ void column_rows(const float *const *col, double zc, double tz, double rtz, int nb,
+                                            int nv, double k, float out[NP]) {
+    const double zk = zc - k;  // sample offset from voxel k of row b: zk + tz*b
+    const double bc = -zk * rtz;
+    const double hw = fabs(rtz);
+    int bs = (int)ceil(bc - hw);
     bs = max(0, min(bs, nv - nb));
 #pragma unroll
     for (int p = 0; p < NP; ++p) out[p] = 0.f;
     for (int t = 0; t < nb; ++t) {
         const int b = bs + t;
-        const float fz = fmaf(tz, (float)b, zc);
-        const float wgt = fmaxf(0.f, 1.f - fabsf(fz - k));
+        const float d = (float)fma(tz, (double)b, zk);
+        const float wgt = fmaxf(0.f, 1.f - fabsf(d));
 #pragma unroll
         for (int p = 0; p < NP; ++p) out[p] = fmaf(wgt, col[p][b], out[p]);
     }
@@ -268,7 +270,7 @@ template <int KZ, int NP, typename OT>
 __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict__ pt0, const float *__restrict__ pt1,
                                                          OT *__restrict__ vol0, OT *__restrict__ vol1,
                                                          const SepView *__restrict__ sep,
-                                                         const float4 *__restrict__ cols,
+                                                         const ColD *__restrict__ cols,
                                                          const uint8_t *__restrict__ axis, int nx, int ny, int nz,
                                                          int nu, int nv, int nviews_sub, int view0, int view_step) {
     const int lane = threadIdx.x & 63;
@@ -279,9 +281,9 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
     const int i = ij % nx, j = ij / nx;
     if (j >= ny) return;  // whole wave; no barrier below
     const float fi = (float)i, fj = (float)j;
-    float kf[KZ];
+    double kf[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) kf[q] = (float)(zc_id * 64 * KZ + q * 64 + lane);
+    for (int q = 0; q < KZ; ++q) kf[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][KZ];
 #pragma unroll
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
             for (int q = 0; q < KZ; ++q) pv[p][q] = 0.f;
         const int v = view0 + vl * view_step;
         const SepView S = sep[v];
-        const float4 *cv = cols + (long)v * nu;
+        const ColD *cv = cols + (long)v * nu;
         const uint8_t *av = axis + (long)v * nu;
         const float *base0 = pt0 + (long)vl * nu * nv;
         const float *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
@@ -319,22 +321,24 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
             ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
             for (int a = alo; a <= ahi; ++a) {
                 if (av[a] != part) continue;
-                const float4 C = cv[a];
-                float tau, wp;
+                const ColD C = cv[a];
+                // FP64 sample coordinates (see the projector)
+                double tau;
+                float wp;
                 if (part == 0) {
-                    tau = (fi - S.sx) * C.z;
-                    wp = 1.f - fabsf(fmaf(tau, C.y, S.sy) - fj);
+                    tau = ((double)i - S.sx) * C.rdx;
+                    wp = 1.f - (float)fabs(fma(tau, C.dy, S.sy) - (double)j);
                 } else {
-                    tau = (fj - S.sy) * C.w;
-                    wp = 1.f - fabsf(fmaf(tau, C.x, S.sx) - fi);
+                    tau = ((double)j - S.sy) * C.rdy;
+                    wp = 1.f - (float)fabs(fma(tau, C.dx, S.sx) - (double)i);
                 }
-                if (!(wp > 0.f) || tau < 0.f || tau > 1.f) continue;
-                const float tz = tau * S.vz;
-                if (!(fabsf(tz) > 1e-20f)) continue;
-                const float zc = fmaf(tau, S.dz0, S.sz);
-                const float rtz = 1.f / tz;
+                if (!(wp > 0.f) || tau < 0.0 || tau > 1.0) continue;
+                const double tz = tau * S.vz;
+                if (!(fabs(tz) > 1e-20)) continue;
+                const double zc = fma(tau, S.dz0, S.sz);
+                const double rtz = 1.0 / tz;
                 // rows whose sample lies within one voxel of k: at most floor(2/|tz|) + 1
-                const int nb = (int)fminf(2.f * fabsf(rtz) + 1.f, (float)nv);
+                const int nb = (int)fmin(2.0 * fabs(rtz) + 1.0, (double)nv);
                 const float *col[NP];
                 col[0] = base0 + (long)a * nv;
                 if (NP > 1) col[NP - 1] = base1 + (long)a * nv;

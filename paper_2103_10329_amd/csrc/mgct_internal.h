@@ -24,9 +24,13 @@ struct ViewIdx {
 // has direction (Dx(a), Dy(a), dz0 + b*vz); the detector column hit by the
 // ray through (px, py, .) is (an0 + an1 px + an2 py)/(ad0 + ad1 px + ad2 py).
 struct SepView {
-    float sx, sy, sz, dz0;
-    float vz, an0, an1, an2;
-    float ad0, ad1, ad2, pad;
+    double sx, sy, sz, dz0, vz;
+    float an0, an1, an2, ad0, ad1, ad2;
+};
+
+// Per-(view, column) ray direction of the separable geometry.
+struct ColD {
+    double dx, dy, rdx, rdy;  // Dx(a), Dy(a), 1/Dx(a), 1/Dy(a)
 };
 
 // Padding (voxels) around the transposed volume copy read by the projector.
@@ -39,7 +43,7 @@ struct Level {
     // device tables
     ViewIdx *d_views = nullptr;      // [view]
     SepView *d_sep = nullptr;        // [view]       (separable only)
-    float4 *d_cols = nullptr;        // [view][nu]: Dx, Dy, 1/Dx, 1/Dy (separable only)
+    ColD *d_cols = nullptr;          // [view][nu] (separable only)
     uint8_t *d_axis = nullptr;       // [view][nu] (separable) or [view][nv][nu]: 0 = x, 1 = y
     long axis_row_stride = 0;        // 0 (separable) or nu
     size_t vox() const { return (size_t)nx * ny * nz; }
