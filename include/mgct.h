@@ -122,7 +122,8 @@ int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const dou
  * ray is sampled on the voxel-centre planes of its major axis between source
  * and pixel, with bilinear interpolation (zero outside the grid), times the
  * sample spacing.  vol: device, vol_dtype F32 or BF16.  proj: device,
- * proj_dtype F32 or F16.  Accumulation is FP32.
+ * proj_dtype F32 or F16.  Accumulation is FP32.  A BF16 volume is read as
+ * BF16 (the projector's internal copy keeps BF16).
  */
 int mgct_project(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype,
                  hipStream_t stream);
@@ -131,10 +132,21 @@ int mgct_project(void *ctx, int level, const void *vol, int vol_dtype, void *pro
  * vol = A^T proj on grid `level` (Sec. 2.1: B is the adjoint of P): exact
  * transpose of mgct_project, evaluated voxel by voxel (a gather; no atomics,
  * so results are bit-identical from run to run).  proj: device, F32 or F16;
- * vol: device, F32 or BF16.  FP32 accumulation over views.
+ * vol: device, F32 or BF16.  FP32 accumulation per view, FP64 across views.
+ * F16 data are pre-scaled into an F16 copy.
  */
 int mgct_backproject(void *ctx, int level, const void *proj, int proj_dtype, void *vol, int vol_dtype,
                      hipStream_t stream);
+
+/*
+ * Storage precision of the copies a Landweber step makes (mgct_landweber_step,
+ * and every Landweber grid of mgct_multigrid_solve): the projector's copy of
+ * the volume (F32 or BF16) and the projected / residual / scaled data stacks
+ * (F32 or F16).  Interpolation and accumulation along rays and across views
+ * stay FP32 (norms FP64); the OS-EMTR coarse solve, the Fourier filter, the
+ * step-size estimate and the iterate itself stay FP32.  Default F32, F32.
+ */
+int mgct_set_precision(void *ctx, int volume_copy_dtype, int stack_dtype);
 
 /* out = p * in on grid `level` (eq. 4's convolution).  in, out: device F32 volumes (may alias). */
 int mgct_precondition(void *ctx, int level, const float *in, float *out, const mgct_filter *f,

@@ -81,6 +81,7 @@ SIGNATURES = {
     "mgct_bilateral": (_ci, [_vp, _ci, _vp, _vp, _cd, _cd, _vp]),
     "mgct_osemtr": (_ci, [_vp, _ci, _vp, _vp, _ci, _ci, _vp]),
     "mgct_multigrid_solve": (_ci, [_vp, _vp, _vp, _ci, ctypes.POINTER(mgct_mg_params), _dp, _vp]),
+    "mgct_set_precision": (_ci, [_vp, _ci, _ci]),
     "mgct_kernel_timing": (_ci, [_vp, _ci]),
     "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
 }
@@ -228,6 +229,11 @@ class Context:
         g = self.geom
         f = 2 ** level
         return (g["nz"] // f, g["ny"] // f, g["nx"] // f), (g["n_views"], g["nv"] // f, g["nu"] // f)
+
+    def set_precision(self, volume_copy: str = "float32", stack: str = "float32"):
+        """Storage of the Landweber steps' internal copies: volume copy
+        float32|bfloat16, data stacks float32|float16."""
+        check(mgct_set_precision(self.handle, _DT[volume_copy], _DT[stack]), "mgct_set_precision")  # noqa: F821
 
     # ---- operators
     def project(self, vol, out=None, level: int = 0, out_dtype=None):

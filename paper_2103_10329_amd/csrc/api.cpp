@@ -105,8 +105,9 @@ bool stack_dtype_ok(int d) { return d == MGCT_F32 || d == MGCT_F16; }
 
 // ---- projector and transpose on a subset of views (view0 + k*step, k < nsub)
 int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *proj, int proj_dtype, int view0,
-               int step, int nsub, hipStream_t s) {
-    const int vt_dtype = vol_dtype;
+               int step, int nsub, hipStream_t s, int vt_dtype = -1) {
+    // the projector's volume copy: BF16 when the input is BF16 or when asked
+    if (vt_dtype < 0 || vol_dtype == MGCT_BF16) vt_dtype = vol_dtype;
     const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
     void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es, true);
     if (!vt) return MGCT_ERR_OOM;
@@ -120,15 +121,24 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
 }
 
 int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, void *vol, int vol_dtype, int view0,
-                   int step, int nsub, hipStream_t s) {
+                   int step, int nsub, hipStream_t s, int pt_dtype = -1) {
     if (!L.separable) return MGCT_ERR_NOT_IMPLEMENTED;
-    WS(pt, float, lvl("pt", g), (size_t)nsub * L.nu * L.nv * 4, false);
+    // the scaled, transposed data copy: F16 when the input is F16 or when asked
+    if (pt_dtype < 0 || proj_dtype == MGCT_F16) pt_dtype = proj_dtype;
+    const size_t es = pt_dtype == MGCT_F32 ? 4 : 2;
+    WS(pt, char, lvl(pt_dtype == MGCT_F32 ? "pt" : "pt16", g), (size_t)nsub * L.nu * L.nv * es, false);
     {
         KernelTimer t(c, MGCT_OP_DATA_PRESCALE, g, s);
-        HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, L, view0, step, nsub, s));
+        HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, pt_dtype, L, view0, step, nsub, s));
+    }
+    const size_t sb = backproject_scratch_bytes(L, nsub, 1);
+    float *scratch = nullptr;
+    if (sb) {
+        scratch = static_cast<float *>(workspace(c, lvl("bp_scratch", g), sb, false));
+        if (!scratch) return MGCT_ERR_OOM;
     }
     KernelTimer t(c, MGCT_OP_BACKPROJECT, g, s);
-    HIPCHK(launch_backproject(pt, vol, vol_dtype, L, view0, step, nsub, s));
+    HIPCHK(launch_backproject(pt, pt_dtype, vol, vol_dtype, scratch, L, view0, step, nsub, s));
     return MGCT_OK;
 }
 
@@ -189,15 +199,19 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
 // norm2_out: device double receiving ||b - A vol||^2 (may be null)
 int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype, double alpha, const mgct_filter *f,
                  double *norm2_out, hipStream_t s) {
-    WS(ax, float, lvl("lw_ax", g), L.rays() * 4, false);
-    WS(r, float, lvl("lw_r", g), L.rays() * 4, false);
+    // internal storage per the context's precision setting; arithmetic and
+    // accumulation stay FP32 (FP64 for the norm)
+    const int sd = c.stack_dtype;
+    const size_t es = sd == MGCT_F32 ? 4 : 2;
+    WS(ax, char, lvl(sd == MGCT_F32 ? "lw_ax" : "lw_ax16", g), L.rays() * es, false);
+    WS(r, char, lvl(sd == MGCT_F32 ? "lw_r" : "lw_r16", g), L.rays() * es, false);
     WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
     WS(part, double, "red_partials", kRedBlocks * 8, false);
     WS(nrm, double, "red_scratch", 8, false);
-    MGCHK(do_project(c, L, g, vol, MGCT_F32, ax, MGCT_F32, 0, 1, L.nviews, s));
-    HIPCHK(launch_residual(b, b_dtype, ax, r, L.rays(), part, kRedBlocks, s));
+    MGCHK(do_project(c, L, g, vol, MGCT_F32, ax, sd, 0, 1, L.nviews, s, c.vt_dtype));
+    HIPCHK(launch_residual(b, b_dtype, ax, r, sd, L.rays(), part, kRedBlocks, s));
     HIPCHK(launch_finish_sum(part, kRedBlocks, norm2_out ? norm2_out : nrm, s));
-    MGCHK(do_backproject(c, L, g, r, MGCT_F32, grad, MGCT_F32, 0, 1, L.nviews, s));
+    MGCHK(do_backproject(c, L, g, r, sd, grad, MGCT_F32, 0, 1, L.nviews, s));
     MGCHK(do_precondition(c, L, g, grad, grad, f, s));
     HIPCHK(launch_axpy(vol, grad, alpha, L.vox(), s));
     return MGCT_OK;
@@ -208,7 +222,7 @@ int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b,
     WS(r, float, lvl("lw_r", g), L.rays() * 4, false);
     WS(part, double, "red_partials", kRedBlocks * 8, false);
     MGCHK(do_project(c, L, g, vol, MGCT_F32, ax, MGCT_F32, 0, 1, L.nviews, s));
-    HIPCHK(launch_residual(b, MGCT_F32, ax, r, L.rays(), part, kRedBlocks, s));
+    HIPCHK(launch_residual(b, MGCT_F32, ax, r, MGCT_F32, L.rays(), part, kRedBlocks, s));
     HIPCHK(launch_finish_sum(part, kRedBlocks, norm2_out, s));
     return MGCT_OK;
 }
@@ -234,9 +248,15 @@ int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int pa
             const int nsub = (L.nviews - m + M - 1) / M;
             MGCHK(do_project(c, L, g, vol, MGCT_F32, l, MGCT_F32, m, M, nsub, s));
             HIPCHK(launch_emtr_terms(l, b, pi, nsrc, dsrc, L, m, M, nsub, s));
-            HIPCHK(launch_scale_transpose_stack(nsrc, MGCT_F32, pt0, L, m, M, nsub, s));
-            HIPCHK(launch_scale_transpose_stack(dsrc, MGCT_F32, pt1, L, m, M, nsub, s));
-            HIPCHK(launch_backproject2(pt0, pt1, num, den, L, m, M, nsub, s));
+            HIPCHK(launch_scale_transpose_stack(nsrc, MGCT_F32, pt0, MGCT_F32, L, m, M, nsub, s));
+            HIPCHK(launch_scale_transpose_stack(dsrc, MGCT_F32, pt1, MGCT_F32, L, m, M, nsub, s));
+            const size_t sb = backproject_scratch_bytes(L, nsub, 2);
+            float *scratch = nullptr;
+            if (sb) {
+                scratch = static_cast<float *>(workspace(c, lvl("bp_scratch2", g), sb, false));
+                if (!scratch) return MGCT_ERR_OOM;
+            }
+            HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s));
             HIPCHK(launch_max_reset(mx, s));
             HIPCHK(launch_max_reduce(den, n, mx, s));
             HIPCHK(launch_emtr_update(vol, num, den, n, mx, s));
@@ -411,6 +431,14 @@ int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const dou
     int r = get_level(c, 0, &L);
     if (r != MGCT_OK) c.has_geom = false;
     return r;
+}
+
+int mgct_set_precision(void *ctx, int volume_copy_dtype, int stack_dtype) {
+    if (!ctx || !vol_dtype_ok(volume_copy_dtype) || !stack_dtype_ok(stack_dtype)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    c.vt_dtype = volume_copy_dtype;
+    c.stack_dtype = stack_dtype;
+    return MGCT_OK;
 }
 
 int mgct_project(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype, hipStream_t s) {

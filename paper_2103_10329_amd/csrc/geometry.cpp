@@ -156,11 +156,15 @@ int build_level(Ctx &c, int g, Level &L) {
             o.ad0 = (float)ad0;
             o.ad1 = (float)ad1;
             o.ad2 = (float)ad2;
+            o.flags = 0;
+            o.pad = 0;
             for (int a = 0; a < nu; ++a) {
                 double ca = a - 0.5 * (nu - 1);
                 double Dx = q.d[0] + ca * q.u[0] - q.s[0];
                 double Dy = q.d[1] + ca * q.u[1] - q.s[1];
-                cols[(size_t)v * nu + a] = ColD{Dx, Dy, 1.0 / Dx, 1.0 / Dy};
+                cols[(size_t)v * nu + a] = ColD{Dx, Dy, 1.0 / Dx, 1.0 / Dy, Dx / q.v[2], Dy / q.v[2],
+                                                (int)axis[(size_t)v * nu + a], {0, 0, 0}};
+                o.flags |= axis[(size_t)v * nu + a] == 0 ? 1 : 2;
             }
         }
     }

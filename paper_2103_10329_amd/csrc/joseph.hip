@@ -20,6 +20,8 @@
 // [view][column][row] so that those row reads are contiguous across lanes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mgct_internal.h"
 
 namespace mgct {
@@ -190,8 +192,8 @@ hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dty
 // ------------------------------------------- data pre-scale and transpose --
 
 // pt[vl][a][b] = proj[vl][b][a] * h|D|/|D_m| of ray (view0 + vl*step, a, b).
-template <typename PT>
-__global__ __launch_bounds__(256) void k_scale_transpose(const PT *__restrict__ proj, float *__restrict__ pt,
+template <typename PT, typename OT>
+__global__ __launch_bounds__(256) void k_scale_transpose(const PT *__restrict__ proj, OT *__restrict__ pt,
                                                          const ViewIdx *__restrict__ views,
                                                          const uint8_t *__restrict__ axis, long axis_view_stride,
                                                          long axis_row_stride, int nu, int nv, double h, int view0,
@@ -220,59 +222,131 @@ __global__ __launch_bounds__(256) void k_scale_transpose(const PT *__restrict__ 
     for (int r = 0; r < 16; ++r) {
         int al = (t >> 6) + 4 * r, bl = t & 63;
         int b = b0 + bl, a = a0 + al;
-        if (a < nu && b < nv) pt[((long)vl * nu + a) * nv + b] = tile[bl][al];
+        if (a < nu && b < nv) store_f(pt, ((long)vl * nu + a) * nv + b, tile[bl][al]);
     }
 }
 
-hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, float *pt, const Level &L, int view0,
-                                        int view_step, int nviews_sub, hipStream_t s) {
+hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, void *pt, int pt_dtype, const Level &L,
+                                        int view0, int view_step, int nviews_sub, hipStream_t s) {
     dim3 grid((L.nu + 63) / 64, (L.nv + 63) / 64, nviews_sub);
     const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
-    if (proj_dtype == MGCT_F32)
-        k_scale_transpose<float><<<grid, 256, 0, s>>>((const float *)proj, pt, L.d_views, L.d_axis, avs,
-                                                      L.axis_row_stride, L.nu, L.nv, L.h, view0, view_step);
-    else if (proj_dtype == MGCT_F16)
-        k_scale_transpose<_Float16><<<grid, 256, 0, s>>>((const _Float16 *)proj, pt, L.d_views, L.d_axis, avs,
-                                                         L.axis_row_stride, L.nu, L.nv, L.h, view0, view_step);
-    else
-        return hipErrorInvalidValue;
+#define MGCT_ST(PT, OT)                                                                                           \
+    k_scale_transpose<PT, OT><<<grid, 256, 0, s>>>((const PT *)proj, (OT *)pt, L.d_views, L.d_axis, avs,          \
+                                                   L.axis_row_stride, L.nu, L.nv, L.h, view0, view_step)
+    if (proj_dtype == MGCT_F32 && pt_dtype == MGCT_F32) MGCT_ST(float, float);
+    else if (proj_dtype == MGCT_F16 && pt_dtype == MGCT_F32) MGCT_ST(_Float16, float);
+    else if (proj_dtype == MGCT_F32 && pt_dtype == MGCT_F16) MGCT_ST(float, _Float16);
+    else if (proj_dtype == MGCT_F16 && pt_dtype == MGCT_F16) MGCT_ST(_Float16, _Float16);
+    else return hipErrorInvalidValue;
+#undef MGCT_ST
     return hipGetLastError();
 }
 
 // -------------------------------------------------------- back-projector --
 
+// Detector column of the ray through (px, py, .); only used to bound the
+// candidate columns (with a margin), so an approximate reciprocal will do.
 __device__ __forceinline__ float column_coord(const SepView &S, float px, float py) {
-    return (S.an0 + S.an1 * px + S.an2 * py) / (S.ad0 + S.ad1 * px + S.ad2 * py);
+    return (S.an0 + S.an1 * px + S.an2 * py) * __builtin_amdgcn_rcpf(S.ad0 + S.ad1 * px + S.ad2 * py);
 }
 
-// Sum over the rows of one column whose sample (zc + tz*b) lies within one
-// voxel of k, of hat(zc + tz*b - k) * data[b].
-template <int NP>
-__device__ __forceinline__ void column_rows(const float *const *col, double zc, double tz, double rtz, int nb,
-                                            int nv, double k, float out[NP]) {
-    const double zk = zc - k;  // sample offset from voxel k of row b: zk + tz*b
-    const double bc = -zk * rtz;
-    const double hw = fabs(rtz);
-    int bs = (int)ceil(bc - hw);
-    bs = max(0, min(bs, nv - nb));
+// One wave handles 64*KZ voxels of one (x, y) column, lane + 64*q for q < KZ.
+// For each view and each candidate detector column a (wave-uniform), the
+// rays of column a meet the voxel's plane on a line along z where row b sits
+// at zk + tz*b relative to the voxel; the lane sums hat(zk + tz*b) * data over
+// the rows with |zk + tz*b| < 1 and weights the sum by the in-plane hat of
+// the column.  PART 0: x-major rays on plane x = i (in-plane offset along y);
+// PART 1: y-major rays on plane y = j (offset along x).
+template <int PART, int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict__ cv,
+                                        const PT *base0, const PT *base1, int i, int j, int nu, int nv,
+                                        const double (&kd)[KZ], float (&pv)[NP][KZ]) {
+    const float fi = (float)i, fj = (float)j;
+    float c1, c2;
+    if (PART == 0) {
+        c1 = column_coord(S, fi, fj - 1.f);
+        c2 = column_coord(S, fi, fj + 1.f);
+    } else {
+        c1 = column_coord(S, fi - 1.f, fj);
+        c2 = column_coord(S, fi + 1.f, fj);
+    }
+    int alo = (int)floorf(fminf(c1, c2) - 0.01f);
+    int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
+    alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
+    ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+    if (alo > ahi) return;
+    // distance of the plane from the source along the major axis
+    const double dm = (PART == 0) ? (double)i - S.sx : (double)j - S.sy;
+    const double inv_dm = 1.0 / dm;
+    for (int a = alo; a <= ahi; ++a) {
+        const ColD C = cv[a];
+        if (C.axis != PART) continue;
+        const double tau = dm * ((PART == 0) ? C.rdx : C.rdy);  // ray parameter at the plane
+        const double off = (PART == 0) ? fma(tau, C.dy, S.sy) - (double)j : fma(tau, C.dx, S.sx) - (double)i;
+        const float wp = 1.f - (float)fabs(off);
+        if (!(wp > 0.f) || tau < 0.0 || tau > 1.0) continue;
+        const double tz = tau * S.vz;                           // row spacing along z at the plane
+        const double zc = fma(tau, S.dz0, S.sz);                // z of row 0 at the plane
+        const double rtz = ((PART == 0) ? C.dxv : C.dyv) * inv_dm;  // 1 / tz
+        const double hw = fabs(rtz);
+        const PT *col0 = base0 + (long)a * nv;
+        const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
+        if (hw < 2.0 && nv >= 4) {
+            // at most 4 rows lie within one voxel of any z: a fixed window
+            const float tzf = (float)tz;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) out[p] = 0.f;
-    for (int t = 0; t < nb; ++t) {
-        const int b = bs + t;
-        const float d = (float)fma(tz, (double)b, zk);
-        const float wgt = fmaxf(0.f, 1.f - fabsf(d));
+            for (int q = 0; q < KZ; ++q) {
+                const double zk = zc - kd[q];
+                int bs = (int)ceil(-zk * rtz - hw);
+                bs = max(0, min(bs, nv - 4));
+                const float d0 = (float)fma(tz, (double)bs, zk);
+                const PT *p0 = col0 + bs;
+                float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) out[p] = fmaf(wgt, col[p][b], out[p]);
+                for (int t = 0; t < 4; ++t) {
+                    const float d = (t == 0) ? d0 : fmaf((float)t, tzf, d0);
+                    const float w = fmaxf(0.f, 1.f - fabsf(d));
+                    s0 = fmaf(w, load_f(p0, t), s0);
+                    if (NP > 1) s1 = fmaf(w, load_f(col1, bs + t), s1);
+                }
+                pv[0][q] = fmaf(wp, s0, pv[0][q]);
+                if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
+            }
+        } else {
+            const int nb = (int)fmin(2.0 * hw + 1.0, (double)nv);
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) {
+                const double zk = zc - kd[q];
+                int bs = (int)ceil(-zk * rtz - hw);
+                bs = max(0, min(bs, nv - nb));
+                float s0 = 0.f, s1 = 0.f;
+                for (int t = 0; t < nb; ++t) {
+                    const int b = bs + t;
+                    const float d = (float)fma(tz, (double)b, zk);
+                    const float w = fmaxf(0.f, 1.f - fabsf(d));
+                    s0 = fmaf(w, load_f(col0, b), s0);
+                    if (NP > 1) s1 = fmaf(w, load_f(col1, b), s1);
+                }
+                pv[0][q] = fmaf(wp, s0, pv[0][q]);
+                if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
+            }
+        }
     }
 }
 
-template <int KZ, int NP, typename OT>
-__global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict__ pt0, const float *__restrict__ pt1,
+// Views [chunk*per, min(nviews_sub, (chunk+1)*per)) with chunk = blockIdx.y.
+// With one chunk the result goes straight to vol0/vol1 (type OT); with more,
+// each chunk writes FP32 partial volumes part0/part1 + chunk * nvox, summed
+// afterwards in a fixed order (deterministic).
+template <int KZ, int NP, typename OT, typename PT>
+__global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
                                                          OT *__restrict__ vol0, OT *__restrict__ vol1,
+                                                         float *__restrict__ part0, float *__restrict__ part1,
                                                          const SepView *__restrict__ sep,
                                                          const ColD *__restrict__ cols,
                                                          const uint8_t *__restrict__ axis, int nx, int ny, int nz,
-                                                         int nu, int nv, int nviews_sub, int view0, int view_step) {
+                                                         int nu, int nv, int nviews_sub, int view0, int view_step,
+                                                         int per_chunk) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
@@ -280,10 +354,9 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
     const int ij = wave / zchunks;
     const int i = ij % nx, j = ij / nx;
     if (j >= ny) return;  // whole wave; no barrier below
-    const float fi = (float)i, fj = (float)j;
-    double kf[KZ];
+    double kd[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) kf[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
+    for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][KZ];
 #pragma unroll
@@ -291,7 +364,9 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
 #pragma unroll
         for (int q = 0; q < KZ; ++q) acc[p][q] = 0.0;
 
-    for (int vl = 0; vl < nviews_sub; ++vl) {
+    const int vbeg = blockIdx.y * per_chunk;
+    const int vend = min(nviews_sub, vbeg + per_chunk);
+    for (int vl = vbeg; vl < vend; ++vl) {
         float pv[NP][KZ];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -300,85 +375,69 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const float *__restrict
         const int v = view0 + vl * view_step;
         const SepView S = sep[v];
         const ColD *cv = cols + (long)v * nu;
-        const uint8_t *av = axis + (long)v * nu;
-        const float *base0 = pt0 + (long)vl * nu * nv;
-        const float *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-#pragma unroll
-        for (int part = 0; part < 2; ++part) {
-            // part 0: x-major rays sampled on plane x = i, in-plane offset in y;
-            // part 1: y-major rays sampled on plane y = j, in-plane offset in x.
-            float c1, c2;
-            if (part == 0) {
-                c1 = column_coord(S, fi, fj - 1.f);
-                c2 = column_coord(S, fi, fj + 1.f);
-            } else {
-                c1 = column_coord(S, fi - 1.f, fj);
-                c2 = column_coord(S, fi + 1.f, fj);
-            }
-            int alo = (int)floorf(fminf(c1, c2) - 0.01f);
-            int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
-            alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
-            ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
-            for (int a = alo; a <= ahi; ++a) {
-                if (av[a] != part) continue;
-                const ColD C = cv[a];
-                // FP64 sample coordinates (see the projector)
-                double tau;
-                float wp;
-                if (part == 0) {
-                    tau = ((double)i - S.sx) * C.rdx;
-                    wp = 1.f - (float)fabs(fma(tau, C.dy, S.sy) - (double)j);
-                } else {
-                    tau = ((double)j - S.sy) * C.rdy;
-                    wp = 1.f - (float)fabs(fma(tau, C.dx, S.sx) - (double)i);
-                }
-                if (!(wp > 0.f) || tau < 0.0 || tau > 1.0) continue;
-                const double tz = tau * S.vz;
-                if (!(fabs(tz) > 1e-20)) continue;
-                const double zc = fma(tau, S.dz0, S.sz);
-                const double rtz = 1.0 / tz;
-                // rows whose sample lies within one voxel of k: at most floor(2/|tz|) + 1
-                const int nb = (int)fmin(2.0 * fabs(rtz) + 1.0, (double)nv);
-                const float *col[NP];
-                col[0] = base0 + (long)a * nv;
-                if (NP > 1) col[NP - 1] = base1 + (long)a * nv;
-#pragma unroll
-                for (int q = 0; q < KZ; ++q) {
-                    float r[NP];
-                    column_rows<NP>(col, zc, tz, rtz, nb, nv, kf[q], r);
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) pv[p][q] = fmaf(wp, r[p], pv[p][q]);
-                }
-            }
-        }
+        const PT *base0 = pt0 + (long)vl * nu * nv;
+        const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
+        if (S.flags & 1) bp_part<0, KZ, NP, PT>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
+        if (S.flags & 2) bp_part<1, KZ, NP, PT>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int q = 0; q < KZ; ++q) acc[p][q] += (double)pv[p][q];
     }
+    const long nvox = (long)nx * ny * nz;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
         const int k = zc_id * 64 * KZ + q * 64 + lane;
         if (k < nz) {
             const long o = ((long)k * ny + j) * nx + i;
-            store_f(vol0, o, (float)acc[0][q]);
-            if (NP > 1) store_f(vol1, o, (float)acc[NP - 1][q]);
+            if (gridDim.y == 1) {
+                store_f(vol0, o, (float)acc[0][q]);
+                if (NP > 1) store_f(vol1, o, (float)acc[NP - 1][q]);
+            } else {
+                part0[blockIdx.y * nvox + o] = (float)acc[0][q];
+                if (NP > 1) part1[blockIdx.y * nvox + o] = (float)acc[NP - 1][q];
+            }
         }
     }
 }
 
-template <int NP, typename OT>
-static hipError_t launch_bp(const float *pt0, const float *pt1, OT *vol0, OT *vol1, const Level &L, int view0,
-                            int view_step, int nviews_sub, hipStream_t s) {
+template <typename OT>
+__global__ void k_sum_chunks(const float *__restrict__ part, OT *__restrict__ out, long nvox, int nchunks) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < nvox; i += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < nchunks; ++c) acc += (double)part[c * nvox + i];
+        store_f(out, i, (float)acc);
+    }
+}
+
+int bp_chunks(const Level &L, int nviews_sub) {
+    int KZ = 1;
+    while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
+    const long waves = (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * L.nx * L.ny;
+    long c = (16384 + waves - 1) / waves;
+    if (c > 64) c = 64;
+    if (c > nviews_sub) c = nviews_sub;
+    return c < 1 ? 1 : (int)c;
+}
+
+template <int NP, typename OT, typename PT>
+static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, float *part, const Level &L,
+                            int view0, int view_step, int nviews_sub, hipStream_t s) {
     if (!L.separable) return hipErrorNotSupported;
     int KZ = 1;
     while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
     const long zchunks = (L.nz + 64 * KZ - 1) / (64 * KZ);
     const long waves = zchunks * L.nx * L.ny;
-    dim3 grid((unsigned)((waves + 3) / 4));
-#define MGCT_BP(K)                                                                                                \
-    k_backproject_sep<K, NP, OT><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, L.d_sep, L.d_cols, L.d_axis, L.nx, L.ny, \
-                                                      L.nz, L.nu, L.nv, nviews_sub, view0, view_step)
+    const int nchunks = bp_chunks(L, nviews_sub);
+    const int per = (nviews_sub + nchunks - 1) / nchunks;
+    const long nvox = (long)L.nx * L.ny * L.nz;
+    float *part0 = part, *part1 = part ? part + (long)nchunks * nvox : nullptr;
+    if (nchunks > 1 && !part) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
+#define MGCT_BP(K)                                                                                                  \
+    k_backproject_sep<K, NP, OT, PT><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
+                                                      L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
+                                                      view_step, per)
     switch (KZ) {
         case 1: MGCT_BP(1); break;
         case 2: MGCT_BP(2); break;
@@ -386,21 +445,35 @@ static hipError_t launch_bp(const float *pt0, const float *pt1, OT *vol0, OT *vo
         default: MGCT_BP(8); break;
     }
 #undef MGCT_BP
+    if (nchunks > 1) {
+        unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);
+        k_sum_chunks<OT><<<g, 256, 0, s>>>(part0, vol0, nvox, nchunks);
+        if (NP > 1) k_sum_chunks<OT><<<g, 256, 0, s>>>(part1, vol1, nvox, nchunks);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(const float *pt, void *vol, int vol_dtype, const Level &L, int view0, int view_step,
-                              int nviews_sub, hipStream_t s) {
-    if (vol_dtype == MGCT_F32)
-        return launch_bp<1, float>(pt, nullptr, (float *)vol, nullptr, L, view0, view_step, nviews_sub, s);
-    if (vol_dtype == MGCT_BF16)
-        return launch_bp<1, uint16_t>(pt, nullptr, (uint16_t *)vol, nullptr, L, view0, view_step, nviews_sub, s);
+size_t backproject_scratch_bytes(const Level &L, int nviews_sub, int np) {
+    const int c = bp_chunks(L, nviews_sub);
+    return c > 1 ? (size_t)c * L.vox() * sizeof(float) * np : 0;
+}
+
+hipError_t launch_backproject(const void *pt, int pt_dtype, void *vol, int vol_dtype, float *scratch, const Level &L,
+                              int view0, int view_step, int nviews_sub, hipStream_t s) {
+#define MGCT_LBP(OT, PT)                                                                                           \
+    return launch_bp<1, OT, PT>((const PT *)pt, nullptr, (OT *)vol, nullptr, scratch, L, view0, view_step,         \
+                                nviews_sub, s)
+    if (vol_dtype == MGCT_F32 && pt_dtype == MGCT_F32) MGCT_LBP(float, float);
+    if (vol_dtype == MGCT_BF16 && pt_dtype == MGCT_F32) MGCT_LBP(uint16_t, float);
+    if (vol_dtype == MGCT_F32 && pt_dtype == MGCT_F16) MGCT_LBP(float, _Float16);
+    if (vol_dtype == MGCT_BF16 && pt_dtype == MGCT_F16) MGCT_LBP(uint16_t, _Float16);
+#undef MGCT_LBP
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, const Level &L,
-                               int view0, int view_step, int nviews_sub, hipStream_t s) {
-    return launch_bp<2, float>(pt0, pt1, vol0, vol1, L, view0, view_step, nviews_sub, s);
+hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, float *scratch,
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
+    return launch_bp<2, float, float>(pt0, pt1, vol0, vol1, scratch, L, view0, view_step, nviews_sub, s);
 }
 
 }  // namespace mgct

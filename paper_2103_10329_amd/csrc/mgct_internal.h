@@ -26,11 +26,17 @@ struct ViewIdx {
 struct SepView {
     double sx, sy, sz, dz0, vz;
     float an0, an1, an2, ad0, ad1, ad2;
+    int flags;  // bit 0: the view has x-major columns, bit 1: y-major columns
+    int pad;
 };
 
 // Per-(view, column) ray direction of the separable geometry.
+// 64 bytes: one scalar load per column.
 struct ColD {
     double dx, dy, rdx, rdy;  // Dx(a), Dy(a), 1/Dx(a), 1/Dy(a)
+    double dxv, dyv;          // Dx(a)/vz, Dy(a)/vz
+    int axis;                 // 0: x-major, 1: y-major
+    int pad[3];
 };
 
 // Padding (voxels) around the transposed volume copy read by the projector.
@@ -73,6 +79,9 @@ struct Ctx {
         int op, level;
         hipEvent_t start, stop;
     };
+    // storage of the Landweber steps' internal copies: the projector's
+    // volume copy (F32 or BF16) and the data/residual stacks (F32 or F16)
+    int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
@@ -100,19 +109,22 @@ hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int
                                    hipStream_t s);
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L,
                           int view0, int view_step, int nviews_sub, hipStream_t s);
-hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, float *pt, const Level &L,
+hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, void *pt, int pt_dtype, const Level &L,
                                         int view0, int view_step, int nviews_sub, hipStream_t s);
-hipError_t launch_backproject(const float *pt, void *vol, int vol_dtype, const Level &L, int view0,
-                              int view_step, int nviews_sub, hipStream_t s);
-hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, const Level &L,
-                               int view0, int view_step, int nviews_sub, hipStream_t s);
+// scratch: backproject_scratch_bytes() bytes (partial volumes when the views
+// are split over several chunks of waves for small grids), may be null if 0
+size_t backproject_scratch_bytes(const Level &L, int nviews_sub, int np);
+hipError_t launch_backproject(const void *pt, int pt_dtype, void *vol, int vol_dtype, float *scratch, const Level &L,
+                              int view0, int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, float *scratch,
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
 
 // Volume / stack operations (volume_ops.hip)
 hipError_t launch_fill(float *x, size_t n, float value, hipStream_t s);
 hipError_t launch_copy(const float *x, float *y, size_t n, hipStream_t s);
 hipError_t launch_convert_to_f32(const void *x, int dtype, float *y, size_t n, hipStream_t s);
-hipError_t launch_residual(const void *b, int b_dtype, const float *ax, float *r, size_t n, double *partials,
-                           int nblocks, hipStream_t s);
+hipError_t launch_residual(const void *b, int b_dtype, const void *ax, void *r, int ax_dtype, size_t n,
+                           double *partials, int nblocks, hipStream_t s);
 hipError_t launch_sumsq(const float *x, size_t n, double *partials, int nblocks, hipStream_t s);
 hipError_t launch_finish_sum(const double *partials, int n, double *out, hipStream_t s);
 hipError_t launch_axpy(float *y, const float *x, double alpha, size_t n, hipStream_t s);

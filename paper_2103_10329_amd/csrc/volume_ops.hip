@@ -60,23 +60,29 @@ __device__ __forceinline__ double block_sum(double v) {
     return red[0];
 }
 
-// r = b - ax; partials[block] = sum of r^2 over the block's grid-stride share.
-template <typename T>
-__global__ __launch_bounds__(256) void k_residual(const T *b, const float *ax, float *r, size_t n, double *partials) {
+// r = b - ax; partials[block] = sum of r^2 (of the stored r) over the
+// block's grid-stride share.  b: F32/F16, ax and r: F32 or F16 storage.
+template <typename TB, typename TA>
+__global__ __launch_bounds__(256) void k_residual(const TB *b, const TA *ax, TA *r, size_t n, double *partials) {
     double acc = 0.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        float d = to_f<T>(b[i]) - ax[i];
+        const TA d = (TA)(to_f<TB>(b[i]) - to_f<TA>(ax[i]));
         r[i] = d;
-        acc += (double)d * (double)d;
+        const double dd = (double)to_f<TA>(d);
+        acc += dd * dd;
     }
     double t = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
-hipError_t launch_residual(const void *b, int b_dtype, const float *ax, float *r, size_t n, double *partials,
-                           int nblocks, hipStream_t s) {
-    if (b_dtype == MGCT_F32) k_residual<float><<<nblocks, 256, 0, s>>>((const float *)b, ax, r, n, partials);
-    else if (b_dtype == MGCT_F16) k_residual<_Float16><<<nblocks, 256, 0, s>>>((const _Float16 *)b, ax, r, n, partials);
+hipError_t launch_residual(const void *b, int b_dtype, const void *ax, void *r, int ax_dtype, size_t n,
+                           double *partials, int nblocks, hipStream_t s) {
+#define MGCT_RES(TB, TA) k_residual<TB, TA><<<nblocks, 256, 0, s>>>((const TB *)b, (const TA *)ax, (TA *)r, n, partials)
+    if (b_dtype == MGCT_F32 && ax_dtype == MGCT_F32) MGCT_RES(float, float);
+    else if (b_dtype == MGCT_F16 && ax_dtype == MGCT_F32) MGCT_RES(_Float16, float);
+    else if (b_dtype == MGCT_F32 && ax_dtype == MGCT_F16) MGCT_RES(float, _Float16);
+    else if (b_dtype == MGCT_F16 && ax_dtype == MGCT_F16) MGCT_RES(_Float16, _Float16);
     else return hipErrorInvalidValue;
+#undef MGCT_RES
     return hipGetLastError();
 }
 
