@@ -39,6 +39,41 @@ template <> __device__ __forceinline__ float load_f<float>(const float *p, long 
 template <> __device__ __forceinline__ float load_f<uint16_t>(const uint16_t *p, long i) { return bf16_to_f32(p[i]); }
 template <> __device__ __forceinline__ float load_f<_Float16>(const _Float16 *p, long i) { return (float)p[i]; }
 
+// Load element `i` of an array smaller than 4 GiB through a 32-bit byte
+// offset, so that the access can use the scalar-base + 32-bit-offset form.
+template <typename T> __device__ __forceinline__ float load_off(const T *p, uint32_t i) {
+    const uint32_t byte = i * (uint32_t)sizeof(T);
+    return load_f(reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte), 0);
+}
+
+// Elements i and i+1 through a 32-bit byte offset, as one access.
+__device__ __forceinline__ float2 load_pair(const float *p, uint32_t i) {
+    const char *q = reinterpret_cast<const char *>(p) + i * 4u;
+    float2 r;
+    __builtin_memcpy(&r, __builtin_assume_aligned(q, 4), 8);
+    return r;
+}
+__device__ __forceinline__ float2 load_pair(const uint16_t *p, uint32_t i) {
+    const char *q = reinterpret_cast<const char *>(p) + i * 2u;
+    uint32_t u;
+    __builtin_memcpy(&u, __builtin_assume_aligned(q, 2), 4);
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+}
+
+// Elements i .. i+3 through a 32-bit byte offset, as one access.
+__device__ __forceinline__ float4 load_quad(const float *p, uint32_t i) {
+    const char *q = reinterpret_cast<const char *>(p) + i * 4u;
+    float4 r;
+    __builtin_memcpy(&r, __builtin_assume_aligned(q, 4), 16);
+    return r;
+}
+__device__ __forceinline__ float4 load_quad(const _Float16 *p, uint32_t i) {
+    const char *q = reinterpret_cast<const char *>(p) + i * 2u;
+    _Float16 h[4];
+    __builtin_memcpy(h, __builtin_assume_aligned(q, 2), 8);
+    return make_float4((float)h[0], (float)h[1], (float)h[2], (float)h[3]);
+}
+
 template <typename T> __device__ __forceinline__ void store_f(T *p, long i, float x);
 template <> __device__ __forceinline__ void store_f<float>(float *p, long i, float x) { p[i] = x; }
 template <> __device__ __forceinline__ void store_f<uint16_t>(uint16_t *p, long i, float x) { p[i] = f32_to_bf16(x); }
@@ -172,9 +207,109 @@ __global__ __launch_bounds__(256) void k_project(const VT *__restrict__ vt, PT *
     store_f(proj, ((long)vl * nv + b) * nu + a, acc * scale);
 }
 
+// Projector for the separable geometry (detector columns horizontal, rows
+// vertical).  All rays of one detector column share their major axis, their
+// ray parameter tau at every plane and their in-plane (x or y) sample
+// position; only the z coordinate depends on the row.  Each wave therefore
+// first tabulates, for its column, one entry per plane in LDS (the planes are
+// spread over the 64 lanes): the voxel offset of the in-plane tap pair, its
+// weight and tau.  The sampling loop then reads the entry (a broadcast LDS
+// read) and computes only z = s_z + tau * D_z(row) in FP64 and the bilinear
+// interpolation.
+struct PlaneEntry {
+    int off;     // offset of the (plane, in-plane tap, z = -2 pad) voxel in the padded copy
+    float wa;    // weight of the second in-plane tap
+    double tau;  // ray parameter at the plane
+};
+
+template <typename VT, typename PT>
+__global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vt, PT *__restrict__ proj,
+                                                     const ViewIdx *__restrict__ views,
+                                                     const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
+                                                     int nv, double h, int view0, int view_step, int tab_len) {
+    extern __shared__ PlaneEntry tab[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = blockIdx.x * 4 + w;
+    const int b = blockIdx.y * 64 + lane;
+    const int v = view0 + blockIdx.z * view_step;
+    PlaneEntry *T = tab + w * tab_len;
+    const int ac = min(a, nu - 1);  // waves past the last column build a table nobody reads
+    const ColD C = cols[(long)v * nu + ac];
+    const ViewIdx &V = views[v];
+    const int m = C.axis;
+    const double Dm = (m == 0) ? C.dx : C.dy, Da = (m == 0) ? C.dy : C.dx, rDm = (m == 0) ? C.rdx : C.rdy;
+    const double sm = V.s[m], sa = V.s[1 - m];
+    const int n_m = (m == 0) ? nx : ny, n_a = (m == 0) ? ny : nx;
+    const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+    const int Sm = (m == 0) ? PY * PZ : PZ;
+    const int Sa = (m == 0) ? PZ : PY * PZ;
+    // planes between source and detector whose in-plane sample can touch the grid
+    double lo = fmax(0.0, ceil(fmin(sm, sm + Dm)));
+    double hi = fmin((double)(n_m - 1), floor(fmax(sm, sm + Dm)));
+    const double Ba = Da * rDm;
+    clip_range(lo, hi, sa - sm * Ba, Ba, -1.5, n_a + 0.5);
+    if (!(fabs(Dm) > 0.0) || !isfinite(Ba)) hi = lo - 1.0;
+    const int l0 = (int)fmax(lo, 0.0), l1 = (int)fmin(hi, (double)(n_m - 1));
+    for (int base = l0; base <= l1; base += 64) {
+        const int l = base + lane;
+        if (l <= l1) {
+            const double tau = ((double)l - sm) * rDm;
+            const double fa = fma(tau, Da, sa) + kVolPad;
+            const double ga = floor(fa);
+            PlaneEntry e;
+            e.off = (l + kVolPad) * Sm + (int)ga * Sa;
+            e.wa = (float)(fa - ga);
+            e.tau = tau;
+            T[l] = e;
+        }
+    }
+    __syncthreads();
+    if (a >= nu || b >= nv) return;  // no barrier below
+
+    double D[3];
+    const double len = ray_setup(V, nu, nv, a, b, D);
+    const double Dz = D[2];
+    // planes whose z sample lies within the padded grid, for this row
+    const double Bz = Dz * rDm;
+    double zlo = (double)l0, zhi = (double)l1;
+    clip_range(zlo, zhi, V.s[2] - sm * Bz, Bz, -1.5, nz + 0.5);
+    const float scale = (float)(h * len / fabs(D[m]));
+    const double szp = V.s[2] + kVolPad;
+    float acc = 0.f;
+    if (zlo <= zhi && isfinite(Bz)) {
+        const int lz0 = (int)zlo, lz1 = (int)zhi;
+#pragma unroll 2
+        for (int l = lz0; l <= lz1; ++l) {
+            const PlaneEntry e = T[l];
+            const double fz = fma(e.tau, Dz, szp);
+            const double gz = floor(fz);
+            const float wz = (float)(fz - gz);
+            const uint32_t off = (uint32_t)(e.off + (int)gz);
+            const float2 r0 = load_pair(vt, off), r1 = load_pair(vt, off + Sa);
+            const float q0 = fmaf(wz, r0.y - r0.x, r0.x), q1 = fmaf(wz, r1.y - r1.x, r1.x);
+            acc += fmaf(e.wa, q1 - q0, q0);
+        }
+    }
+    store_f(proj, ((long)blockIdx.z * nv + b) * nu + a, acc * scale);
+}
+
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
                           int view_step, int nviews_sub, hipStream_t s) {
     dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
+    if (L.separable) {
+        const int tab_len = std::max(L.nx, L.ny);
+        const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
+#define MGCT_PROJS(VT, PT)                                                                                      \
+    k_project_sep<VT, PT><<<grid, 256, lds, s>>>((const VT *)vt, (PT *)proj, L.d_views, L.d_cols, L.nx, L.ny,    \
+                                                 L.nz, L.nu, L.nv, L.h, view0, view_step, tab_len)
+        if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F32) MGCT_PROJS(float, float);
+        else if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F16) MGCT_PROJS(float, _Float16);
+        else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F32) MGCT_PROJS(uint16_t, float);
+        else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F16) MGCT_PROJS(uint16_t, _Float16);
+        else return hipErrorInvalidValue;
+#undef MGCT_PROJS
+        return hipGetLastError();
+    }
     const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
     const long ars = L.axis_row_stride;
 #define MGCT_PROJ(VT, PT)                                                                                       \
@@ -300,14 +435,17 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
                 int bs = (int)ceil(-zk * rtz - hw);
                 bs = max(0, min(bs, nv - 4));
                 const float d0 = (float)fma(tz, (double)bs, zk);
-                const PT *p0 = col0 + bs;
+                const float4 r0 = load_quad(col0, (uint32_t)bs);
+                const float4 r1 = (NP > 1) ? load_quad(col1, (uint32_t)bs) : r0;
+                const float v0[4] = {r0.x, r0.y, r0.z, r0.w};
+                const float v1[4] = {r1.x, r1.y, r1.z, r1.w};
                 float s0 = 0.f, s1 = 0.f;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const float d = (t == 0) ? d0 : fmaf((float)t, tzf, d0);
                     const float w = fmaxf(0.f, 1.f - fabsf(d));
-                    s0 = fmaf(w, load_f(p0, t), s0);
-                    if (NP > 1) s1 = fmaf(w, load_f(col1, bs + t), s1);
+                    s0 = fmaf(w, v0[t], s0);
+                    if (NP > 1) s1 = fmaf(w, v1[t], s1);
                 }
                 pv[0][q] = fmaf(wp, s0, pv[0][q]);
                 if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);

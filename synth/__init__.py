@@ -15,4 +15,7 @@ from .phantom import (  # noqa: F401
     line_integrals,
     add_noise,
     make_dataset,
+    crop,
+    line_integrals_clipped,
+    crop_dataset,
 )

@@ -39,6 +39,9 @@ def _load():
         lib.synth_line_integrals.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, dp, ctypes.c_int, dp, dp]
         lib.synth_line_integrals.restype = None
+        lib.synth_line_integrals_clipped.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                                     ctypes.c_int, dp, ctypes.c_int, dp, dp, dp]
+        lib.synth_line_integrals_clipped.restype = None
         lib.synth_voxelize.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
                                        ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp]
         lib.synth_voxelize.restype = None
@@ -131,6 +134,53 @@ def line_integrals(ph: Phantom, views: np.ndarray, nu: int, nv: int) -> np.ndarr
         b = np.zeros((1, 7))
     _load().synth_line_integrals(V, _ptr(views), nu, nv, ne, _ptr(e), nb, _ptr(b), _ptr(out))
     return out
+
+
+def crop(ph: Phantom, lo, hi) -> Phantom:
+    """Shapes whose bounding box meets the box [lo, hi] (the others cannot
+    contribute to anything inside it)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    e = ph.ellipsoids
+    r = e[:, 12:15].max(axis=1, keepdims=True)
+    keep_e = np.all((e[:, 0:3] + r >= lo) & (e[:, 0:3] - r <= hi), axis=1)
+    b = ph.boxes
+    keep_b = np.all((b[:, 3:6] >= lo) & (b[:, 0:3] <= hi), axis=1) if b.shape[0] else np.zeros(0, bool)
+    return Phantom(np.ascontiguousarray(e[keep_e]), np.ascontiguousarray(b[keep_b]))
+
+
+def line_integrals_clipped(ph: Phantom, views: np.ndarray, nu: int, nv: int, lo, hi) -> np.ndarray:
+    """Exact line integrals of the phantom intersected with the box [lo, hi]."""
+    ph = crop(ph, lo, hi)
+    views = np.ascontiguousarray(views, dtype=np.float64)
+    V = views.shape[0]
+    out = np.zeros((V, nv, nu))
+    e = np.ascontiguousarray(ph.ellipsoids, dtype=np.float64).reshape(-1, 16)
+    b = np.ascontiguousarray(ph.boxes, dtype=np.float64).reshape(-1, 7)
+    ne, nb = e.shape[0], b.shape[0]
+    if ne == 0:
+        e = np.zeros((1, 16))
+    if nb == 0:
+        b = np.zeros((1, 7))
+    clip = np.ascontiguousarray(np.concatenate([np.asarray(lo, float), np.asarray(hi, float)]))
+    _load().synth_line_integrals_clipped(V, _ptr(views), nu, nv, ne, _ptr(e), nb, _ptr(b), _ptr(clip), _ptr(out))
+    return out
+
+
+def crop_dataset(name: str = "c2", n: int = 64, nu: int = 96, levels: int = 4):
+    """The central n^3 fine-voxel box of a workload's phantom, seen through a
+    nu x nu detector of the workload's pixel size with all of its views.
+    Returns dict(views, h, n, nu, mu, b, b_true)."""
+    cfg = CONFIGS[name]
+    idx = int(name[1:])
+    views = trajectory(cfg.n_views, cfg.z_levels, cfg.pixel)
+    ph = random_phantom(cfg, 1000 + idx)
+    half = 0.5 * n * cfg.h
+    lo, hi = (-half,) * 3, (half,) * 3
+    b_true = line_integrals_clipped(ph, views, nu, nu, lo, hi)
+    b = add_noise(b_true, cfg, 3000 + idx)
+    mu = voxelize(crop(ph, lo, hi), n, cfg.h, ss=4)
+    return dict(views=views, h=cfg.h, n=n, nu=nu, mu=mu, b=b, b_true=b_true, levels=levels)
 
 
 def add_noise(b_true: np.ndarray, cfg: ScanConfig, seed: int) -> np.ndarray:

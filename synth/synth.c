@@ -64,6 +64,96 @@ static double box_chord(const double *b, const double s[3], const double D[3])
     return (t1 - t0) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
 }
 
+/* Parameter interval [t0, t1] of the segment inside an axis-aligned box. */
+static void box_interval(const double *lo, const double *hi, const double s[3], const double D[3],
+                         double *t0, double *t1)
+{
+    double a = 0.0, b = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (D[k] == 0.0) {
+            if (s[k] < lo[k] || s[k] > hi[k]) { a = 1.0; b = 0.0; }
+            continue;
+        }
+        double ta = (lo[k] - s[k]) / D[k], tb = (hi[k] - s[k]) / D[k];
+        if (ta > tb) { double t = ta; ta = tb; tb = t; }
+        if (ta > a) a = ta;
+        if (tb < b) b = tb;
+    }
+    *t0 = a;
+    *t1 = b;
+}
+
+/* Like ellipsoid_chord, restricted to t in [c0, c1]. */
+static double ellipsoid_chord_clipped(const double *e, const double s[3], const double D[3], double c0, double c1)
+{
+    const double *c = e, *R = e + 3, *ax = e + 12;
+    double sp[3], dp[3];
+    for (int k = 0; k < 3; ++k) {
+        double ps = 0.0, pd = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            ps += R[r * 3 + k] * (s[r] - c[r]);
+            pd += R[r * 3 + k] * D[r];
+        }
+        sp[k] = ps / ax[k];
+        dp[k] = pd / ax[k];
+    }
+    double A = dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2];
+    double B = 2.0 * (sp[0] * dp[0] + sp[1] * dp[1] + sp[2] * dp[2]);
+    double C = sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2] - 1.0;
+    double disc = B * B - 4.0 * A * C;
+    if (disc <= 0.0 || A <= 0.0) return 0.0;
+    double r = sqrt(disc);
+    double t0 = (-B - r) / (2.0 * A), t1 = (-B + r) / (2.0 * A);
+    if (t0 < c0) t0 = c0;
+    if (t1 > c1) t1 = c1;
+    if (t1 <= t0) return 0.0;
+    return (t1 - t0) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+}
+
+/*
+ * Line integrals of the phantom restricted to the box [clip[0..2], clip[3..5]]
+ * (every shape intersected with the box).
+ */
+void synth_line_integrals_clipped(int n_views, const double *views, int nu, int nv,
+                                  int n_ell, const double *ell, int n_box, const double *box,
+                                  const double *clip, double *out)
+{
+    long total = (long)n_views * nv * nu;
+#pragma omp parallel for schedule(static)
+    for (long r = 0; r < total; ++r) {
+        int a = (int)(r % nu);
+        int b = (int)((r / nu) % nv);
+        int v = (int)(r / ((long)nu * nv));
+        const double *g = views + (size_t)v * 12;
+        double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
+        double D[3];
+        for (int k = 0; k < 3; ++k) D[k] = g[3 + k] + ca * g[6 + k] + cb * g[9 + k] - g[k];
+        double c0, c1;
+        box_interval(clip, clip + 3, g, D, &c0, &c1);
+        double acc = 0.0;
+        if (c1 > c0) {
+            for (int e = 0; e < n_ell; ++e) {
+                const double *E = ell + (size_t)e * ELL_STRIDE;
+                double ch = ellipsoid_chord_clipped(E, g, D, c0, c1);
+                if (ch > 0.0) acc += E[15] * ch;
+            }
+            for (int e = 0; e < n_box; ++e) {
+                const double *Bx = box + (size_t)e * BOX_STRIDE;
+                double lo[3], hi[3];
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = Bx[k] > clip[k] ? Bx[k] : clip[k];
+                    hi[k] = Bx[3 + k] < clip[3 + k] ? Bx[3 + k] : clip[3 + k];
+                }
+                if (lo[0] >= hi[0] || lo[1] >= hi[1] || lo[2] >= hi[2]) continue;
+                double t0, t1;
+                box_interval(lo, hi, g, D, &t0, &t1);
+                if (t1 > t0) acc += Bx[6] * (t1 - t0) * sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+            }
+        }
+        out[r] = acc;
+    }
+}
+
 /* out[v][b][a] = sum_k kappa_k * chord_k(ray(v,a,b)). */
 void synth_line_integrals(int n_views, const double *views, int nu, int nv,
                           int n_ell, const double *ell, int n_box, const double *box,
