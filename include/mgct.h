@@ -170,6 +170,31 @@ int mgct_estimate_step(void *ctx, int level, const mgct_filter *f, int iters, ui
 int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_dtype, double alpha,
                         const mgct_filter *f, double *resid_norm, hipStream_t stream);
 
+/*
+ * Geometry derivative for joint model estimation (paper Sec. 1: geometry
+ * such as thermal drift estimated jointly with the image): with the volume
+ * vol (device F32, grid `level`) and a cotangent stack cot (device F32,
+ * e.g. the residual A vol - b for the gradient of 0.5 ||A vol - b||^2),
+ * dviews (host, n_views x 12 doubles, written) receives
+ * d/d(view) sum_rays cot * (A vol) for each view's s, d, u, v (physical
+ * units), differentiating the Joseph sums with their major axes and plane
+ * sets held fixed (the sum is piecewise smooth).  Synchronises the stream.
+ */
+int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *cot, double *dviews,
+                           hipStream_t stream);
+
+/*
+ * Chain rule from per-view gradients (dviews, n_views x 12, host) to the
+ * three parameters of a rigid misalignment of every view of views0 (host,
+ * n_views x 12, the unperturbed table): dx and dz move the source by
+ * dx*voxel along the view's unit column direction and dz*voxel along z; the
+ * detector's column and row steps rotate by tilt_deg (degrees) about its
+ * normal.  grad (host, 3) = d/d(dx, dz, tilt_deg) at (dx, dz, tilt_deg).
+ * Host-only arithmetic.
+ */
+int mgct_geometry_param_grad(int n_views, const double *views0, const double *dviews, double voxel, double dx,
+                             double dz, double tilt_deg, double grad[3]);
+
 /* Restrict (Algorithm 1): coarse = 2x2x2 block mean of fine (grid level -> level+1). */
 int mgct_restrict_volume(void *ctx, int level, const float *fine, float *coarse, hipStream_t stream);
 

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "Geom", "build", "project", "backproject", "project_rays", "backproject_voxels",
-    "weight", "dense_matrix", "major_axis", "num_threads",
+    "weight", "dense_matrix", "major_axis", "num_threads", "project_geom_grad",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +56,8 @@ def _load():
         lib.oracle_weight.restype = cd
         lib.oracle_dense_matrix.argtypes = geo + [ci, D, D]
         lib.oracle_dense_matrix.restype = None
+        lib.oracle_project_geom_grad.argtypes = geo + [ci, D, D, D, D]
+        lib.oracle_project_geom_grad.restype = None
         lib.oracle_major_axis.argtypes = [D]
         lib.oracle_major_axis.restype = ci
         lib.oracle_num_threads.argtypes = []
@@ -177,6 +179,17 @@ def dense_matrix(geom: Geom) -> np.ndarray:
     W = np.zeros((geom.n_views * geom.nv * geom.nu, geom.nx * geom.ny * geom.nz))
     _load().oracle_dense_matrix(*geom._args(), geom.n_views, _dp(geom.views), _dp(W))
     return W
+
+
+def project_geom_grad(geom: Geom, vol: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """d/d(views) of sum(g * A(views) vol): (V, 12) in the order s, d, u, v
+    (analytic derivative of the Joseph sums, major axes and plane sets held
+    fixed)."""
+    vol = np.ascontiguousarray(vol, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros((geom.n_views, 12))
+    _load().oracle_project_geom_grad(*geom._args(), geom.n_views, _dp(geom.views), _dp(vol), _dp(g), _dp(out))
+    return out
 
 
 def major_axis(D) -> int:

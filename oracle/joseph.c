@@ -305,6 +305,99 @@ void oracle_backproject_voxels(int nx, int ny, int nz, double h, const double *o
     }
 }
 
+/*
+ * Gradient of sum_rays g[ray] * (A vol)[ray] with respect to each view's 12
+ * geometry values (s, d, u, v), from the derivative of the Joseph sum above
+ * (the major axis and the set of planes are held fixed: the sum is
+ * piecewise smooth).  For a sample on plane X of axis m, with D = q - s,
+ * t = (X - s_m)/D_m and p = s + t D:
+ *   dp_k/ds_k = 1 - t, dp_k/dq_k = t             (k in-plane)
+ *   dp_k/ds_m = D_k (t - 1)/D_m, dp_k/dq_m = -D_k t / D_m
+ * and the bilinear sample f has df/dp_k = (difference of the two taps along
+ * k, interpolated along the other in-plane axis) / h.  The ray is
+ * L * sum f with L = h |D| / |D_m|.  Pixel centre q = d + ca u + cb v, so
+ * dq/dd = I, dq/du = ca I, dq/dv = cb I.  dviews[v*12 + ...] is overwritten.
+ */
+void oracle_project_geom_grad(int nx, int ny, int nz, double h, const double *origin,
+                              int nu, int nv, int n_views, const double *views,
+                              const double *vol, const double *g, double *dviews)
+{
+    vgeom G;
+    make_vgeom(&G, nx, ny, nz, h, origin);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < n_views; ++v) {
+        const double *view = views + (size_t)v * 12;
+        const double *s = view;
+        double acc[12] = {0};
+        for (int b = 0; b < nv; ++b)
+            for (int a = 0; a < nu; ++a) {
+                double gr = g[((size_t)v * nv + b) * nu + a];
+                if (gr == 0.0) continue;
+                double q[3], D[3];
+                ray_of(view, nu, nv, a, b, q, D);
+                int m = oracle_major_axis(D);
+                int ax[2] = {(m == 0) ? 1 : 0, (m == 2) ? 1 : 2};
+                double len = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+                double L = h * len / fabs(D[m]);
+                double sum = 0.0, ds[3] = {0, 0, 0}, dq[3] = {0, 0, 0};
+                for (int l = 0; l < G.n[m]; ++l) {
+                    double X = voxel_centre(&G, m, l);
+                    double t = (X - s[m]) / D[m];
+                    if (t < 0.0 || t > 1.0) continue;
+                    double f[2];
+                    int j[2];
+                    for (int c = 0; c < 2; ++c) {
+                        double p = s[ax[c]] + t * D[ax[c]];
+                        f[c] = (p - G.o[ax[c]]) / h + 0.5 * (G.n[ax[c]] - 1);
+                    }
+                    if (!(f[0] > -1.0 && f[0] < G.n[ax[0]] && f[1] > -1.0 && f[1] < G.n[ax[1]])) continue;
+                    j[0] = (int)floor(f[0]);
+                    j[1] = (int)floor(f[1]);
+                    double val[2][2];
+                    for (int i0 = 0; i0 < 2; ++i0)
+                        for (int i1 = 0; i1 < 2; ++i1) {
+                            int ia = j[0] + i0, ib = j[1] + i1;
+                            double x = 0.0;
+                            if (ia >= 0 && ia < G.n[ax[0]] && ib >= 0 && ib < G.n[ax[1]]) {
+                                int idx[3];
+                                idx[m] = l; idx[ax[0]] = ia; idx[ax[1]] = ib;
+                                x = vol[((size_t)idx[2] * G.n[1] + idx[1]) * G.n[0] + idx[0]];
+                            }
+                            val[i0][i1] = x;
+                        }
+                    double w0 = f[0] - j[0], w1 = f[1] - j[1];
+                    sum += (1 - w0) * (1 - w1) * val[0][0] + w0 * (1 - w1) * val[1][0] +
+                           (1 - w0) * w1 * val[0][1] + w0 * w1 * val[1][1];
+                    /* df/dp along each in-plane axis */
+                    double dfd[2];
+                    dfd[0] = ((1 - w1) * (val[1][0] - val[0][0]) + w1 * (val[1][1] - val[0][1])) / h;
+                    dfd[1] = ((1 - w0) * (val[0][1] - val[0][0]) + w0 * (val[1][1] - val[1][0])) / h;
+                    for (int c = 0; c < 2; ++c) {
+                        int k = ax[c];
+                        ds[k] += dfd[c] * (1.0 - t);
+                        dq[k] += dfd[c] * t;
+                        ds[m] += dfd[c] * D[k] * (t - 1.0) / D[m];
+                        dq[m] += dfd[c] * (-D[k] * t / D[m]);
+                    }
+                }
+                /* dL/dD */
+                double dL[3];
+                for (int k = 0; k < 3; ++k) dL[k] = h * D[k] / (len * fabs(D[m]));
+                dL[m] -= h * len / (D[m] * fabs(D[m]));
+                double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
+                for (int k = 0; k < 3; ++k) {
+                    double dys = L * ds[k] - dL[k] * sum;
+                    double dyq = L * dq[k] + dL[k] * sum;
+                    acc[k] += gr * dys;
+                    acc[3 + k] += gr * dyq;
+                    acc[6 + k] += gr * ca * dyq;
+                    acc[9 + k] += gr * cb * dyq;
+                }
+            }
+        for (int k = 0; k < 12; ++k) dviews[(size_t)v * 12 + k] = acc[k];
+    }
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -18,6 +18,7 @@ __all__ = [
     "precondition", "restrict_volume", "restrict_stack", "prolongate", "soft_threshold",
     "bilateral", "splitmix64_uniform", "power_iteration", "landweber_step", "osemtr",
     "multigrid", "filter_identity", "filter_stencil27", "filter_radial",
+    "perturbation_jacobian", "geometry_param_grad",
 ]
 
 
@@ -310,3 +311,36 @@ def multigrid(geom: Geom, mu: np.ndarray, b: np.ndarray, levels: int, n_outer: i
     for n in range(n_outer):
         x = mg(x, 0, n)
     return x, hist
+
+
+# ---------------------------------------------------------------------------
+# Joint geometry estimation (paper Sec. 1: model parameters such as drift
+# estimated jointly with the image)
+# ---------------------------------------------------------------------------
+
+def perturbation_jacobian(views0: np.ndarray, h: float, dx: float, dz: float, tilt_deg: float) -> np.ndarray:
+    """d(views)/d(dx, dz, tilt) for the perturbation model: the source moves
+    by dx*h along the view's unit column direction and dz*h along z; the
+    column and row steps rotate by tilt (degrees) about the detector normal,
+    keeping their lengths.  Returns (V, 12, 3)."""
+    V = views0.shape[0]
+    J = np.zeros((V, 12, 3))
+    u0, v0 = views0[:, 6:9], views0[:, 9:12]
+    lu = np.linalg.norm(u0, axis=1, keepdims=True)
+    lv = np.linalg.norm(v0, axis=1, keepdims=True)
+    uh, vh = u0 / lu, v0 / lv
+    J[:, 0:3, 0] = h * uh
+    J[:, 2, 1] = h
+    t = math.radians(tilt_deg)
+    c, s = math.cos(t), math.sin(t)
+    k = math.pi / 180.0
+    J[:, 6:9, 2] = k * lu * (-s * uh + c * vh)
+    J[:, 9:12, 2] = k * lv * (-c * uh - s * vh)
+    return J
+
+
+def geometry_param_grad(views0, dviews, h, dx, dz, tilt_deg) -> np.ndarray:
+    """Chain rule: gradient with respect to (dx, dz, tilt) from the per-view
+    gradient with respect to (s, d, u, v)."""
+    J = perturbation_jacobian(np.asarray(views0, dtype=np.float64), h, dx, dz, tilt_deg)
+    return np.einsum("vk,vkp->p", np.asarray(dviews, dtype=np.float64), J)

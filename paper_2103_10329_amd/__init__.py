@@ -82,6 +82,8 @@ SIGNATURES = {
     "mgct_osemtr": (_ci, [_vp, _ci, _vp, _vp, _ci, _ci, _vp]),
     "mgct_multigrid_solve": (_ci, [_vp, _vp, _vp, _ci, ctypes.POINTER(mgct_mg_params), _dp, _vp]),
     "mgct_set_precision": (_ci, [_vp, _ci, _ci]),
+    "mgct_project_geom_grad": (_ci, [_vp, _ci, _vp, _vp, _dp, _vp]),
+    "mgct_geometry_param_grad": (_ci, [_ci, _dp, _dp, _cd, _cd, _cd, _cd, _dp]),
     "mgct_kernel_timing": (_ci, [_vp, _ci]),
     "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
 }
@@ -300,6 +302,14 @@ class Context:
         check(mgct_osemtr(self.handle, level, _ptr(vol), _ptr(b), subsets, passes, _stream()),  # noqa: F821
               "mgct_osemtr")
 
+    def project_geom_grad(self, vol, cot, level: int = 0) -> np.ndarray:
+        """d/d(views) of sum(cot * A vol): (n_views, 12) float64 (s, d, u, v)."""
+        out = np.zeros((self.geom["n_views"], 12))
+        check(mgct_project_geom_grad(self.handle, level, _ptr(vol), _ptr(cot),  # noqa: F821
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+              "mgct_project_geom_grad")
+        return out
+
     def kernel_timing(self, enable: bool):
         check(mgct_kernel_timing(self.handle, 1 if enable else 0), "mgct_kernel_timing")  # noqa: F821
 
@@ -333,3 +343,16 @@ class Context:
         check(mgct_multigrid_solve(self.handle, _ptr(vol), _ptr(b), _dtype_code(b), ctypes.byref(p), hp,  # noqa: F821
                                    _stream()), "mgct_multigrid_solve")
         return hist[: n_outer * levels].reshape(n_outer, levels) if want_hist else None
+
+
+def geometry_param_grad(views0, dviews, voxel, dx, dz, tilt_deg) -> np.ndarray:
+    """d/d(dx, dz, tilt_deg) from per-view gradients (see mgct.h)."""
+    load_library()
+    v0 = np.ascontiguousarray(np.asarray(views0, dtype=np.float64).reshape(-1, 12))
+    dv = np.ascontiguousarray(np.asarray(dviews, dtype=np.float64).reshape(-1, 12))
+    out = np.zeros(3)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(mgct_geometry_param_grad(v0.shape[0], v0.ctypes.data_as(dp), dv.ctypes.data_as(dp), float(voxel),  # noqa: F821
+                                   float(dx), float(dz), float(tilt_deg), out.ctypes.data_as(dp)),
+          "mgct_geometry_param_grad")
+    return out

@@ -122,7 +122,7 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
 
 int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, void *vol, int vol_dtype, int view0,
                    int step, int nsub, hipStream_t s, int pt_dtype = -1) {
-    if (!L.separable) return MGCT_ERR_NOT_IMPLEMENTED;
+    if (!L.separable && vol_dtype != MGCT_F32) return MGCT_ERR_NOT_IMPLEMENTED;
     // the scaled, transposed data copy: F16 when the input is F16 or when asked
     if (pt_dtype < 0 || proj_dtype == MGCT_F16) pt_dtype = proj_dtype;
     const size_t es = pt_dtype == MGCT_F32 ? 4 : 2;
@@ -131,14 +131,17 @@ int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, vo
         KernelTimer t(c, MGCT_OP_DATA_PRESCALE, g, s);
         HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, pt_dtype, L, view0, step, nsub, s));
     }
-    const size_t sb = backproject_scratch_bytes(L, nsub, 1);
+    const size_t sb = L.separable ? backproject_scratch_bytes(L, nsub, 1) : backproject_gen_scratch_bytes(L, nsub);
     float *scratch = nullptr;
     if (sb) {
         scratch = static_cast<float *>(workspace(c, lvl("bp_scratch", g), sb, false));
         if (!scratch) return MGCT_ERR_OOM;
     }
     KernelTimer t(c, MGCT_OP_BACKPROJECT, g, s);
-    HIPCHK(launch_backproject(pt, pt_dtype, vol, vol_dtype, scratch, L, view0, step, nsub, s));
+    if (L.separable)
+        HIPCHK(launch_backproject(pt, pt_dtype, vol, vol_dtype, scratch, L, view0, step, nsub, s));
+    else
+        HIPCHK(launch_backproject_gen(pt, pt_dtype, (float *)vol, scratch, L, view0, step, nsub, s));
     return MGCT_OK;
 }
 
@@ -250,13 +253,24 @@ int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int pa
             HIPCHK(launch_emtr_terms(l, b, pi, nsrc, dsrc, L, m, M, nsub, s));
             HIPCHK(launch_scale_transpose_stack(nsrc, MGCT_F32, pt0, MGCT_F32, L, m, M, nsub, s));
             HIPCHK(launch_scale_transpose_stack(dsrc, MGCT_F32, pt1, MGCT_F32, L, m, M, nsub, s));
-            const size_t sb = backproject_scratch_bytes(L, nsub, 2);
-            float *scratch = nullptr;
-            if (sb) {
-                scratch = static_cast<float *>(workspace(c, lvl("bp_scratch2", g), sb, false));
-                if (!scratch) return MGCT_ERR_OOM;
+            if (L.separable) {
+                const size_t sb = backproject_scratch_bytes(L, nsub, 2);
+                float *scratch = nullptr;
+                if (sb) {
+                    scratch = static_cast<float *>(workspace(c, lvl("bp_scratch2", g), sb, false));
+                    if (!scratch) return MGCT_ERR_OOM;
+                }
+                HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s));
+            } else {
+                const size_t sb = backproject_gen_scratch_bytes(L, nsub);
+                float *scratch = nullptr;
+                if (sb) {
+                    scratch = static_cast<float *>(workspace(c, lvl("bp_scratch", g), sb, false));
+                    if (!scratch) return MGCT_ERR_OOM;
+                }
+                HIPCHK(launch_backproject_gen(pt0, MGCT_F32, num, scratch, L, m, M, nsub, s));
+                HIPCHK(launch_backproject_gen(pt1, MGCT_F32, den, scratch, L, m, M, nsub, s));
             }
-            HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s));
             HIPCHK(launch_max_reset(mx, s));
             HIPCHK(launch_max_reduce(den, n, mx, s));
             HIPCHK(launch_emtr_update(vol, num, den, n, mx, s));
@@ -498,6 +512,47 @@ int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_d
     return MGCT_OK;
 }
 
+int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *cot, double *dviews, hipStream_t s) {
+    if (!ctx || !vol || !cot || !dviews) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *Lp;
+    MGCHK(get_level(c, level, &Lp));
+    Level &L = *Lp;
+    void *vt = workspace(c, lvl("vt32", level), L.padded_vox() * 4, true);
+    if (!vt) return MGCT_ERR_OOM;
+    WS(partial, double, lvl("gg_partial", level), geom_grad_partial_bytes(L), false);
+    WS(dv, double, lvl("gg_dviews", level), (size_t)L.nviews * 12 * 8, false);
+    HIPCHK(launch_transpose_volume(vol, MGCT_F32, vt, MGCT_F32, L, s));
+    HIPCHK(launch_geom_grad(vt, MGCT_F32, cot, partial, dv, L, s));
+    HIPCHK(hipMemcpyAsync(dviews, dv, (size_t)L.nviews * 12 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MGCT_OK;
+}
+
+int mgct_geometry_param_grad(int n_views, const double *views0, const double *dviews, double voxel, double dx,
+                             double dz, double tilt_deg, double grad[3]) {
+    if (n_views < 1 || !views0 || !dviews || !grad || !(voxel > 0.0)) return MGCT_ERR_INVALID_ARG;
+    const double t = tilt_deg * M_PI / 180.0, ct = cos(t), st = sin(t), k = M_PI / 180.0;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int v = 0; v < n_views; ++v) {
+        const double *w = views0 + (size_t)v * 12, *d = dviews + (size_t)v * 12;
+        double lu = sqrt(w[6] * w[6] + w[7] * w[7] + w[8] * w[8]);
+        double lv = sqrt(w[9] * w[9] + w[10] * w[10] + w[11] * w[11]);
+        double uh[3] = {w[6] / lu, w[7] / lu, w[8] / lu}, vh[3] = {w[9] / lv, w[10] / lv, w[11] / lv};
+        for (int e = 0; e < 3; ++e) {
+            g0 += d[e] * voxel * uh[e];                                 // source along the unit column direction
+            g2 += d[6 + e] * k * lu * (-st * uh[e] + ct * vh[e]);       // column step rotates
+            g2 += d[9 + e] * k * lv * (-ct * uh[e] - st * vh[e]);       // row step rotates
+        }
+        g1 += d[2] * voxel;                                             // source along z
+    }
+    grad[0] = g0;
+    grad[1] = g1;
+    grad[2] = g2;
+    return MGCT_OK;
+}
+
 int mgct_restrict_volume(void *ctx, int level, const float *fine, float *coarse, hipStream_t s) {
     if (!ctx || !fine || !coarse) return MGCT_ERR_INVALID_ARG;
     Ctx &c = *as_ctx(ctx);
@@ -559,7 +614,6 @@ int mgct_osemtr(void *ctx, int level, float *vol, const float *b, int subsets, i
     HIPCHK(hipSetDevice(c.device));
     Level *L;
     MGCHK(get_level(c, level, &L));
-    if (!L->separable) return MGCT_ERR_NOT_IMPLEMENTED;
     return do_osemtr(c, *L, level, vol, b, subsets, passes, s);
 }
 
@@ -574,8 +628,6 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
     const int NL = p->levels;
     std::vector<Level *> Ls(NL);
     for (int g = 0; g < NL; ++g) MGCHK(get_level(c, g, &Ls[g]));
-    for (int g = 0; g < NL; ++g)
-        if (!Ls[g]->separable) return MGCT_ERR_NOT_IMPLEMENTED;
     const int nland = NL == 1 ? 1 : NL - 1;  // grids with a Landweber step
     for (int g = 0; g < nland; ++g) MGCHK(check_filter(&p->filter, *Ls[g]));
 

@@ -615,3 +615,276 @@ hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, 
 }
 
 }  // namespace mgct
+
+namespace mgct {
+
+// ------------------------------------------------- geometry derivative --
+//
+// d/d(view parameters) of sum over rays of g[ray] * (A vol)[ray], for the
+// 12 values (s, d, u, v) of every view.  Same ray walk as k_project (major
+// axis and plane set held fixed, the sum being piecewise smooth).  With
+// D = q - s and t = (plane - s_m)/D_m, a sample's in-plane coordinates are
+// p_k = s_k + t D_k, so dp_k/ds_k = 1 - t, dp_k/dq_k = t,
+// dp_k/ds_m = D_k (t - 1)/D_m and dp_k/dq_m = -D_k t/D_m; the bilinear
+// sample's derivative along each in-plane axis is the tap difference
+// interpolated along the other axis.  The ray value is L * sum with
+// L = h|D|/|D_m|.  Pixel centre q = d + ca u + cb v.
+// Each block reduces its rays' 12-vectors in FP64 into one partial per block;
+// k_geom_grad_sum then adds a view's partials in a fixed order.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_geom_grad(const VT *__restrict__ vt, const float *__restrict__ cot,
+                                                   const ViewIdx *__restrict__ views,
+                                                   const uint8_t *__restrict__ axis, long axis_view_stride,
+                                                   long axis_row_stride, int nx, int ny, int nz, int nu, int nv,
+                                                   double h, double *__restrict__ partial) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = blockIdx.x * 4 + w;
+    const int b = blockIdx.y * 64 + lane;
+    const int v = blockIdx.z;
+    double out[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = 0.0;
+    const float gr = (a < nu && b < nv) ? cot[((long)v * nv + b) * nu + a] : 0.f;
+    if (gr != 0.f) {
+        const ViewIdx &V = views[v];
+        double D[3];
+        const double len = ray_setup(V, nu, nv, a, b, D);
+        const int m = axis[v * axis_view_stride + b * axis_row_stride + a];
+        const int ia = (m == 0) ? 1 : 0;
+        const double Dm = D[m], Da = D[ia], Dz = D[2];
+        const double sm = V.s[m], sa = V.s[ia], sz = V.s[2];
+        const double Ba = Da / Dm, Bz = Dz / Dm;
+        const double Aa = sa - sm * Ba, Az = sz - sm * Bz;
+        const int n_m = (m == 0) ? nx : ny, n_a = (m == 0) ? ny : nx;
+        double lo = fmax(0.0, ceil(fmin(sm, sm + Dm)));
+        double hi = fmin((double)(n_m - 1), floor(fmax(sm, sm + Dm)));
+        clip_range(lo, hi, Aa, Ba, -1.5, n_a + 0.5);
+        clip_range(lo, hi, Az, Bz, -1.5, nz + 0.5);
+        if (!(fabs(Dm) > 0.0) || !isfinite(Ba) || !isfinite(Bz)) hi = lo - 1.0;
+        // sums over samples: value, and per in-plane axis c the derivative
+        // (index units) and its t-weighted sum
+        double S = 0.0, Ga = 0.0, Gat = 0.0, Gz = 0.0, Gzt = 0.0;
+        if (lo <= hi) {
+            const int l0 = (int)lo, l1 = (int)hi;
+            const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+            const int Sm = (m == 0) ? PY * PZ : PZ;
+            const int Sa = (m == 0) ? PZ : PY * PZ;
+            const double Aap = Aa + kVolPad, Azp = Az + kVolPad;
+            for (int l = l0; l <= l1; ++l) {
+                const double fa = fma((double)l, Ba, Aap), fz = fma((double)l, Bz, Azp);
+                const double ga = floor(fa), gz = floor(fz);
+                const float wa = (float)(fa - ga), wz = (float)(fz - gz);
+                const uint32_t off = (uint32_t)((l + kVolPad) * Sm + (int)ga * Sa + (int)gz);
+                const float2 r0 = load_pair(vt, off), r1 = load_pair(vt, off + Sa);
+                const float q0 = fmaf(wz, r0.y - r0.x, r0.x), q1 = fmaf(wz, r1.y - r1.x, r1.x);
+                const float f = fmaf(wa, q1 - q0, q0);
+                const float dfa = q1 - q0;
+                const float dfz = fmaf(wa, (r1.y - r1.x) - (r0.y - r0.x), r0.y - r0.x);
+                const double t = ((double)l - sm) / Dm;
+                S += (double)f;
+                Ga += (double)dfa;
+                Gat += t * (double)dfa;
+                Gz += (double)dfz;
+                Gzt += t * (double)dfz;
+            }
+        }
+        // to physical units: positions scale by h, derivatives per index unit by 1/h
+        const double L = h * len / fabs(Dm);
+        double ds[3] = {0, 0, 0}, dq[3] = {0, 0, 0};
+        ds[ia] = (Ga - Gat) / h;
+        dq[ia] = Gat / h;
+        ds[2] = (Gz - Gzt) / h;
+        dq[2] = Gzt / h;
+        ds[m] = ((Gat - Ga) * Da + (Gzt - Gz) * Dz) / (Dm * h);
+        dq[m] = -(Gat * Da + Gzt * Dz) / (Dm * h);
+        double dL[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dL[k] = D[k] / (len * fabs(Dm));
+        dL[m] -= len / (Dm * fabs(Dm));
+        const double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
+        const double gd = (double)gr;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double dys = L * ds[k] - dL[k] * S;
+            const double dyq = L * dq[k] + dL[k] * S;
+            out[k] = gd * dys;
+            out[3 + k] = gd * dyq;
+            out[6 + k] = gd * ca * dyq;
+            out[9 + k] = gd * cb * dyq;
+        }
+    }
+    // block reduction of the 12 sums (fixed order)
+    __shared__ double red[12][256];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = out[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) {
+        const long bpv = (long)gridDim.x * gridDim.y;
+        const long blk = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        partial[((long)v * bpv + blk) * 12 + threadIdx.x] = red[threadIdx.x][0];
+    }
+}
+
+__global__ void k_geom_grad_sum(const double *__restrict__ partial, long bpv, double *__restrict__ dviews) {
+    const int v = blockIdx.x;
+    if (threadIdx.x < 12) {
+        double acc = 0.0;
+        for (long i = 0; i < bpv; ++i) acc += partial[((long)v * bpv + i) * 12 + threadIdx.x];
+        dviews[(long)v * 12 + threadIdx.x] = acc;
+    }
+}
+
+size_t geom_grad_partial_bytes(const Level &L) {
+    const long bpv = (long)((L.nu + 3) / 4) * ((L.nv + 63) / 64);
+    return (size_t)L.nviews * bpv * 12 * sizeof(double);
+}
+
+hipError_t launch_geom_grad(const void *vt, int vt_dtype, const float *cot, double *partial, double *dviews,
+                            const Level &L, hipStream_t s) {
+    dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, L.nviews);
+    const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
+    if (vt_dtype == MGCT_F32)
+        k_geom_grad<float><<<grid, 256, 0, s>>>((const float *)vt, cot, L.d_views, L.d_axis, avs, L.axis_row_stride,
+                                                L.nx, L.ny, L.nz, L.nu, L.nv, L.h, partial);
+    else
+        return hipErrorInvalidValue;
+    const long bpv = (long)grid.x * grid.y;
+    k_geom_grad_sum<<<L.nviews, 64, 0, s>>>(partial, bpv, dviews);
+    return hipGetLastError();
+}
+
+// ---------------------------------------- general-geometry back-projector --
+//
+// Any detector orientation (no z-major rays).  For each voxel and view, the
+// rays whose Joseph samples can touch the voxel pass through the cube of
+// half-width one voxel around it; the bounding box of the cube's eight
+// corners projected on the detector (plus one pixel) gives the candidate
+// pixels.  Each candidate's weight is recomputed exactly as the projector
+// forms it: its major axis from the per-ray table, the sample on the
+// voxel's own plane of that axis, and the two hat functions.  One lane per
+// voxel, lanes along z; per-view partial sums in FP32, summed in FP64.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_backproject_gen(const PT *__restrict__ pt, float *__restrict__ vol,
+                                                         float *__restrict__ part, const ViewIdx *__restrict__ views,
+                                                         const uint8_t *__restrict__ axis, long axis_view_stride,
+                                                         long axis_row_stride, int nx, int ny, int nz, int nu, int nv,
+                                                         int nviews_sub, int view0, int view_step, int per_chunk) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int zchunks = (nz + 63) / 64;
+    const int k = (wave % zchunks) * 64 + lane;
+    const int ij = wave / zchunks;
+    const int i = ij % nx, j = ij / nx;
+    if (j >= ny) return;  // whole wave; no barrier below
+    const double P[3] = {(double)i, (double)j, (double)k};
+    double acc = 0.0;
+    const int vbeg = blockIdx.y * per_chunk;
+    const int vend = min(nviews_sub, vbeg + per_chunk);
+    for (int vl = vbeg; vl < vend && k < nz; ++vl) {
+        const int v = view0 + vl * view_step;
+        const ViewIdx &V = views[v];
+        // detector-plane projection of the cube corners
+        const double n0 = V.u[1] * V.v[2] - V.u[2] * V.v[1];
+        const double n1 = V.u[2] * V.v[0] - V.u[0] * V.v[2];
+        const double n2 = V.u[0] * V.v[1] - V.u[1] * V.v[0];
+        const double num = n0 * (V.d[0] - V.s[0]) + n1 * (V.d[1] - V.s[1]) + n2 * (V.d[2] - V.s[2]);
+        const double uu = V.u[0] * V.u[0] + V.u[1] * V.u[1] + V.u[2] * V.u[2];
+        const double uv = V.u[0] * V.v[0] + V.u[1] * V.v[1] + V.u[2] * V.v[2];
+        const double vv = V.v[0] * V.v[0] + V.v[1] * V.v[1] + V.v[2] * V.v[2];
+        const double det = uu * vv - uv * uv;
+        double amin = 1e30, amax = -1e30, bmin = 1e30, bmax = -1e30;
+        bool ok = true;
+        for (int c = 0; c < 8; ++c) {
+            const double Q[3] = {P[0] + ((c & 1) ? 1.0 : -1.0), P[1] + ((c & 2) ? 1.0 : -1.0),
+                                 P[2] + ((c & 4) ? 1.0 : -1.0)};
+            const double den = n0 * (Q[0] - V.s[0]) + n1 * (Q[1] - V.s[1]) + n2 * (Q[2] - V.s[2]);
+            const double t = num / den;
+            if (!(den != 0.0) || !(t > 0.0)) { ok = false; break; }
+            double X[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) X[e] = V.s[e] + t * (Q[e] - V.s[e]) - V.d[e];
+            const double xu = X[0] * V.u[0] + X[1] * V.u[1] + X[2] * V.u[2];
+            const double xv = X[0] * V.v[0] + X[1] * V.v[1] + X[2] * V.v[2];
+            const double pa = (xu * vv - xv * uv) / det + 0.5 * (nu - 1);
+            const double pb = (xv * uu - xu * uv) / det + 0.5 * (nv - 1);
+            amin = fmin(amin, pa); amax = fmax(amax, pa);
+            bmin = fmin(bmin, pb); bmax = fmax(bmax, pb);
+        }
+        int a0 = 0, a1 = nu - 1, b0 = 0, b1 = nv - 1;
+        if (ok) {
+            a0 = max(0, (int)floor(fmax(amin, -2.0)) - 1);
+            a1 = min(nu - 1, (int)ceil(fmin(amax, (double)nu + 1.0)) + 1);
+            b0 = max(0, (int)floor(fmax(bmin, -2.0)) - 1);
+            b1 = min(nv - 1, (int)ceil(fmin(bmax, (double)nv + 1.0)) + 1);
+        }
+        const PT *base = pt + (long)vl * nu * nv;
+        float pv = 0.f;
+        for (int a = a0; a <= a1; ++a) {
+            for (int b = b0; b <= b1; ++b) {
+                double D[3];
+                const double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) D[e] = (V.d[e] + ca * V.u[e] + cb * V.v[e]) - V.s[e];
+                const int m = axis[v * axis_view_stride + b * axis_row_stride + a];
+                const int ia = (m == 0) ? 1 : 0;
+                const double t = (P[m] - V.s[m]) / D[m];
+                if (!(t >= 0.0 && t <= 1.0)) continue;
+                const float wa = 1.f - (float)fabs(fma(t, D[ia], V.s[ia]) - P[ia]);
+                const float wz = 1.f - (float)fabs(fma(t, D[2], V.s[2]) - P[2]);
+                if (wa > 0.f && wz > 0.f) pv = fmaf(wa * wz, load_f(base, (long)a * nv + b), pv);
+            }
+        }
+        acc += (double)pv;
+    }
+    if (k < nz) {
+        const long o = ((long)k * ny + j) * nx + i;
+        if (gridDim.y == 1) vol[o] = (float)acc;
+        else part[(long)blockIdx.y * nx * ny * nz + o] = (float)acc;
+    }
+}
+
+hipError_t launch_backproject_gen(const void *pt, int pt_dtype, float *vol, float *scratch, const Level &L, int view0,
+                                  int view_step, int nviews_sub, hipStream_t s) {
+    const long waves = (long)((L.nz + 63) / 64) * L.nx * L.ny;
+    long c = (16384 + waves - 1) / waves;
+    if (c > 64) c = 64;
+    if (c > nviews_sub) c = nviews_sub;
+    const int nchunks = c < 1 ? 1 : (int)c;
+    if (nchunks > 1 && !scratch) return hipErrorInvalidValue;
+    const int per = (nviews_sub + nchunks - 1) / nchunks;
+    dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
+    const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
+    const long ars = L.axis_row_stride;
+    if (pt_dtype == MGCT_F32)
+        k_backproject_gen<float><<<grid, 256, 0, s>>>((const float *)pt, vol, scratch, L.d_views, L.d_axis, avs, ars,
+                                                      L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0, view_step,
+                                                      per);
+    else if (pt_dtype == MGCT_F16)
+        k_backproject_gen<_Float16><<<grid, 256, 0, s>>>((const _Float16 *)pt, vol, scratch, L.d_views, L.d_axis, avs,
+                                                         ars, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,
+                                                         view_step, per);
+    else
+        return hipErrorInvalidValue;
+    if (nchunks > 1) {
+        const long nvox = (long)L.nx * L.ny * L.nz;
+        unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);
+        k_sum_chunks<float><<<g, 256, 0, s>>>(scratch, vol, nvox, nchunks);
+    }
+    return hipGetLastError();
+}
+
+size_t backproject_gen_scratch_bytes(const Level &L, int nviews_sub) {
+    const long waves = (long)((L.nz + 63) / 64) * L.nx * L.ny;
+    long c = (16384 + waves - 1) / waves;
+    if (c > 64) c = 64;
+    if (c > nviews_sub) c = nviews_sub;
+    return c > 1 ? (size_t)c * L.vox() * sizeof(float) : 0;
+}
+
+}  // namespace mgct

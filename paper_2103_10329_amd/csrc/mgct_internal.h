@@ -119,6 +119,15 @@ hipError_t launch_backproject(const void *pt, int pt_dtype, void *vol, int vol_d
 hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, float *scratch,
                                const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
 
+// general-geometry transpose (any detector orientation; F32 output)
+size_t backproject_gen_scratch_bytes(const Level &L, int nviews_sub);
+hipError_t launch_backproject_gen(const void *pt, int pt_dtype, float *vol, float *scratch, const Level &L, int view0,
+                                  int view_step, int nviews_sub, hipStream_t s);
+// derivative with respect to the views' (s, d, u, v); dviews: device, views x 12
+size_t geom_grad_partial_bytes(const Level &L);
+hipError_t launch_geom_grad(const void *vt, int vt_dtype, const float *cot, double *partial, double *dviews,
+                            const Level &L, hipStream_t s);
+
 // Volume / stack operations (volume_ops.hip)
 hipError_t launch_fill(float *x, size_t n, float value, hipStream_t s);
 hipError_t launch_copy(const float *x, float *y, size_t n, hipStream_t s);
