@@ -109,6 +109,19 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
     // the projector's volume copy: BF16 when the input is BF16 or when asked
     if (vt_dtype < 0 || vol_dtype == MGCT_BF16) vt_dtype = vol_dtype;
     const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
+    if (L.separable) {
+        const bool f32 = vt_dtype == MGCT_F32;
+        void *vtx = workspace(c, lvl(f32 ? "vtx32" : "vtx16", g), pair_copy_elems(L) * es, true);
+        void *vty = workspace(c, lvl(f32 ? "vty32" : "vty16", g), pair_copy_elems(L) * es, true);
+        if (!vtx || !vty) return MGCT_ERR_OOM;
+        {
+            KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
+            HIPCHK(launch_transpose_pairs(vol, vol_dtype, vtx, vty, vt_dtype, L, s));
+        }
+        KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+        HIPCHK(launch_project_sep(vtx, vty, vt_dtype, proj, proj_dtype, L, view0, step, nsub, s));
+        return MGCT_OK;
+    }
     void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es, true);
     if (!vt) return MGCT_ERR_OOM;
     {

@@ -146,6 +146,87 @@ hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int
     return hipGetLastError();
 }
 
+// ----------------------------------------------- pair-expanded copies --
+//
+// For the separable projector every Joseph sample needs the 2x2 taps
+// (in-plane a, z) at (a0, z0) .. (a0+1, z0+1).  Two copies store each voxel
+// next to its neighbour along a: vtx[x][y][z] = (mu[x][y][z], mu[x][y+1][z])
+// for x-major rays (a = y) and vty[y][x][z] = (mu[x][y][z], mu[x+1][y][z])
+// for y-major rays (a = x), zero-padded by kVolPad, z fastest.  The four
+// taps of a sample are then 4 consecutive values: one 16-byte gather.
+// Grid: (x tiles of 64, z tiles of 64, y + 1 for y in [-1, ny-1]).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_transpose_pairs(const TI *__restrict__ vol, TO *__restrict__ vtx,
+                                                         TO *__restrict__ vty, int nx, int ny, int nz) {
+    __shared__ float t0[64][67];  // row y, x in [x0-1, x0+64]
+    __shared__ float t1[64][65];  // row y+1, x in [x0, x0+63]
+    const int x0 = blockIdx.x * 64, z0 = blockIdx.y * 64, y = (int)blockIdx.z - 1;
+    const int t = threadIdx.x;
+    for (int q = t; q < 64 * 66; q += 256) {
+        const int zl = q / 66, xl = q % 66;
+        const int z = z0 + zl, x = x0 - 1 + xl;
+        float v = 0.f;
+        if (y >= 0 && z < nz && x >= 0 && x < nx) v = load_f(vol, ((long)z * ny + y) * nx + x);
+        t0[zl][xl] = v;
+    }
+    for (int q = t; q < 64 * 64; q += 256) {
+        const int zl = q >> 6, xl = q & 63;
+        const int z = z0 + zl, x = x0 + xl;
+        float v = 0.f;
+        if (y + 1 < ny && z < nz && x < nx) v = load_f(vol, ((long)z * ny + (y + 1)) * nx + x);
+        t1[zl][xl] = v;
+    }
+    __syncthreads();
+    const long PX = nx + 2 * kVolPad, PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+    // vtx pairs along y: x in [x0, x0+63], y in [-1, ny-1]
+    for (int q = t; q < 64 * 64; q += 256) {
+        const int xl = q >> 6, zl = q & 63;
+        const int z = z0 + zl, x = x0 + xl;
+        if (z < nz && x < nx) {
+            const long o = (((long)(x + kVolPad) * PY + (y + kVolPad)) * PZ + (z + kVolPad)) * 2;
+            store_f(vtx, o, t0[zl][xl + 1]);
+            store_f(vtx, o + 1, t1[zl][xl]);
+        }
+    }
+    // vty pairs along x: y in [0, ny-1], x in [x0, x0+63] (and x = -1 for the first tile)
+    if (y >= 0) {
+        for (int q = t; q < 65 * 64; q += 256) {
+            const int xl = (q >> 6) - 1, zl = q & 63;
+            const int z = z0 + zl, x = x0 + xl;
+            if (z < nz && x < nx && (xl >= 0 || x0 == 0)) {
+                const long o = (((long)(y + kVolPad) * PX + (x + kVolPad)) * PZ + (z + kVolPad)) * 2;
+                store_f(vty, o, t0[zl][xl + 1]);
+                store_f(vty, o + 1, t0[zl][xl + 2]);
+            }
+        }
+    }
+}
+
+hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,
+                                  hipStream_t s) {
+    dim3 grid((L.nx + 63) / 64, (L.nz + 63) / 64, L.ny + 1);
+#define MGCT_TP(TI, TO) \
+    k_transpose_pairs<TI, TO><<<grid, 256, 0, s>>>((const TI *)vol, (TO *)vtx, (TO *)vty, L.nx, L.ny, L.nz)
+    if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_F32) MGCT_TP(float, float);
+    else if (vol_dtype == MGCT_BF16 && vt_dtype == MGCT_BF16) MGCT_TP(uint16_t, uint16_t);
+    else if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_BF16) MGCT_TP(float, uint16_t);
+    else return hipErrorInvalidValue;
+#undef MGCT_TP
+    return hipGetLastError();
+}
+
+size_t pair_copy_elems(const Level &L) {
+    return (size_t)(L.nx + 2 * kVolPad) * (L.ny + 2 * kVolPad) * (L.nz + 2 * kVolPad) * 2;
+}
+
+__device__ __forceinline__ float4 load_quad(const uint16_t *p, uint32_t i) {
+    const char *q = reinterpret_cast<const char *>(p) + i * 2u;
+    uint2 u;
+    __builtin_memcpy(&u, __builtin_assume_aligned(q, 4), 8);
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                       __uint_as_float(u.y & 0xffff0000u));
+}
+
 // ------------------------------------------------------------- projector --
 
 template <typename VT, typename PT>
@@ -223,8 +304,8 @@ struct PlaneEntry {
 };
 
 template <typename VT, typename PT>
-__global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vt, PT *__restrict__ proj,
-                                                     const ViewIdx *__restrict__ views,
+__global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
+                                                     PT *__restrict__ proj, const ViewIdx *__restrict__ views,
                                                      const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
                                                      int nv, double h, int view0, int view_step, int tab_len) {
     extern __shared__ PlaneEntry tab[];
@@ -240,9 +321,10 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vt, 
     const double Dm = (m == 0) ? C.dx : C.dy, Da = (m == 0) ? C.dy : C.dx, rDm = (m == 0) ? C.rdx : C.rdy;
     const double sm = V.s[m], sa = V.s[1 - m];
     const int n_m = (m == 0) ? nx : ny, n_a = (m == 0) ? ny : nx;
-    const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
-    const int Sm = (m == 0) ? PY * PZ : PZ;
-    const int Sa = (m == 0) ? PZ : PY * PZ;
+    // pair copy of this major axis: [plane][a][z] pairs along a
+    const VT *vt = (m == 0) ? vtx : vty;
+    const int PA = n_a + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+    const int Sm = PA * PZ, Sa = PZ;
     // planes between source and detector whose in-plane sample can touch the grid
     double lo = fmax(0.0, ceil(fmin(sm, sm + Dm)));
     double hi = fmin((double)(n_m - 1), floor(fmax(sm, sm + Dm)));
@@ -257,7 +339,7 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vt, 
             const double fa = fma(tau, Da, sa) + kVolPad;
             const double ga = floor(fa);
             PlaneEntry e;
-            e.off = (l + kVolPad) * Sm + (int)ga * Sa;
+            e.off = (l + kVolPad) * Sm + (int)ga * Sa;  // in pairs
             e.wa = (float)(fa - ga);
             e.tau = tau;
             T[l] = e;
@@ -284,24 +366,25 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vt, 
             const double fz = fma(e.tau, Dz, szp);
             const double gz = floor(fz);
             const float wz = (float)(fz - gz);
-            const uint32_t off = (uint32_t)(e.off + (int)gz);
-            const float2 r0 = load_pair(vt, off), r1 = load_pair(vt, off + Sa);
-            const float q0 = fmaf(wz, r0.y - r0.x, r0.x), q1 = fmaf(wz, r1.y - r1.x, r1.x);
+            // taps (a0,z0) (a1,z0) (a0,z1) (a1,z1)
+            const float4 r = load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
+            const float q0 = fmaf(wz, r.z - r.x, r.x), q1 = fmaf(wz, r.w - r.y, r.y);
             acc += fmaf(e.wa, q1 - q0, q0);
         }
     }
     store_f(proj, ((long)blockIdx.z * nv + b) * nu + a, acc * scale);
 }
 
-hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
-                          int view_step, int nviews_sub, hipStream_t s) {
+hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, void *proj, int proj_dtype,
+                              const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
     dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
-    if (L.separable) {
+    {
         const int tab_len = std::max(L.nx, L.ny);
         const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
 #define MGCT_PROJS(VT, PT)                                                                                      \
-    k_project_sep<VT, PT><<<grid, 256, lds, s>>>((const VT *)vt, (PT *)proj, L.d_views, L.d_cols, L.nx, L.ny,    \
-                                                 L.nz, L.nu, L.nv, L.h, view0, view_step, tab_len)
+    k_project_sep<VT, PT><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)proj, L.d_views,        \
+                                                 L.d_cols, L.nx, L.ny, L.nz, L.nu, L.nv, L.h, view0, view_step,  \
+                                                 tab_len)
         if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F32) MGCT_PROJS(float, float);
         else if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F16) MGCT_PROJS(float, _Float16);
         else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F32) MGCT_PROJS(uint16_t, float);
@@ -310,6 +393,11 @@ hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dty
 #undef MGCT_PROJS
         return hipGetLastError();
     }
+}
+
+hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
+                          int view_step, int nviews_sub, hipStream_t s) {
+    dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
     const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
     const long ars = L.axis_row_stride;
 #define MGCT_PROJ(VT, PT)                                                                                       \

@@ -109,6 +109,12 @@ hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int
                                    hipStream_t s);
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L,
                           int view0, int view_step, int nviews_sub, hipStream_t s);
+// separable geometry: pair-expanded copies for x-major and y-major rays
+size_t pair_copy_elems(const Level &L);
+hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,
+                                  hipStream_t s);
+hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, void *proj, int proj_dtype,
+                              const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
 hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, void *pt, int pt_dtype, const Level &L,
                                         int view0, int view_step, int nviews_sub, hipStream_t s);
 // scratch: backproject_scratch_bytes() bytes (partial volumes when the views
