@@ -14,3 +14,4 @@ results are not pinned to anything outside the oracle say "parity unpinned".
 
 from .core import *  # noqa: F401,F403
 from .methods import *  # noqa: F401,F403
+from . import cnn  # noqa: F401

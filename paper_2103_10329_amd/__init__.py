@@ -225,7 +225,9 @@ class Context:
         dp = ctypes.POINTER(ctypes.c_double)
         check(mgct_set_geometry(self.handle, nx, ny, nz, float(voxel), org.ctypes.data_as(dp), nu, nv,  # noqa: F821
                                 views.shape[0], views.ctypes.data_as(dp)), "mgct_set_geometry")
-        self.geom = dict(nx=nx, ny=ny, nz=nz, nu=nu, nv=nv, n_views=views.shape[0], voxel=voxel)
+        self.geom = dict(nx=nx, ny=ny, nz=nz, nu=nu, nv=nv, n_views=views.shape[0], voxel=voxel,
+                         origin=tuple(float(o) for o in org))
+        self._views_np = views.copy()
 
     def shapes(self, level: int = 0):
         g = self.geom
