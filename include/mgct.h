@@ -242,6 +242,27 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
                          double *resid_hist, hipStream_t stream);
 
 /*
+ * Learned preconditioner (spec extension; refines eq. 4's filtered
+ * update u): out = u + f(u), f = four 3^3 convolutions 1 -> 16 -> 32 -> 32 -> 1
+ * with zero "same" padding and erf-GELU after the first three.  Parameters:
+ * one FP32 vector of MGCT_CNN_PARAMS values, W1 b1 W2 b2 W3 b3 W4 b4, each W
+ * as [out][in][kz][ky][kx] (cross-correlation, as torch's conv3d).  The
+ * library keeps an FP32 master copy and Adam state per context; the matrix
+ * core layers use BF16 weights and activations with FP32 accumulation.
+ * Volumes: device F32 [nz][ny][nx], nx a multiple of 32.
+ */
+#define MGCT_CNN_PARAMS 42849
+int mgct_cnn_set_weights(void *ctx, const float *weights /* host */, int n);  /* also resets Adam */
+int mgct_cnn_get_weights(void *ctx, float *weights /* host */, int n);
+int mgct_cnn_forward(void *ctx, int nx, int ny, int nz, const float *u, float *out, hipStream_t stream);
+/* forward + backward of the mean squared error against target; grads host (n params), loss host (may be NULL) */
+int mgct_cnn_gradients(void *ctx, int nx, int ny, int nz, const float *u, const float *target, float *grads,
+                       double *loss, hipStream_t stream);
+/* forward + backward + one Adam step (beta 0.9/0.999, eps 1e-8) of learning rate lr */
+int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const float *target, double lr,
+                        double *loss, hipStream_t stream);
+
+/*
  * Kernel timing (instrumentation).  While enabled, every launch of the
  * kernels below is bracketed by HIP events recorded on the launch's stream.
  * mgct_kernel_timing(ctx, 1) enables and clears the records, (ctx, 0)

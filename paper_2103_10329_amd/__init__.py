@@ -84,6 +84,11 @@ SIGNATURES = {
     "mgct_set_precision": (_ci, [_vp, _ci, _ci]),
     "mgct_project_geom_grad": (_ci, [_vp, _ci, _vp, _vp, _dp, _vp]),
     "mgct_geometry_param_grad": (_ci, [_ci, _dp, _dp, _cd, _cd, _cd, _cd, _dp]),
+    "mgct_cnn_set_weights": (_ci, [_vp, ctypes.POINTER(ctypes.c_float), _ci]),
+    "mgct_cnn_get_weights": (_ci, [_vp, ctypes.POINTER(ctypes.c_float), _ci]),
+    "mgct_cnn_forward": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
+    "mgct_cnn_gradients": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.POINTER(ctypes.c_float), _dp, _vp]),
+    "mgct_cnn_train_step": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _cd, _dp, _vp]),
     "mgct_kernel_timing": (_ci, [_vp, _ci]),
     "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
 }
@@ -312,6 +317,44 @@ class Context:
               "mgct_project_geom_grad")
         return out
 
+    # ---- learned preconditioner
+    CNN_PARAMS = 42849
+
+    def cnn_set_weights(self, flat):
+        w = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        check(mgct_cnn_set_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size),  # noqa: F821
+              "mgct_cnn_set_weights")
+
+    def cnn_get_weights(self) -> np.ndarray:
+        w = np.zeros(self.CNN_PARAMS, dtype=np.float32)
+        check(mgct_cnn_get_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size),  # noqa: F821
+              "mgct_cnn_get_weights")
+        return w
+
+    def cnn_forward(self, u, out=None):
+        import torch
+        nz, ny, nx = u.shape
+        if out is None:
+            out = torch.empty_like(u)
+        check(mgct_cnn_forward(self.handle, nx, ny, nz, _ptr(u), _ptr(out), _stream()), "mgct_cnn_forward")  # noqa: F821
+        return out
+
+    def cnn_gradients(self, u, target):
+        nz, ny, nx = u.shape
+        g = np.zeros(self.CNN_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        check(mgct_cnn_gradients(self.handle, nx, ny, nz, _ptr(u), _ptr(target),  # noqa: F821
+                                 g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss), _stream()),
+              "mgct_cnn_gradients")
+        return g, loss.value
+
+    def cnn_train_step(self, u, target, lr, want_loss=True):
+        nz, ny, nx = u.shape
+        loss = ctypes.c_double()
+        check(mgct_cnn_train_step(self.handle, nx, ny, nz, _ptr(u), _ptr(target), float(lr),  # noqa: F821
+                                  ctypes.byref(loss) if want_loss else None, _stream()), "mgct_cnn_train_step")
+        return loss.value if want_loss else None
+
     def kernel_timing(self, enable: bool):
         check(mgct_kernel_timing(self.handle, 1 if enable else 0), "mgct_kernel_timing")  # noqa: F821
 
@@ -357,4 +400,22 @@ def geometry_param_grad(views0, dviews, voxel, dx, dz, tilt_deg) -> np.ndarray:
     check(mgct_geometry_param_grad(v0.shape[0], v0.ctypes.data_as(dp), dv.ctypes.data_as(dp), float(voxel),  # noqa: F821
                                    float(dx), float(dz), float(tilt_deg), out.ctypes.data_as(dp)),
           "mgct_geometry_param_grad")
+    return out
+
+
+def cnn_flatten(params) -> np.ndarray:
+    """[[W1, b1], ..., [W4, b4]] (W as [co][ci][3][3][3]) -> flat FP32 vector in
+    the library's order W1 b1 W2 b2 W3 b3 W4 b4."""
+    return np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for layer in params for a in layer]).astype(
+        np.float32)
+
+
+def cnn_unflatten(flat):
+    shapes = [((16, 1, 3, 3, 3), (16,)), ((32, 16, 3, 3, 3), (32,)), ((32, 32, 3, 3, 3), (32,)), ((1, 32, 3, 3, 3), (1,))]
+    out, k = [], 0
+    flat = np.asarray(flat, dtype=np.float64)
+    for ws, bs in shapes:
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        out.append([flat[k:k + nw].reshape(ws), flat[k + nw:k + nw + nb].reshape(bs)])
+        k += nw + nb
     return out

@@ -31,6 +31,7 @@ SOURCES = {
     "joseph.hip": ["-O3"],
     "volume_ops.hip": ["-O3"],
     "fft.hip": ["-O3"],
+    "cnn.hip": ["-O3"],
 }
 
 

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <functional>
 #include <sstream>
 #include <string>
@@ -340,10 +341,146 @@ int do_estimate(Ctx &c, Level &L, int g, const mgct_filter *f, int iters, uint64
     return MGCT_OK;
 }
 
+int cnn_buffers(Ctx &c, long n, bool train, CnnBuffers &B) {
+    auto get = [&](const char *name, size_t bytes, bool zero = false) { return workspace(c, name, bytes, zero); };
+    B.h1 = (uint16_t *)get("cnn_h1", n * 16 * 2);
+    B.h2 = (uint16_t *)get("cnn_h2", n * 32 * 2);
+    B.h3 = (uint16_t *)get("cnn_h3", n * 32 * 2);
+    if (!B.h1 || !B.h2 || !B.h3) return MGCT_ERR_OOM;
+    if (!train) return MGCT_OK;
+    B.z1 = (float *)get("cnn_z1", n * 16 * 4);
+    B.z2 = (float *)get("cnn_z2", n * 32 * 4);
+    B.z3 = (float *)get("cnn_z3", n * 32 * 4);
+    B.dout = (float *)get("cnn_dout", n * 4);
+    B.dz3 = (uint16_t *)get("cnn_dz3", n * 32 * 2);
+    B.dz2 = (uint16_t *)get("cnn_dz2", n * 32 * 2);
+    B.dz1 = (uint16_t *)get("cnn_dz1", n * 16 * 2);
+    B.dz1f = (float *)get("cnn_dz1f", n * 16 * 4);
+    B.gT = (uint16_t *)get("cnn_gT", n * 32 * 2);
+    if (!B.z1 || !B.z2 || !B.z3 || !B.dout || !B.dz3 || !B.dz2 || !B.dz1 || !B.dz1f || !B.gT) return MGCT_ERR_OOM;
+    return MGCT_OK;
+}
+
+// padded channels-first copy (its zero border must survive: allocated zeroed
+// once per volume shape) and the partial-sum scratch
+int cnn_train_scratch(Ctx &c, int nx, int ny, int nz, CnnBuffers &B) {
+    const size_t padded = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * 32 * 2;
+    std::string key = "cnn_xT_" + std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz);
+    B.xT = (uint16_t *)workspace(c, key, padded, true);
+    const long n = (long)nx * ny * nz;
+    const long rows = (long)ny * nz, nch = (rows + 15) / 16, nvb = (n + 4095) / 4096;
+    const size_t part = std::max((size_t)nch * 27 * 1024, (size_t)nvb * 865) * 4;
+    B.partial = (float *)workspace(c, "cnn_partial", part);
+    if (!B.xT || !B.partial) return MGCT_ERR_OOM;
+    return MGCT_OK;
+}
+
+int cnn_check(Ctx &c, int nx, int ny, int nz) {
+    if (!c.cnn.ready) return MGCT_ERR_INVALID_ARG;
+    if (nx < 32 || ny < 1 || nz < 1 || nx % 32) return MGCT_ERR_INVALID_ARG;
+    return MGCT_OK;
+}
+
 }  // namespace
 
 // ======================================================================
 extern "C" {
+
+int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
+    if (!ctx || !w || n != kCnnParams) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    CnnState &S = c.cnn;
+    if (!S.master) {
+        void *p = nullptr;
+        const size_t fb = kCnnParams * 4;
+        if (hipMalloc(&p, 4 * fb + 2 * (size_t)27 * 32 * 16 + 3 * 2 * (size_t)27 * 32 * 32) != hipSuccess)
+            return MGCT_ERR_OOM;
+        char *q = (char *)p;
+        S.master = (float *)q; q += fb;
+        S.adam_m = (float *)q; q += fb;
+        S.adam_v = (float *)q; q += fb;
+        S.grads = (float *)q; q += fb;
+        S.p2f = (uint16_t *)q; q += 2 * 27 * 32 * 16;
+        S.p3f = (uint16_t *)q; q += 2 * 27 * 32 * 32;
+        S.p3d = (uint16_t *)q; q += 2 * 27 * 32 * 32;
+        S.p2d = (uint16_t *)q;
+    }
+    HIPCHK(hipMemcpy(S.master, w, kCnnParams * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(S.adam_m, 0, kCnnParams * 4));
+    HIPCHK(hipMemset(S.adam_v, 0, kCnnParams * 4));
+    S.adam_t = 0;
+    HIPCHK(cnn_pack(S, 0));
+    HIPCHK(hipDeviceSynchronize());
+    S.ready = true;
+    return MGCT_OK;
+}
+
+int mgct_cnn_get_weights(void *ctx, float *w, int n) {
+    if (!ctx || !w || n != kCnnParams) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    if (!c.cnn.ready) return MGCT_ERR_INVALID_ARG;
+    HIPCHK(hipSetDevice(c.device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(w, c.cnn.master, kCnnParams * 4, hipMemcpyDeviceToHost));
+    return MGCT_OK;
+}
+
+int mgct_cnn_forward(void *ctx, int nx, int ny, int nz, const float *u, float *out, hipStream_t s) {
+    if (!ctx || !u || !out) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    MGCHK(cnn_check(c, nx, ny, nz));
+    CnnBuffers B;
+    MGCHK(cnn_buffers(c, (long)nx * ny * nz, false, B));
+    HIPCHK(cnn_forward(c.cnn, B, u, out, nx, ny, nz, false, s));
+    return MGCT_OK;
+}
+
+static int cnn_fwd_bwd(Ctx &c, int nx, int ny, int nz, const float *u, const float *target, double *loss,
+                       hipStream_t s) {
+    const long n = (long)nx * ny * nz;
+    CnnBuffers B;
+    MGCHK(cnn_buffers(c, n, true, B));
+    MGCHK(cnn_train_scratch(c, nx, ny, nz, B));
+    WS(out, float, "cnn_out", n * 4, false);
+    WS(part, double, "red_partials", kRedBlocks * 8, false);
+    WS(lsum, double, "cnn_loss", 8, false);
+    HIPCHK(cnn_forward(c.cnn, B, u, out, nx, ny, nz, true, s));
+    HIPCHK(cnn_backward(c.cnn, B, u, out, target, c.cnn.grads, part, kRedBlocks, nx, ny, nz, s));
+    HIPCHK(launch_finish_sum(part, kRedBlocks, lsum, s));
+    if (loss) {
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, lsum, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *loss = v / (double)n;
+    }
+    return MGCT_OK;
+}
+
+int mgct_cnn_gradients(void *ctx, int nx, int ny, int nz, const float *u, const float *target, float *grads,
+                       double *loss, hipStream_t s) {
+    if (!ctx || !u || !target || !grads) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    MGCHK(cnn_check(c, nx, ny, nz));
+    MGCHK(cnn_fwd_bwd(c, nx, ny, nz, u, target, loss, s));
+    HIPCHK(hipMemcpyAsync(grads, c.cnn.grads, kCnnParams * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MGCT_OK;
+}
+
+int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const float *target, double lr,
+                        double *loss, hipStream_t s) {
+    if (!ctx || !u || !target || !(lr > 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    MGCHK(cnn_check(c, nx, ny, nz));
+    MGCHK(cnn_fwd_bwd(c, nx, ny, nz, u, target, loss, s));
+    HIPCHK(cnn_adam(c.cnn, c.cnn.grads, (float)lr, s));
+    return MGCT_OK;
+}
+
 
 const char *mgct_status_string(int st) {
     switch (st) {
@@ -431,6 +568,7 @@ int mgct_destroy(void *ctx) {
     (void)hipDeviceSynchronize();
     release_events(*c);
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->cnn.master) (void)hipFree(c->cnn.master);
     for (auto &kv : c->ws) (void)hipFree(kv.second.first);
     for (auto &L : c->levels) free_level(L);
     delete c;

@@ -1,0 +1,439 @@
+// Learned preconditioner: a residual 3-D CNN applied to the filtered
+// Landweber update u (eq. 4's step), out = u + f(u), with f four 3^3
+// convolutions 1 -> 16 -> 32 -> 32 -> 1 (zero "same" padding, erf-GELU after
+// the first three).  BF16 weights and activations, FP32 accumulation, FP32
+// master weights and Adam state.
+//
+// Layout: activations channels-last [voxel][channel] (voxel = (z*ny + y)*nx
+// + x).  The two 32-output layers (and their input gradients) are implicit
+// GEMMs on the matrix cores: a wave computes 32 consecutive voxels along x
+// times 32 output channels with v_mfma_f32_32x32x16_bf16, K running over the
+// 27 taps times the input channels in chunks of 16; each lane's A operand is
+// the 8 contiguous channels of one shifted voxel (one 16-byte load).  The
+// weight gradients of those layers are GEMMs with K = voxels on
+// channels-first copies (8 consecutive voxels per lane).  The 1-channel first
+// and last layers run on the vector ALUs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mgct_internal.h"
+
+namespace mgct {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// offsets into the FP32 master parameter vector ([co][ci][kz][ky][kx] per layer)
+constexpr int kW1 = 0, kB1 = 432, kW2 = 448, kB2 = 14272, kW3 = 14304, kB3 = 41952, kW4 = 41984, kB4 = 42848;
+static_assert(kB4 + 1 == kCnnParams, "parameter layout");
+
+__device__ __forceinline__ float bf(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t to_bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+struct Dims {
+    int nx, ny, nz;
+};
+__device__ __forceinline__ bool tap_voxel(const Dims &d, int x, int y, int z, int t, long &v) {
+    const int xx = x + (t % 3) - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
+    if (xx < 0 || yy < 0 || zz < 0 || xx >= d.nx || yy >= d.ny || zz >= d.nz) return false;
+    v = ((long)zz * d.ny + yy) * d.nx + xx;
+    return true;
+}
+
+// ------------------------------------------------------------ weights ----
+
+// P2f[t][co][ci] (ci<16), P3f[t][co][ci], P3d[t][ci][co] = W3[co][ci][26-t],
+// P2d[t][ci][co] = W2[co][ci][26-t] for ci < 16, zero for ci in 16..31.
+__global__ void k_pack_weights(const float *__restrict__ w, uint16_t *P2f, uint16_t *P3f, uint16_t *P3d,
+                               uint16_t *P2d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 27 * 32 * 16) {
+        const int t = i / 512, co = (i / 16) % 32, ci = i % 16;
+        P2f[i] = to_bf(w[kW2 + (co * 16 + ci) * 27 + t]);
+    }
+    if (i < 27 * 32 * 32) {
+        const int t = i / 1024, a = (i / 32) % 32, c = i % 32;
+        P3f[i] = to_bf(w[kW3 + (a * 32 + c) * 27 + t]);          // a = co, c = ci
+        P3d[i] = to_bf(w[kW3 + (c * 32 + a) * 27 + (26 - t)]);   // a = ci, c = co
+        P2d[i] = a < 16 ? to_bf(w[kW2 + (c * 16 + a) * 27 + (26 - t)]) : (uint16_t)0;
+    }
+}
+
+// ------------------------------------------------------ VALU layers ----
+
+// z1[v][16] = b1 + sum_t W1[co][t] u[v + off_t]; h1 = GELU(z1) (BF16).
+__global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ u, const float *__restrict__ w,
+                                                   float *__restrict__ z1, uint16_t *__restrict__ h1, Dims d) {
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+    float in[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        long q;
+        in[t] = tap_voxel(d, x, y, z, t, q) ? u[q] : 0.f;
+    }
+#pragma unroll 4
+    for (int co = 0; co < 16; ++co) {
+        float acc = w[kB1 + co];
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc = fmaf(w[kW1 + co * 27 + t], in[t], acc);
+        if (z1) z1[v * 16 + co] = acc;
+        h1[v * 16 + co] = to_bf(gelu(acc));
+    }
+}
+
+// out[v] = u[v] + b4 + sum_{t, ci} W4[ci][t] h3[v + off_t][ci]
+__global__ __launch_bounds__(256) void k_conv4_fwd(const uint16_t *__restrict__ h3, const float *__restrict__ w,
+                                                   const float *__restrict__ u, float *__restrict__ out, Dims d) {
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+    float acc = w[kB4];
+    for (int t = 0; t < 27; ++t) {
+        long q;
+        if (!tap_voxel(d, x, y, z, t, q)) continue;
+        const uint4 *p = reinterpret_cast<const uint4 *>(h3 + q * 32);
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const uint4 r = p[c4];
+            const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ci = c4 * 8 + e * 2;
+                acc = fmaf(w[kW4 + ci * 27 + t], __uint_as_float(wd[e] << 16), acc);
+                acc = fmaf(w[kW4 + (ci + 1) * 27 + t], __uint_as_float(wd[e] & 0xffff0000u), acc);
+            }
+        }
+    }
+    out[v] = u[v] + acc;
+}
+
+// loss partials and dout = 2 (out - target) / n
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, const float *__restrict__ target,
+                                             float *__restrict__ dout, double *__restrict__ partials, long n) {
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float e = out[i] - target[i];
+        dout[i] = 2.f * e / (float)n;
+        acc += (double)e * e;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// dz3[v][ci] = GELU'(z3[v][ci]) * sum_t W4[ci][t] dout[v - off_t]
+__global__ __launch_bounds__(256) void k_conv4_bwd_input(const float *__restrict__ dout, const float *__restrict__ w,
+                                                         const float *__restrict__ z3, uint16_t *__restrict__ dz3,
+                                                         Dims d) {
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+    float g[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        long q;
+        g[t] = tap_voxel(d, x, y, z, 26 - t, q) ? dout[q] : 0.f;  // v - off_t = v + off_(26-t)
+    }
+    for (int ci = 0; ci < 32; ++ci) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc = fmaf(w[kW4 + ci * 27 + t], g[t], acc);
+        dz3[v * 32 + ci] = to_bf(acc * gelu_grad(z3[v * 32 + ci]));
+    }
+}
+
+// Weight gradient of a layer with one input channel (layer 1: X = u, G = dz1
+// [v][16]) or one output channel (layer 4: X = h3 [v][32] BF16, G = dout):
+// grad[o] = sum_v X(v + off_t(o), c(o)) * G(v, c'(o)) over a block's chunk of
+// voxels; bias gradients (sum_v G) in the last slots.  partial[block][R].
+template <int MODE>  // 1: layer 1 (R = 16*27 + 16), 4: layer 4 (R = 32*27 + 1)
+__global__ __launch_bounds__(256) void k_wgrad_valu(const float *__restrict__ xf, const uint16_t *__restrict__ xh,
+                                                    const float *__restrict__ g, float *__restrict__ partial, Dims d,
+                                                    long chunk) {
+    constexpr int R = MODE == 1 ? 16 * 27 + 16 : 32 * 27 + 1;
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
+    for (int o = threadIdx.x; o < R; o += blockDim.x) {
+        double acc = 0.0;
+        if (MODE == 1) {
+            if (o < 432) {
+                const int co = o / 27, t = o % 27;
+                for (long v = v0; v < v1; ++v) {
+                    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+                    long q;
+                    if (tap_voxel(d, x, y, z, t, q)) acc += (double)(xf[q] * g[v * 16 + co]);
+                }
+            } else {
+                const int co = o - 432;
+                for (long v = v0; v < v1; ++v) acc += (double)g[v * 16 + co];
+            }
+        } else {
+            if (o < 864) {
+                const int ci = o / 27, t = o % 27;
+                for (long v = v0; v < v1; ++v) {
+                    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+                    long q;
+                    if (tap_voxel(d, x, y, z, t, q)) acc += (double)(bf(xh[q * 32 + ci]) * g[v]);
+                }
+            } else {
+                for (long v = v0; v < v1; ++v) acc += (double)g[v];
+            }
+        }
+        partial[blockIdx.x * (long)R + o] = (float)acc;
+    }
+}
+
+// grads[dst + j] = sum_b partial[b][j] (fixed order)
+__global__ void k_sum_partials(const float *__restrict__ partial, int nparts, int R, float *__restrict__ grads,
+                               int dst_stride_mode) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= R) return;
+    double acc = 0.0;
+    for (int b = 0; b < nparts; ++b) acc += (double)partial[(long)b * R + j];
+    grads[j] = (float)acc;
+    (void)dst_stride_mode;
+}
+
+// ------------------------------------------------------ matrix cores ----
+
+// MODE 0 (forward): out channels 32, z = acc + bias -> zout (FP32, may be
+//   null), hout = BF16 GELU(z).
+// MODE 1 (input gradient): out channels NOUT (16 or 32), hout = BF16
+//   acc * GELU'(zprev).
+// X: [v][CI] BF16; P: [27][32][CI] BF16 (B operand, n-major).  nx % 32 == 0.
+template <int CI, int MODE>
+__global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
+                                                   const float *__restrict__ bias, const float *__restrict__ zprev,
+                                                   float *__restrict__ zout, uint16_t *__restrict__ hout, int nout,
+                                                   Dims d) {
+    const int lane = threadIdx.x & 63;
+    const long tile = blockIdx.x * 4L + (threadIdx.x >> 6);
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long v0 = tile * 32;
+    if (v0 >= n) return;  // whole wave; no barrier below
+    const int m = lane & 31, kh = lane >> 5;
+    const int x0 = (int)(v0 % d.nx), y = (int)((v0 / d.nx) % d.ny), z = (int)(v0 / ((long)d.nx * d.ny));
+    floatx16 acc = {};
+    for (int t = 0; t < 27; ++t) {
+        long q;
+        const bool ok = tap_voxel(d, x0 + m, y, z, t, q);
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc) {
+            bf16x8 a = {};
+            if (ok) a = *reinterpret_cast<const bf16x8 *>(X + q * CI + kc * 16 + kh * 8);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + m) * CI + kc * 16 + kh * 8);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    // D[i][j]: column j = lane % 32, row i = 8 (r / 4) + 4 (lane / 32) + r % 4 for register r
+    const int col = m;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+        const long v = v0 + row;
+        if (MODE == 0) {
+            const float zv = acc[r] + bias[col];
+            if (zout) zout[v * 32 + col] = zv;
+            hout[v * 32 + col] = to_bf(gelu(zv));
+        } else if (col < nout) {
+            hout[v * nout + col] = to_bf(acc[r] * gelu_grad(zprev[v * nout + col]));
+        }
+    }
+}
+
+// channels-last BF16 [v][C] -> channels-first [C][nz+2][ny+2][nx+2] (zero border)
+__global__ void k_to_cf_padded(const uint16_t *__restrict__ x, uint16_t *__restrict__ xt, int C, Dims d) {
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n * C) return;
+    const long v = i / C;
+    const int c = (int)(i % C);
+    const int xx = (int)(v % d.nx), yy = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long)d.nx * d.ny));
+    const long PX = d.nx + 2, PY = d.ny + 2, PZ = d.nz + 2;
+    xt[(((long)c * PZ + zz + 1) * PY + yy + 1) * PX + xx + 1] = x[i];
+}
+
+// channels-last BF16 [v][C] -> channels-first [C][v]
+__global__ void k_to_cf(const uint16_t *__restrict__ x, uint16_t *__restrict__ xt, int C, long n) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n * C) return;
+    const long v = i / C;
+    const int c = (int)(i % C);
+    xt[(long)c * n + v] = x[i];
+}
+
+// dW[t][co][ci] partial over a chunk of rows: sum_v G[co][v] X[ci][v + off_t]
+// (G channels-first [32][n], X channels-first padded [CI][nz+2][ny+2][nx+2]).
+// One wave per (tap, chunk); K = 16 voxels per MFMA along x (nx % 16 == 0).
+// partial[chunk][t][co][ci] (32 x 32, ci >= CI left zero).
+template <int CI>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const uint16_t *__restrict__ G, const uint16_t *__restrict__ X,
+                                                    float *__restrict__ partial, Dims d, int rows_per_chunk,
+                                                    int nchunks) {
+    const int lane = threadIdx.x & 63;
+    const long wid = blockIdx.x * 4L + (threadIdx.x >> 6);
+    if (wid >= 27L * nchunks) return;  // whole wave; no barrier below
+    const int t = (int)(wid % 27), chunk = (int)(wid / 27);
+    const int m = lane & 31, kh = lane >> 5;
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long PX = d.nx + 2, PY = d.ny + 2, PZ = d.nz + 2;
+    const int nrows = d.ny * d.nz;
+    const int r0 = chunk * rows_per_chunk, r1 = min(nrows, r0 + rows_per_chunk);
+    floatx16 acc = {};
+    for (int row = r0; row < r1; ++row) {
+        const int y = row % d.ny, z = row / d.ny;
+        const long vrow = (long)row * d.nx;
+        const long prow = (((long)m * PZ + z + 1 + dz) * PY + y + 1 + dy) * PX + 1 + dx;
+        for (int x0 = 0; x0 < d.nx; x0 += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(G + (long)m * n + vrow + x0 + kh * 8);
+            bf16x8 b = {};
+            if (m < CI) {
+                const uint16_t *src = X + prow + x0 + kh * 8;
+                __builtin_memcpy(&b, __builtin_assume_aligned(src, 2), 16);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    float *dst = partial + ((long)chunk * 27 + t) * 1024;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);  // co
+        dst[row * 32 + m] = acc[r];                        // ci = m
+    }
+}
+
+// grads[W at layer offset][co][ci][t] = sum_chunks partial[chunk][t][co][ci]
+__global__ void k_wgrad_mfma_sum(const float *__restrict__ partial, int nchunks, int CI, float *__restrict__ gw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over co*CI*27
+    if (i >= 32 * CI * 27) return;
+    const int co = i / (CI * 27), ci = (i / 27) % CI, t = i % 27;
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; ++c) acc += (double)partial[((long)c * 27 + t) * 1024 + co * 32 + ci];
+    gw[i] = (float)acc;
+}
+
+// db[co] = sum_v G[v][co] (BF16 channels-last), partial per block then summed.
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ g, int C, long n, long chunk,
+                                                   float *__restrict__ partial) {
+    const long v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
+    __shared__ double red[256];
+    for (int c = 0; c < C; ++c) {
+        double acc = 0.0;
+        for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) acc += (double)bf(g[v * C + c]);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * (long)C + c] = (float)red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_bf16_to_f32(const uint16_t *__restrict__ x, float *__restrict__ y, long n) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = bf(x[i]);
+}
+
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------ drivers ----
+
+static unsigned blocks(long n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t cnn_pack(CnnState &S, hipStream_t s) {
+    k_pack_weights<<<blocks(27 * 32 * 32), 256, 0, s>>>(S.master, S.p2f, S.p3f, S.p3d, S.p2d);
+    return hipGetLastError();
+}
+
+hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *out, int nx, int ny, int nz,
+                       bool keep, hipStream_t s) {
+    const Dims d{nx, ny, nz};
+    const long n = (long)nx * ny * nz;
+    const unsigned vb = blocks(n), tb = (unsigned)((n / 32 + 3) / 4);
+    k_conv1_fwd<<<vb, 256, 0, s>>>(u, S.master, keep ? B.z1 : nullptr, B.h1, d);
+    k_conv_mfma<16, 0><<<tb, 256, 0, s>>>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d);
+    k_conv_mfma<32, 0><<<tb, 256, 0, s>>>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d);
+    k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
+    return hipGetLastError();
+}
+
+hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const float *out, const float *target,
+                        float *grads, double *loss_partials, int n_loss_blocks, int nx, int ny, int nz,
+                        hipStream_t s) {
+    const Dims d{nx, ny, nz};
+    const long n = (long)nx * ny * nz;
+    const unsigned vb = blocks(n), tb = (unsigned)((n / 32 + 3) / 4);
+    k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
+    // layer 4
+    const long vchunk = 4096;
+    const int nvb = (int)((n + vchunk - 1) / vchunk);
+    k_wgrad_valu<4><<<nvb, 256, 0, s>>>(nullptr, B.h3, B.dout, B.partial, d, vchunk);
+    k_sum_partials<<<blocks(865), 256, 0, s>>>(B.partial, nvb, 865, grads + kW4, 0);
+    k_conv4_bwd_input<<<vb, 256, 0, s>>>(B.dout, S.master, B.z3, B.dz3, d);
+    // layer 3: weights (channels-first copies), bias, input gradient -> dz2
+    const int rows = ny * nz;
+    const int rpc = 16, nch = (rows + rpc - 1) / rpc;
+    k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz3, B.gT, 32, n);
+    k_to_cf_padded<<<blocks(n * 32), 256, 0, s>>>(B.h2, B.xT, 32, d);
+    k_wgrad_mfma<32><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
+    k_wgrad_mfma_sum<<<blocks(32 * 32 * 27), 256, 0, s>>>(B.partial, nch, 32, grads + kW3);
+    k_bias_grad<<<nvb, 256, 0, s>>>(B.dz3, 32, n, vchunk, B.partial);
+    k_sum_partials<<<1, 256, 0, s>>>(B.partial, nvb, 32, grads + kB3, 0);
+    k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz3, S.p3d, nullptr, B.z2, nullptr, B.dz2, 32, d);
+    // layer 2
+    k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz2, B.gT, 32, n);
+    k_to_cf_padded<<<blocks(n * 16), 256, 0, s>>>(B.h1, B.xT, 16, d);
+    k_wgrad_mfma<16><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
+    k_wgrad_mfma_sum<<<blocks(32 * 16 * 27), 256, 0, s>>>(B.partial, nch, 16, grads + kW2);
+    k_bias_grad<<<nvb, 256, 0, s>>>(B.dz2, 32, n, vchunk, B.partial);
+    k_sum_partials<<<1, 256, 0, s>>>(B.partial, nvb, 32, grads + kB2, 0);
+    k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz2, S.p2d, nullptr, B.z1, nullptr, B.dz1, 16, d);
+    // layer 1 (input gradient not needed); dz1 holds GELU' * dh1 in BF16
+    k_bf16_to_f32<<<blocks(n * 16), 256, 0, s>>>(B.dz1, B.dz1f, n * 16);
+    k_wgrad_valu<1><<<nvb, 256, 0, s>>>(u, nullptr, B.dz1f, B.partial, d, vchunk);
+    k_sum_partials<<<blocks(448), 256, 0, s>>>(B.partial, nvb, 448, grads + kW1, 0);
+    return hipGetLastError();
+}
+
+hipError_t cnn_adam(CnnState &S, const float *grads, float lr, hipStream_t s) {
+    S.adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)S.adam_t), c2 = 1.f - powf(b2, (float)S.adam_t);
+    k_adam<<<blocks(kCnnParams), 256, 0, s>>>(S.master, grads, S.adam_m, S.adam_v, kCnnParams, lr, b1, b2, 1e-8f, c1,
+                                              c2);
+    return cnn_pack(S, s);
+}
+
+}  // namespace mgct

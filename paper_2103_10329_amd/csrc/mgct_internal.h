@@ -59,6 +59,36 @@ struct Level {
     }
 };
 
+// ---- learned preconditioner (cnn.hip)
+constexpr int kCnnParams = 42849;  // 1->16->32->32->1 channels, 3^3 kernels, biases
+
+struct CnnState {
+    float *master = nullptr;  // FP32 parameters [W1 b1 W2 b2 W3 b3 W4 b4]
+    float *adam_m = nullptr, *adam_v = nullptr, *grads = nullptr;
+    uint16_t *p2f = nullptr, *p3f = nullptr, *p3d = nullptr, *p2d = nullptr;  // packed BF16 operands
+    int adam_t = 0;
+    bool ready = false;
+};
+
+// activation / gradient buffers for one volume of n voxels
+struct CnnBuffers {
+    float *z1 = nullptr, *z2 = nullptr, *z3 = nullptr;      // pre-activations, FP32 [n][C]
+    uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;   // activations, BF16 [n][C]
+    float *dout = nullptr;                                  // [n]
+    uint16_t *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
+    float *dz1f = nullptr;
+    uint16_t *gT = nullptr, *xT = nullptr;                  // channels-first copies for weight gradients
+    float *partial = nullptr;
+};
+
+hipError_t cnn_pack(CnnState &S, hipStream_t s);
+hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *out, int nx, int ny, int nz,
+                       bool keep, hipStream_t s);
+hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const float *out, const float *target,
+                        float *grads, double *loss_partials, int n_loss_blocks, int nx, int ny, int nz,
+                        hipStream_t s);
+hipError_t cnn_adam(CnnState &S, const float *grads, float lr, hipStream_t s);
+
 struct Ctx {
     int device = 0;
     bool has_geom = false;
@@ -82,6 +112,7 @@ struct Ctx {
     // storage of the Landweber steps' internal copies: the projector's
     // volume copy (F32 or BF16) and the data/residual stacks (F32 or F16)
     int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
+    CnnState cnn;
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
