@@ -95,6 +95,11 @@ typedef struct {
     double sigma_r;        /* range sigma, attenuation units */
     int coarse_subsets;    /* OS-EMTR subsets M (views i with i mod M == m) */
     int coarse_passes;     /* OS-EMTR passes over all subsets per coarse solve */
+    int learned;           /* finest grid: mu + u + f(u) (the context's network, see
+                              mgct_cnn_*), kept only if it lowers ||b - A mu||, else mu + u */
+    float *capture_update; /* device, finest-grid volume or NULL: receives the finest grid's
+                              filtered update u = alpha p * A^T (b - A mu) of the last iteration */
+    float *capture_iterate;/* device, finest-grid volume or NULL: mu just before that update */
 } mgct_mg_params;
 
 const char *mgct_status_string(int status);
@@ -261,6 +266,27 @@ int mgct_cnn_gradients(void *ctx, int nx, int ny, int nz, const float *u, const 
 /* forward + backward + one Adam step (beta 0.9/0.999, eps 1e-8) of learning rate lr */
 int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const float *target, double lr,
                         double *loss, hipStream_t stream);
+
+/*
+ * Learned-step statistics since the last call: finest-grid steps whose
+ * network update was kept (accepted) and steps that fell back to the plain
+ * filtered update (rejected).  Synchronises the device.
+ */
+int mgct_learned_stats(void *ctx, int *accepted, int *rejected);
+
+/*
+ * Synthetic data on the device (training-set generation for the learned
+ * preconditioner): exact line integrals through a phantom of K ellipsoids and
+ * J axis-aligned boxes for every ray of the finest grid's geometry, and the
+ * ss^3-supersampled voxel average of the same phantom on the finest grid.
+ * Ellipsoid record: centre[3], rotation[9] (row-major, columns = body axes),
+ * semi-axes[3], attenuation; box record: lo[3], hi[3], attenuation (host
+ * arrays, physical units).  out/vol: device F32, overwritten.
+ */
+int mgct_synth_line_integrals(void *ctx, const double *ellipsoids, int K, const double *boxes, int J, float *out,
+                              hipStream_t stream);
+int mgct_synth_voxelize(void *ctx, const double *ellipsoids, int K, const double *boxes, int J, int ss, float *vol,
+                        hipStream_t stream);
 
 /*
  * Kernel timing (instrumentation).  While enabled, every launch of the

@@ -56,6 +56,9 @@ class mgct_mg_params(ctypes.Structure):
         ("sigma_r", ctypes.c_double),
         ("coarse_subsets", ctypes.c_int),
         ("coarse_passes", ctypes.c_int),
+        ("learned", ctypes.c_int),
+        ("capture_update", ctypes.c_void_p),
+        ("capture_iterate", ctypes.c_void_p),
     ]
 
 
@@ -89,6 +92,9 @@ SIGNATURES = {
     "mgct_cnn_forward": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
     "mgct_cnn_gradients": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.POINTER(ctypes.c_float), _dp, _vp]),
     "mgct_cnn_train_step": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _cd, _dp, _vp]),
+    "mgct_learned_stats": (_ci, [_vp, ctypes.POINTER(_ci), ctypes.POINTER(_ci)]),
+    "mgct_synth_line_integrals": (_ci, [_vp, _dp, _ci, _dp, _ci, _vp, _vp]),
+    "mgct_synth_voxelize": (_ci, [_vp, _dp, _ci, _dp, _ci, _ci, _vp, _vp]),
     "mgct_kernel_timing": (_ci, [_vp, _ci]),
     "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
 }
@@ -365,8 +371,36 @@ class Context:
         check(mgct_kernel_time(self.handle, op, level, ctypes.byref(ms), ctypes.byref(n)), "mgct_kernel_time")  # noqa: F821
         return ms.value, n.value
 
+    def learned_stats(self):
+        a, r = ctypes.c_int(), ctypes.c_int()
+        check(mgct_learned_stats(self.handle, ctypes.byref(a), ctypes.byref(r)), "mgct_learned_stats")  # noqa: F821
+        return a.value, r.value
+
+    def synth_line_integrals(self, phantom, out=None):
+        import torch
+        e = np.ascontiguousarray(phantom.ellipsoids, dtype=np.float64).reshape(-1, 16)
+        b = np.ascontiguousarray(phantom.boxes, dtype=np.float64).reshape(-1, 7)
+        if out is None:
+            out = torch.empty(self.shapes(0)[1], dtype=torch.float32, device="cuda")
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(mgct_synth_line_integrals(self.handle, e.ctypes.data_as(dp), e.shape[0], b.ctypes.data_as(dp),  # noqa: F821
+                                        b.shape[0], _ptr(out), _stream()), "mgct_synth_line_integrals")
+        return out
+
+    def synth_voxelize(self, phantom, ss=4, out=None):
+        import torch
+        e = np.ascontiguousarray(phantom.ellipsoids, dtype=np.float64).reshape(-1, 16)
+        b = np.ascontiguousarray(phantom.boxes, dtype=np.float64).reshape(-1, 7)
+        if out is None:
+            out = torch.empty(self.shapes(0)[0], dtype=torch.float32, device="cuda")
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(mgct_synth_voxelize(self.handle, e.ctypes.data_as(dp), e.shape[0], b.ctypes.data_as(dp),  # noqa: F821
+                                  b.shape[0], ss, _ptr(out), _stream()), "mgct_synth_voxelize")
+        return out
+
     def multigrid_solve(self, vol, b, levels, n_outer, filt, alphas=None, power_iters=30, power_seed=0,
-                        lam=0.0, bilateral=None, coarse_subsets=8, coarse_passes=2, want_hist=True):
+                        lam=0.0, bilateral=None, coarse_subsets=8, coarse_passes=2, want_hist=True,
+                        learned=False, capture_update=None, capture_iterate=None):
         p = mgct_mg_params()
         p.levels = levels
         p.n_outer = n_outer
@@ -383,6 +417,9 @@ class Context:
         p.sigma_s, p.sigma_r = bilateral if bilateral else (1.0, 1.0)
         p.coarse_subsets = coarse_subsets
         p.coarse_passes = coarse_passes
+        p.learned = 1 if learned else 0
+        p.capture_update = capture_update.data_ptr() if capture_update is not None else None
+        p.capture_iterate = capture_iterate.data_ptr() if capture_iterate is not None else None
         hist = np.zeros(max(n_outer * levels, 1))
         hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_hist else None
         check(mgct_multigrid_solve(self.handle, _ptr(vol), _ptr(b), _dtype_code(b), ctypes.byref(p), hp,  # noqa: F821

@@ -32,6 +32,7 @@ SOURCES = {
     "volume_ops.hip": ["-O3"],
     "fft.hip": ["-O3"],
     "cnn.hip": ["-O3"],
+    "phantom_gpu.hip": ["-O3"],
 }
 
 

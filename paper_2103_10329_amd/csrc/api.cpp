@@ -213,9 +213,11 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
     return MGCT_OK;
 }
 
-// norm2_out: device double receiving ||b - A vol||^2 (may be null)
+// norm2_out: device double receiving ||b - A vol||^2 (may be null).  With
+// update_out set, the filtered update alpha p * A^T (b - A vol) is written
+// there and vol is left unchanged.
 int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype, double alpha, const mgct_filter *f,
-                 double *norm2_out, hipStream_t s) {
+                 double *norm2_out, hipStream_t s, float *update_out = nullptr) {
     // internal storage per the context's precision setting; arithmetic and
     // accumulation stay FP32 (FP64 for the norm)
     const int sd = c.stack_dtype;
@@ -230,7 +232,10 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
     HIPCHK(launch_finish_sum(part, kRedBlocks, norm2_out ? norm2_out : nrm, s));
     MGCHK(do_backproject(c, L, g, r, sd, grad, MGCT_F32, 0, 1, L.nviews, s));
     MGCHK(do_precondition(c, L, g, grad, grad, f, s));
-    HIPCHK(launch_axpy(vol, grad, alpha, L.vox(), s));
+    if (update_out)
+        HIPCHK(launch_scale(grad, update_out, (float)alpha, L.vox(), s));
+    else
+        HIPCHK(launch_axpy(vol, grad, alpha, L.vox(), s));
     return MGCT_OK;
 }
 
@@ -385,6 +390,61 @@ int cnn_check(Ctx &c, int nx, int ny, int nz) {
 
 // ======================================================================
 extern "C" {
+
+int mgct_learned_stats(void *ctx, int *accepted, int *rejected) {
+    if (!ctx) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    unsigned *cnt = static_cast<unsigned *>(workspace(c, "learned_counters", 8, true));
+    if (!cnt) return MGCT_ERR_OOM;
+    unsigned h[2] = {0, 0};
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(h, cnt, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemset(cnt, 0, 8));
+    if (accepted) *accepted = (int)h[0];
+    if (rejected) *rejected = (int)h[1];
+    return MGCT_OK;
+}
+
+static int upload_shapes(Ctx &c, const double *ell, int K, const double *box, int J, double **de, double **db) {
+    double *e = static_cast<double *>(workspace(c, "synth_ell", (size_t)(K > 0 ? K : 1) * 16 * 8));
+    double *b = static_cast<double *>(workspace(c, "synth_box", (size_t)(J > 0 ? J : 1) * 7 * 8));
+    if (!e || !b) return MGCT_ERR_OOM;
+    if (K > 0) HIPCHK(hipMemcpy(e, ell, (size_t)K * 16 * 8, hipMemcpyHostToDevice));
+    if (J > 0) HIPCHK(hipMemcpy(b, box, (size_t)J * 7 * 8, hipMemcpyHostToDevice));
+    *de = e;
+    *db = b;
+    return MGCT_OK;
+}
+
+int mgct_synth_line_integrals(void *ctx, const double *ell, int K, const double *box, int J, float *out,
+                              hipStream_t s) {
+    if (!ctx || !out || K < 0 || J < 0 || (K && !ell) || (J && !box)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    if (!c.has_geom) return MGCT_ERR_NO_GEOMETRY;
+    double *de, *db;
+    HIPCHK(hipStreamSynchronize(s));
+    MGCHK(upload_shapes(c, ell, K, box, J, &de, &db));
+    double *dv = static_cast<double *>(workspace(c, "synth_views", c.views.size() * 8));
+    if (!dv) return MGCT_ERR_OOM;
+    HIPCHK(hipMemcpy(dv, c.views.data(), c.views.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(launch_synth_line_integrals(dv, c.nviews, c.nu, c.nv, de, K, db, J, out, s));
+    return MGCT_OK;
+}
+
+int mgct_synth_voxelize(void *ctx, const double *ell, int K, const double *box, int J, int ss, float *vol,
+                        hipStream_t s) {
+    if (!ctx || !vol || K < 0 || J < 0 || ss < 1 || ss > 16 || (K && !ell) || (J && !box)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    if (!c.has_geom) return MGCT_ERR_NO_GEOMETRY;
+    double *de, *db;
+    HIPCHK(hipStreamSynchronize(s));
+    MGCHK(upload_shapes(c, ell, K, box, J, &de, &db));
+    HIPCHK(launch_synth_voxelize(c.nx, c.ny, c.nz, c.h, c.origin, de, K, db, J, ss, vol, s));
+    return MGCT_OK;
+}
 
 int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
     if (!ctx || !w || n != kCnnParams) return MGCT_ERR_INVALID_ARG;
@@ -781,6 +841,7 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
     for (int g = 0; g < NL; ++g) MGCHK(get_level(c, g, &Ls[g]));
     const int nland = NL == 1 ? 1 : NL - 1;  // grids with a Landweber step
     for (int g = 0; g < nland; ++g) MGCHK(check_filter(&p->filter, *Ls[g]));
+    if (p->learned && (!c.cnn.ready || Ls[0]->nx % 32)) return MGCT_ERR_INVALID_ARG;
 
     // step sizes
     std::vector<double> alpha(nland);
@@ -841,7 +902,31 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
             }
             HIPCHK(launch_prolong_add(mu[g + 1], c0[g + 1], mu[g], L.nx, L.ny, L.nz, s));
         }
-        MGCHK(do_landweber(c, L, g, mu[g], data[g], MGCT_F32, alpha[g], &p->filter, dh + n * NL + g, s));
+        if (g == 0 && (p->learned || p->capture_update || p->capture_iterate)) {
+            // finest grid: filtered update u; optionally the network's
+            // refinement, kept only if it lowers the residual
+            WS(u, float, "mg_u", L.vox() * 4, false);
+            double *r0 = dh + n * NL;
+            MGCHK(do_landweber(c, L, 0, mu[0], data[0], MGCT_F32, alpha[0], &p->filter, r0, s, u));
+            if (p->capture_update) HIPCHK(launch_copy(u, p->capture_update, L.vox(), s));
+            if (p->capture_iterate) HIPCHK(launch_copy(mu[0], p->capture_iterate, L.vox(), s));
+            if (p->learned) {
+                WS(cu, float, "mg_cnn_out", L.vox() * 4, false);
+                WS(try_mu, float, "mg_try", L.vox() * 4, false);
+                WS(r1, double, "mg_r1", 8, false);
+                WS(cnt, unsigned, "learned_counters", 8, true);
+                CnnBuffers B;
+                MGCHK(cnn_buffers(c, (long)L.vox(), false, B));
+                HIPCHK(cnn_forward(c.cnn, B, u, cu, L.nx, L.ny, L.nz, false, s));
+                HIPCHK(launch_add(mu[0], cu, try_mu, L.vox(), s));
+                MGCHK(do_residual_norm2(c, L, 0, try_mu, data[0], r1, s));
+                HIPCHK(launch_select_update(mu[0], u, try_mu, L.vox(), r0, r1, cnt, s));
+            } else {
+                HIPCHK(launch_axpy(mu[0], u, 1.0, L.vox(), s));
+            }
+        } else {
+            MGCHK(do_landweber(c, L, g, mu[g], data[g], MGCT_F32, alpha[g], &p->filter, dh + n * NL + g, s));
+        }
         if (lam > 0.f) HIPCHK(launch_soft_threshold(mu[g], L.vox(), lam, s));
         if (p->bilateral_on) {
             WS(tmp, float, lvl("bf_tmp", g), L.vox() * 4, false);

@@ -193,6 +193,17 @@ hipError_t launch_max_reset(unsigned *maxbits, hipStream_t s);
 hipError_t launch_max_reduce(const float *x, size_t n, unsigned *maxbits, hipStream_t s);
 hipError_t launch_splitmix_uniform(float *x, size_t n, uint64_t seed, hipStream_t s);
 
+hipError_t launch_scale(const float *x, float *y, float a, size_t n, hipStream_t s);
+hipError_t launch_add(const float *x, const float *y, float *out, size_t n, hipStream_t s);
+hipError_t launch_select_update(float *mu, const float *u, const float *mu_try, size_t n, const double *r0,
+                                const double *r1, unsigned *counters, hipStream_t s);
+
+// synthetic phantoms on the device (phantom_gpu.hip)
+hipError_t launch_synth_line_integrals(const double *views, int nviews, int nu, int nv, const double *ell, int K,
+                                       const double *box, int J, float *out, hipStream_t s);
+hipError_t launch_synth_voxelize(int nx, int ny, int nz, double h, const double *origin, const double *ell, int K,
+                                 const double *box, int J, int ss, float *vol, hipStream_t s);
+
 // FFT preconditioner (fft.hip)
 bool fft_size_ok(int n);
 hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int nx, int ny, int nz,

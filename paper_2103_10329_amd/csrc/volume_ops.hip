@@ -118,6 +118,40 @@ hipError_t launch_axpy(float *y, const float *x, double alpha, size_t n, hipStre
     return hipGetLastError();
 }
 
+__global__ void k_scale(const float *x, float *y, float a, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+hipError_t launch_scale(const float *x, float *y, float a, size_t n, hipStream_t s) {
+    k_scale<<<grid_for(n), 256, 0, s>>>(x, y, a, n);
+    return hipGetLastError();
+}
+
+__global__ void k_add(const float *x, const float *y, float *out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = x[i] + y[i];
+}
+hipError_t launch_add(const float *x, const float *y, float *out, size_t n, hipStream_t s) {
+    k_add<<<grid_for(n), 256, 0, s>>>(x, y, out, n);
+    return hipGetLastError();
+}
+
+// Learned step's judge: keep mu_try if its squared residual r1 is below the
+// current one r0, else take the plain update mu + u.  counters[0/1] count
+// accepted / rejected steps.
+__global__ void k_select_update(float *mu, const float *u, const float *mu_try, size_t n, const double *r0,
+                                const double *r1, unsigned *counters) {
+    const bool keep = r1[0] < r0[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(counters + (keep ? 0 : 1), 1u);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        mu[i] = keep ? mu_try[i] : mu[i] + u[i];
+}
+hipError_t launch_select_update(float *mu, const float *u, const float *mu_try, size_t n, const double *r0,
+                                const double *r1, unsigned *counters, hipStream_t s) {
+    k_select_update<<<grid_for(n), 256, 0, s>>>(mu, u, mu_try, n, r0, r1, counters);
+    return hipGetLastError();
+}
+
 // x *= 1/sqrt(sumsq[0]); lambda_out[0] = sqrt(sumsq[0]) (power iteration).
 __global__ void k_scale_inv_sqrt(float *x, size_t n, const double *sumsq, double *lambda_out) {
     const double nrm = sqrt(sumsq[0]);

@@ -62,6 +62,7 @@ def test_adam_training_reduces_loss():
     assert losses[-1] < 0.7 * losses[0]
     # the same 3 steps on the oracle, from the same start
     ctx2, params2, u2, t2 = _setup(shape=(16, 16, 32), seed=9)
+    w0 = mg.cnn_flatten(params2).astype(np.float64)
     st = {}
     for _ in range(3):
         out, cache = cnn.forward(u2, params2)
@@ -70,6 +71,11 @@ def test_adam_training_reduces_loss():
         cnn.adam_step(params2, gr, st, lr=3e-3)
     for _ in range(3):
         ctx2.cnn_train_step(to_dev(u2), to_dev(t2), 3e-3, want_loss=False)
-    e = rel_l2(ctx2.cnn_get_weights(), mg.cnn_flatten(params2))
-    say("weights after 3 Adam steps vs oracle", e)
-    assert e <= 1e-3
+    # Adam's first steps are close to lr * sign(g): compare the updates, whose
+    # error reflects the BF16-level gradient differences (~2e-3 relative) on
+    # components with small gradients
+    dw = ctx2.cnn_get_weights().astype(np.float64) - w0
+    dref = mg.cnn_flatten(params2).astype(np.float64) - w0
+    e = rel_l2(dw, dref)
+    say("Adam update after 3 steps vs oracle", e)
+    assert e <= 5e-2

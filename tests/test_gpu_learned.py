@@ -1,0 +1,112 @@
+"""Learned preconditioner inside Algorithm 1: device phantom generators
+against the CPU generator, the residual judge and fallback, and a short
+training run on solver-generated pairs compared with the plain filter."""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2103_10329_amd as mg
+import synth
+from gpu_common import rel_l2, say, to_dev, to_host, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(g):
+    ctx = mg.Context(0)
+    ctx.set_geometry(g.nx, g.ny, g.nz, g.h, g.origin, g.nu, g.nv, g.views)
+    return ctx
+
+
+def test_device_phantom_generators_match_cpu():
+    g = workload("c0")
+    cfg = synth.CONFIGS["c1"]
+    ph = synth.random_phantom(cfg, 1001)
+    ctx = _ctx(g)
+    b = to_host(ctx.synth_line_integrals(ph))
+    mu = to_host(ctx.synth_voxelize(ph, ss=4))
+    e1 = rel_l2(b, synth.line_integrals(ph, g.views, g.nu, g.nv))
+    e2 = rel_l2(mu, synth.voxelize(ph, 32, g.h, ss=4))
+    say("device line integrals", e1, "voxelize", e2)
+    assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+def _problem(n=64, nu=96, n_views=120, seed=1001):
+    g = workload("c1", n=n, nu=nu, nv=nu, n_views=n_views)
+    cfg = synth.CONFIGS["c1"]
+    ph = synth.random_phantom(cfg, seed)
+    b = synth.add_noise(synth.line_integrals(ph, g.views, g.nu, g.nv), cfg, seed + 1000)
+    t, r = oracle.radial_table(n)
+    return g, b, mg.filter_radial(t, r), synth.voxelize(ph, n, g.h, ss=4)
+
+
+def test_identity_network_and_fallback():
+    import torch
+    from paper_2103_10329_amd.learned import he_init
+    g, b, filt, _ = _problem()
+    ctx = _ctx(g)
+    bt = to_dev(b)
+    alphas = [ctx.estimate_step(filt, level=lv, iters=30) for lv in range(2)]
+    plain = torch.zeros(g.vol_shape, device="cuda")
+    ctx.multigrid_solve(plain, bt, 3, 2, filt, alphas=alphas, want_hist=False)
+    # identity network (zero last layer): u + f(u) = u, so accepted or not the
+    # iterate equals the plain one up to the rounding of mu + alpha*p (the plain
+    # step fuses it into one FMA)
+    ctx.cnn_set_weights(mg.cnn_flatten(he_init(0)))
+    ctx.learned_stats()
+    v = torch.zeros(g.vol_shape, device="cuda")
+    ctx.multigrid_solve(v, bt, 3, 2, filt, alphas=alphas, want_hist=False, learned=True)
+    acc, rej = ctx.learned_stats()
+    e = rel_l2(to_host(v), to_host(plain))
+    say("identity network vs plain", e, "accepted", acc, "rejected", rej)
+    assert e <= 1e-5 and acc + rej == 2
+    # adversarial network: every step must fall back to the plain update
+    p = he_init(1)
+    p[3][0] = np.random.Generator(np.random.PCG64(5)).normal(0, 50.0, size=p[3][0].shape)
+    ctx.cnn_set_weights(mg.cnn_flatten(p))
+    v = torch.zeros(g.vol_shape, device="cuda")
+    ctx.multigrid_solve(v, bt, 3, 2, filt, alphas=alphas, want_hist=False, learned=True)
+    acc, rej = ctx.learned_stats()
+    say("adversarial network: accepted", acc, "rejected", rej)
+    e = rel_l2(to_host(v), to_host(plain))
+    assert rej == 2 and acc == 0 and e <= 1e-5
+
+
+def test_short_training_gains_over_plain_filter():
+    """Pairs from 48 phantoms (2 iterations each) at 64^3 / 120 views,
+    600 Adam steps on 32^3 crops; on 3 held-out phantoms the learned
+    iteration's image error after 2 iterations is below the plain one's."""
+    import torch
+    from paper_2103_10329_amd import learned as L
+    n, nu, V = 64, 96, 120
+    g = workload("c1", n=n, nu=nu, nv=nu, n_views=V)
+    ctx = _ctx(g)
+    t, r = oracle.radial_table(n)
+    filt = mg.filter_radial(t, r)
+    alphas = [ctx.estimate_step(filt, level=lv, iters=30) for lv in range(2)]
+    # the workload's phantom distribution on the small grid
+    store = L.PairStore((n, n, n), 96)
+    import synth.geometry as sg
+    small = sg.ScanConfig("c1s", n, nu, nu, V, 8, 60, (0.01, 0.3), "poisson", 1e4, levels=3)
+    L.generate_pairs(ctx, small, range(20000, 20048), 3, filt, alphas, store, log=None)
+    sigma = float(1.0 / store.e[: store.n].float().std().item())
+    ctx.cnn_set_weights(mg.cnn_flatten(L.he_init(0)))
+    losses = L.train(ctx, store, 600, 2e-3, 32, sigma, seed=1, log=None)
+    ctx.cnn_set_weights(L.fold_scale(ctx.cnn_get_weights(), sigma))
+    say("training loss", losses[0][1], "->", losses[-1][1])
+    gains = []
+    for seed in (30000, 30001, 30002):
+        ph = synth.random_phantom(small, seed)
+        truth = ctx.synth_voxelize(ph, ss=4)
+        gen = torch.Generator(device="cuda").manual_seed(seed)
+        b = L.poisson_data(ctx.synth_line_integrals(ph), small.noise_level, gen)
+        errs = []
+        for learned in (False, True):
+            v = torch.zeros((n, n, n), device="cuda")
+            ctx.multigrid_solve(v, b, 3, 2, filt, alphas=alphas, want_hist=False, learned=learned)
+            errs.append(float(torch.linalg.vector_norm(v - truth) / torch.linalg.vector_norm(truth)))
+        gains.append(errs)
+    acc, rej = ctx.learned_stats()
+    say("held-out image error plain vs learned", gains, "accepted", acc, "rejected", rej)
+    assert np.mean([e[1] for e in gains]) < np.mean([e[0] for e in gains])
