@@ -45,11 +45,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sirt", action="store_true")
     ap.add_argument("--sirt-cap", type=int, default=1000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (views would shard across "
               "GPUs with one sum-exchange of A^T per step; see the design notes).", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
 
@@ -59,7 +65,7 @@ def main():
     cfg = synth.CONFIGS[WORKLOAD]
     n, V, nu, nv = cfg.n, cfg.n_views, cfg.nu, cfg.nv
     t0 = time.time()
-    d = synth.make_dataset(WORKLOAD, truth=False)
+    d = synth.make_dataset(WORKLOAD, truth=not args.no_sirt)
     log("data %.1fs" % (time.time() - t0))
     views = d["views"]
 
@@ -105,7 +111,10 @@ def main():
         for g in range(levels):
             ms, cnt = ctx.kernel_time(op, g)
             if cnt:
-                kt["%s@%d" % (name, g)] = {"ms_avg": ms / cnt, "launches": cnt}
+                e = {"ms_avg": ms / cnt, "launches": cnt}
+                if name in ("project", "backproject"):
+                    e["gvox_views_s"] = (n >> g) ** 3 * V / (ms / cnt * 1e-3) / 1e9
+                kt["%s@%d" % (name, g)] = e
     # per-view-stream bytes of one fine-grid application (FP32 volume and data)
     bytes_per_launch = V * (n ** 3 * 4 + nu * nv * 4)
     tA = kt["project@0"]["ms_avg"]
@@ -113,15 +122,15 @@ def main():
     dom = "backproject@0" if tB >= tA else "project@0"
     t_dom = kt[dom]["ms_avg"] * 1e-3
     achieved = bytes_per_launch / t_dom / 1e9
-    roofline = {"kernel": "k_backproject_sep" if dom.startswith("back") else "k_project",
-                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+    kname = "k_backproject_sep" if dom.startswith("back") else "k_project_sep"
+    roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
     a_at = n ** 3 * V / ((tA + tB) * 1e-3) / 1e9
 
     out = {
-        "metric": "A+Aᵀ Gvoxel·views/s (% HBM roofline); time-to-residual vs plain SIRT",
-        "value": value, "unit": "Gvoxel·views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": "A+A\u1d40 Gvoxel\u00b7views/s (% HBM roofline); time-to-residual vs plain SIRT",
+        "value": value, "unit": "Gvoxel\u00b7views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "pmg-128^3-360x192^2-L3-radial", "volume": [n, n, n], "views": V,
@@ -129,48 +138,147 @@ def main():
                    "soft_threshold": lam, "bilateral": list(bil), "coarse": "OS-EMTR M=8 x2"},
         "roofline": roofline,
         "a_plus_at_kernels_gvox_views_s": a_at,
+        "a_plus_at_hbm_frac": 2 * bytes_per_launch / ((tA + tB) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms": kt,
         "step_size_estimate_s": t_alpha,
     }
 
-    # time-to-residual: 2 PMG iterations from zero vs plain SIRT from zero
     if not args.no_sirt:
-        def resid(v):
-            p = ctx.project(v)
-            return float(torch.linalg.vector_norm((b - p).double()).item())
-
-        bnorm = float(torch.linalg.vector_norm(b.double()).item())
-        v = torch.zeros((n, n, n), device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(2):
-            step(v)
-        torch.cuda.synchronize()
-        t_pmg = time.perf_counter() - t0
-        r_pmg = resid(v)
-        a_sirt = ctx.estimate_step(None, level=0, iters=30, seed=0)
-        vs = torch.zeros((n, n, n), device="cuda")
-        k, t_sirt, r_s = 0, 0.0, None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        while k < args.sirt_cap:
-            r_before = ctx.landweber_step(vs, b, a_sirt, None, want_norm=True)  # ||b - A mu_k||
-            if r_before <= r_pmg:
-                break
-            k += 1
-        torch.cuda.synchronize()
-        t_sirt = time.perf_counter() - t0
-        out["time_to_residual"] = {
-            "target_rel_residual": r_pmg / bnorm, "pmg_iterations": 2, "pmg_s": t_pmg,
-            "sirt_iterations": k if k < args.sirt_cap else None, "sirt_cap": args.sirt_cap,
-            "sirt_s": t_sirt, "sirt_alpha": a_sirt,
-            "speedup": (t_sirt / t_pmg) if k < args.sirt_cap else None}
-        log("time-to-residual", out["time_to_residual"])
+        out.update(quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args))
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, views, alphas, lam, bil)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
+    """Time-to-residual and image error.  Target: the relative residual
+    ||b - A mu|| / ||b|| of 2 iterations of Algorithm 1 from zero.  Plain SIRT
+    (unfiltered Landweber, eq. 2) and full-resolution OS-EMTR (eq. 3, 8
+    subsets per iteration) run from zero until they reach it.  Image error:
+    masked relative L2 error against the phantom (cylinder of radius 14.4,
+    |z| <= 12) for SIRT after 2 and 10 iterations, OS-EMTR after 2 and 10,
+    Algorithm 1 after 2 plain and, with trained weights present, learned."""
+    import torch
+
+    import synth
+    from paper_2103_10329_amd import learned as lrn
+    cfg = synth.CONFIGS[WORKLOAD]
+    n = cfg.n
+    truth = torch.from_numpy(d["mu"].astype(np.float32)).cuda()
+    mask = torch.from_numpy(synth.evaluation_mask(n, cfg.h)).cuda()
+    tm = truth[mask].double()
+
+    def err(v):
+        return float(torch.linalg.vector_norm(v[mask].double() - tm) / torch.linalg.vector_norm(tm))
+
+    def resid(v):
+        return float(torch.linalg.vector_norm((b - ctx.project(v)).double()).item())
+
+    bnorm = float(torch.linalg.vector_norm(b.double()).item())
+    v = torch.zeros((n, n, n), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        step(v)
+    torch.cuda.synchronize()
+    t_pmg = time.perf_counter() - t0
+    r_pmg = resid(v)
+    errors = {"pmg_plain_2": err(v)}
+    pmg = {"iterations": 2, "seconds": t_pmg, "rel_residual": r_pmg / bnorm}
+
+    # learned step (weights trained by paper_2103_10329_amd.learned on the
+    # same phantom distribution), same parameters otherwise
+    if os.path.exists(lrn.DEFAULT_WEIGHTS):
+        ctx.cnn_set_weights(lrn.load_weights())
+        vl = torch.zeros((n, n, n), device="cuda")
+        ctx.multigrid_solve(vl, b, levels, 1, filt, alphas=alphas, lam=lam, bilateral=bil,
+                            want_hist=False, learned=True)  # warm-up of the network buffers
+        vl.zero_()
+        ctx.learned_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.multigrid_solve(vl, b, levels, 2, filt, alphas=alphas, lam=lam, bilateral=bil,
+                            want_hist=False, learned=True)
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t0
+        acc, rej = ctx.learned_stats()
+        errors["pmg_learned_2"] = err(vl)
+        pmg["learned"] = {"seconds": t_l, "rel_residual": resid(vl) / bnorm, "accepted": acc, "rejected": rej}
+
+    # SIRT: from zero until ||b - A mu_k|| <= target
+    a_sirt = ctx.estimate_step(None, level=0, iters=30, seed=0)
+    vs = torch.zeros((n, n, n), device="cuda")
+    k = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while k < args.sirt_cap:
+        if ctx.landweber_step(vs, b, a_sirt, None, want_norm=True) <= r_pmg:  # ||b - A mu_k||
+            break
+        k += 1
+    torch.cuda.synchronize()
+    t_sirt = time.perf_counter() - t0
+    vs.zero_()
+    for it in range(1, 11):
+        ctx.landweber_step(vs, b, a_sirt, None, want_norm=False)
+        if it in (2, 10):
+            errors["sirt_%d" % it] = err(vs)
+
+    # OS-EMTR at full resolution, 8 subsets per iteration
+    vo = torch.zeros((n, n, n), device="cuda")
+    cap_os = min(args.sirt_cap, 200)
+    reached, t_os = None, 0.0
+    for ko in range(1, cap_os + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.osemtr(vo, b, subsets=8, passes=1, level=0)
+        torch.cuda.synchronize()
+        t_os += time.perf_counter() - t0
+        if ko in (2, 10):
+            errors["osemtr_%d" % ko] = err(vo)
+        if reached is None and resid(vo) <= r_pmg:
+            reached = (ko, t_os)
+        if reached is not None and ko >= 10:
+            break
+    ttr = {"target_rel_residual": r_pmg / bnorm, "pmg": pmg,
+           "sirt_iterations": k if k < args.sirt_cap else None, "sirt_cap": args.sirt_cap,
+           "sirt_s": t_sirt, "sirt_alpha": a_sirt,
+           "speedup_vs_sirt": (t_sirt / t_pmg) if k < args.sirt_cap else None,
+           "osemtr_iterations": reached[0] if reached else None, "osemtr_s": reached[1] if reached else None,
+           "osemtr_cap": cap_os}
+    log("time-to-residual", ttr)
+    log("masked image error", errors)
+    return {"time_to_residual": ttr, "image_error_masked": errors}
+
+
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes, scaled by the same counters on a plain copy of known size, per
+# launch; valid only for the kernel source it was measured on.
+TRAFFIC = {}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if not t:
+        return None
+    src = os.path.join(ROOT, "paper_2103_10329_amd", "csrc", "joseph.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t["bytes_per_launch"]
+
+
+def copy_calibration(size_mib=1024, reps=5):
+    """A plain device copy of known size (for scaling the HBM byte counters)."""
+    import torch
+    x = torch.ones(size_mib << 18, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": size_mib << 20, "reps": reps}), flush=True)
 
 
 def cpu_baseline(d, views, alphas, lam, bil):

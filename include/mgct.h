@@ -247,7 +247,7 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
                          double *resid_hist, hipStream_t stream);
 
 /*
- * Learned preconditioner (spec extension; refines eq. 4's filtered
+ * Learned preconditioner (an extension beyond the paper's fixed filters; refines eq. 4's filtered
  * update u): out = u + f(u), f = four 3^3 convolutions 1 -> 16 -> 32 -> 32 -> 1
  * with zero "same" padding and erf-GELU after the first three.  Parameters:
  * one FP32 vector of MGCT_CNN_PARAMS values, W1 b1 W2 b2 W3 b3 W4 b4, each W

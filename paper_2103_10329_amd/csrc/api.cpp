@@ -252,37 +252,41 @@ int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b,
 int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int passes, hipStream_t s) {
     const size_t n = L.vox(), per = (size_t)L.nu * L.nv;
     const int maxsub = (L.nviews + M - 1) / M;
+    const int nsteps = passes * std::min(M, L.nviews);
     WS(ones, float, lvl("emtr_ones", g), n * 4, false);
     WS(pi, float, lvl("emtr_pi", g), L.rays() * 4, false);
     WS(l, float, lvl("emtr_l", g), maxsub * per * 4, false);
-    WS(nsrc, float, lvl("emtr_ns", g), maxsub * per * 4, false);
-    WS(dsrc, float, lvl("emtr_ds", g), maxsub * per * 4, false);
     WS(pt1, float, lvl("emtr_pt1", g), maxsub * per * 4, false);
     WS(num, float, lvl("emtr_num", g), n * 4, false);
     WS(den, float, lvl("emtr_den", g), n * 4, false);
-    WS(mx, unsigned, "emtr_max", 4, false);
+    WS(mx, unsigned, "emtr_max", (size_t)nsteps * 4, false);
     WS(pt0, float, lvl("pt", g), (size_t)L.nviews * per * 4, false);
-    // support projection A 1 (support = the whole grid)
-    HIPCHK(launch_fill(ones, n, 1.f, s));
-    MGCHK(do_project(c, L, g, ones, MGCT_F32, pi, MGCT_F32, 0, 1, L.nviews, s));
+    // support projection A 1 (support = the whole grid); depends only on the
+    // geometry and the storage precision, so it is kept until either changes
+    if (!c.pi_valid[g]) {
+        HIPCHK(launch_fill(ones, n, 1.f, s));
+        MGCHK(do_project(c, L, g, ones, MGCT_F32, pi, MGCT_F32, 0, 1, L.nviews, s));
+        c.pi_valid[g] = true;
+    }
+    // one max slot per subset step, cleared once (0.0f has all-zero bits)
+    HIPCHK(launch_fill(reinterpret_cast<float *>(mx), nsteps, 0.f, s));
+    int step = 0;
     for (int p = 0; p < passes; ++p) {
-        for (int m = 0; m < M && m < L.nviews; ++m) {
+        for (int m = 0; m < M && m < L.nviews; ++m, ++step) {
             const int nsub = (L.nviews - m + M - 1) / M;
             MGCHK(do_project(c, L, g, vol, MGCT_F32, l, MGCT_F32, m, M, nsub, s));
-            HIPCHK(launch_emtr_terms(l, b, pi, nsrc, dsrc, L, m, M, nsub, s));
-            HIPCHK(launch_scale_transpose_stack(nsrc, MGCT_F32, pt0, MGCT_F32, L, m, M, nsub, s));
-            HIPCHK(launch_scale_transpose_stack(dsrc, MGCT_F32, pt1, MGCT_F32, L, m, M, nsub, s));
+            HIPCHK(launch_emtr_terms_t(l, b, pi, pt0, pt1, L, m, M, nsub, s));
+            int nchunks = 1;
+            float *scratch = nullptr;
             if (L.separable) {
                 const size_t sb = backproject_scratch_bytes(L, nsub, 2);
-                float *scratch = nullptr;
                 if (sb) {
                     scratch = static_cast<float *>(workspace(c, lvl("bp_scratch2", g), sb, false));
                     if (!scratch) return MGCT_ERR_OOM;
                 }
-                HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s));
+                HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s, &nchunks));
             } else {
                 const size_t sb = backproject_gen_scratch_bytes(L, nsub);
-                float *scratch = nullptr;
                 if (sb) {
                     scratch = static_cast<float *>(workspace(c, lvl("bp_scratch", g), sb, false));
                     if (!scratch) return MGCT_ERR_OOM;
@@ -290,9 +294,10 @@ int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int pa
                 HIPCHK(launch_backproject_gen(pt0, MGCT_F32, num, scratch, L, m, M, nsub, s));
                 HIPCHK(launch_backproject_gen(pt1, MGCT_F32, den, scratch, L, m, M, nsub, s));
             }
-            HIPCHK(launch_max_reset(mx, s));
-            HIPCHK(launch_max_reduce(den, n, mx, s));
-            HIPCHK(launch_emtr_update(vol, num, den, n, mx, s));
+            const float *pn = nchunks > 1 ? scratch : nullptr;
+            const float *pd = nchunks > 1 ? scratch + (size_t)nchunks * n : nullptr;
+            HIPCHK(launch_emtr_reduce(pn, pd, num, den, n, nchunks, mx + step, s));
+            HIPCHK(launch_emtr_update(vol, num, den, n, mx + step, s));
         }
     }
     return MGCT_OK;
@@ -360,9 +365,8 @@ int cnn_buffers(Ctx &c, long n, bool train, CnnBuffers &B) {
     B.dz3 = (uint16_t *)get("cnn_dz3", n * 32 * 2);
     B.dz2 = (uint16_t *)get("cnn_dz2", n * 32 * 2);
     B.dz1 = (uint16_t *)get("cnn_dz1", n * 16 * 2);
-    B.dz1f = (float *)get("cnn_dz1f", n * 16 * 4);
     B.gT = (uint16_t *)get("cnn_gT", n * 32 * 2);
-    if (!B.z1 || !B.z2 || !B.z3 || !B.dout || !B.dz3 || !B.dz2 || !B.dz1 || !B.dz1f || !B.gT) return MGCT_ERR_OOM;
+    if (!B.z1 || !B.z2 || !B.z3 || !B.dout || !B.dz3 || !B.dz2 || !B.dz1 || !B.gT) return MGCT_ERR_OOM;
     return MGCT_OK;
 }
 
@@ -374,7 +378,7 @@ int cnn_train_scratch(Ctx &c, int nx, int ny, int nz, CnnBuffers &B) {
     B.xT = (uint16_t *)workspace(c, key, padded, true);
     const long n = (long)nx * ny * nz;
     const long rows = (long)ny * nz, nch = (rows + 15) / 16, nvb = (n + 4095) / 4096;
-    const size_t part = std::max((size_t)nch * 27 * 1024, (size_t)nvb * 865) * 4;
+    const size_t part = std::max({(size_t)nch * 27 * 1024, (size_t)nvb * 32, (size_t)(nx / 32) * nch * 865}) * 4;
     B.partial = (float *)workspace(c, "cnn_partial", part);
     if (!B.xT || !B.partial) return MGCT_ERR_OOM;
     return MGCT_OK;
@@ -647,6 +651,7 @@ int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const dou
         L = Level();
     }
     c.alpha_cache.clear();
+    for (bool &v : c.pi_valid) v = false;
     c.nx = nx; c.ny = ny; c.nz = nz; c.nu = nu; c.nv = nv; c.nviews = n_views;
     c.h = voxel;
     for (int k = 0; k < 3; ++k) c.origin[k] = origin[k];
@@ -663,6 +668,7 @@ int mgct_set_precision(void *ctx, int volume_copy_dtype, int stack_dtype) {
     Ctx &c = *as_ctx(ctx);
     c.vt_dtype = volume_copy_dtype;
     c.stack_dtype = stack_dtype;
+    for (bool &v : c.pi_valid) v = false;
     return MGCT_OK;
 }
 

@@ -161,44 +161,75 @@ __global__ __launch_bounds__(256) void k_conv4_bwd_input(const float *__restrict
     }
 }
 
-// Weight gradient of a layer with one input channel (layer 1: X = u, G = dz1
-// [v][16]) or one output channel (layer 4: X = h3 [v][32] BF16, G = dout):
-// grad[o] = sum_v X(v + off_t(o), c(o)) * G(v, c'(o)) over a block's chunk of
-// voxels; bias gradients (sum_v G) in the last slots.  partial[block][R].
+// Weight gradient of a layer with one input channel (layer 1: X = u FP32,
+// G = dz1 [v][16] BF16) or one output channel (layer 4: X = h3 [v][32] BF16,
+// G = dout FP32): grad[o] = sum_v X(v + off_t(o), c(o)) * G(v, c'(o)), plus
+// the bias gradients (sum_v G) in the last slots.  A block covers one 32-wide
+// x tile of `rpc` consecutive rows (y, z); per row it stages the 3 x 3
+// neighbouring rows of X (34 wide, zero outside the volume) and the row of G
+// in LDS, and each thread accumulates up to four parameters.
+// partial[block][R], block = rowchunk * (nx / 32) + xtile.  nx % 32 == 0.
 template <int MODE>  // 1: layer 1 (R = 16*27 + 16), 4: layer 4 (R = 32*27 + 1)
 __global__ __launch_bounds__(256) void k_wgrad_valu(const float *__restrict__ xf, const uint16_t *__restrict__ xh,
-                                                    const float *__restrict__ g, float *__restrict__ partial, Dims d,
-                                                    long chunk) {
+                                                    const uint16_t *__restrict__ gh, const float *__restrict__ gf,
+                                                    float *__restrict__ partial, Dims d, int rpc) {
     constexpr int R = MODE == 1 ? 16 * 27 + 16 : 32 * 27 + 1;
-    const long n = (long)d.nx * d.ny * d.nz;
-    const long v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
-    for (int o = threadIdx.x; o < R; o += blockDim.x) {
-        double acc = 0.0;
-        if (MODE == 1) {
-            if (o < 432) {
-                const int co = o / 27, t = o % 27;
-                for (long v = v0; v < v1; ++v) {
-                    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
-                    long q;
-                    if (tap_voxel(d, x, y, z, t, q)) acc += (double)(xf[q] * g[v * 16 + co]);
-                }
-            } else {
-                const int co = o - 432;
-                for (long v = v0; v < v1; ++v) acc += (double)g[v * 16 + co];
+    constexpr int C = MODE == 1 ? 1 : 32;    // channels of X
+    constexpr int CG = MODE == 1 ? 16 : 1;   // channels of G
+    constexpr int CS = MODE == 1 ? 1 : 33;   // LDS stride per x (one pad float against bank conflicts)
+    constexpr int NP = (R + 255) / 256;
+    __shared__ float xs[9][34 * CS];
+    __shared__ float gs[32 * CG];
+    const int nxt = d.nx / 32;
+    const int xt = blockIdx.x % nxt, rc = blockIdx.x / nxt;
+    const int x0 = xt * 32;
+    const int nrows = d.ny * d.nz;
+    const int r0 = rc * rpc, r1 = min(nrows, r0 + rpc);
+    float acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+    for (int row = r0; row < r1; ++row) {
+        const int y = row % d.ny, z = row / d.ny;
+        __syncthreads();  // previous row's reads are done
+        for (int e = threadIdx.x; e < 9 * 34 * C; e += 256) {
+            const int tr = e / (34 * C), rem = e % (34 * C);
+            const int xl = rem / C, c = rem % C;
+            const int yy = y + tr % 3 - 1, zz = z + tr / 3 - 1, xx = x0 + xl - 1;
+            float val = 0.f;
+            if (yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx) {
+                const long q = ((long)zz * d.ny + yy) * d.nx + xx;
+                val = MODE == 1 ? xf[q] : bf(xh[q * 32 + c]);
             }
-        } else {
-            if (o < 864) {
-                const int ci = o / 27, t = o % 27;
-                for (long v = v0; v < v1; ++v) {
-                    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
-                    long q;
-                    if (tap_voxel(d, x, y, z, t, q)) acc += (double)(bf(xh[q * 32 + ci]) * g[v]);
-                }
-            } else {
-                for (long v = v0; v < v1; ++v) acc += (double)g[v];
-            }
+            xs[tr][xl * CS + c] = val;
         }
-        partial[blockIdx.x * (long)R + o] = (float)acc;
+        const long gv = (long)row * d.nx + x0;
+        for (int e = threadIdx.x; e < 32 * CG; e += 256)
+            gs[e] = MODE == 1 ? bf(gh[gv * 16 + e]) : gf[gv + e];
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int o = threadIdx.x + 256 * p;
+            if (o >= R) continue;
+            float a = acc[p];
+            if (o < 27 * (MODE == 1 ? 16 : 32)) {
+                const int c2 = o / 27, t = o % 27;  // layer 1: c2 = co (of G); layer 4: c2 = ci (of X)
+                const int tr = t / 3, dx = t % 3;   // tr = 3 (dz + 1) + (dy + 1); LDS column x + dx
+                if (MODE == 1) {
+                    for (int x = 0; x < 32; ++x) a = fmaf(xs[tr][x + dx], gs[x * 16 + c2], a);
+                } else {
+                    for (int x = 0; x < 32; ++x) a = fmaf(xs[tr][(x + dx) * CS + c2], gs[x], a);
+                }
+            } else {
+                const int c2 = o - 27 * (MODE == 1 ? 16 : 32);
+                for (int x = 0; x < 32; ++x) a += gs[x * CG + c2];
+            }
+            acc[p] = a;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int o = threadIdx.x + 256 * p;
+        if (o < R) partial[blockIdx.x * (long)R + o] = acc[p];
     }
 }
 
@@ -335,25 +366,18 @@ __global__ void k_wgrad_mfma_sum(const float *__restrict__ partial, int nchunks,
 // db[co] = sum_v G[v][co] (BF16 channels-last), partial per block then summed.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ g, int C, long n, long chunk,
                                                    float *__restrict__ partial) {
+    // thread (voxel group vg, channel c), C divides 256: coalesced rows of g
+    const int c = threadIdx.x % C, vg = threadIdx.x / C, ng = 256 / C;
     const long v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
+    double acc = 0.0;
+    for (long v = v0 + vg; v < v1; v += ng) acc += (double)bf(g[v * C + c]);
     __shared__ double red[256];
-    for (int c = 0; c < C; ++c) {
-        double acc = 0.0;
-        for (long v = v0 + threadIdx.x; v < v1; v += blockDim.x) acc += (double)bf(g[v * C + c]);
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partial[blockIdx.x * (long)C + c] = (float)red[0];
-        __syncthreads();
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (vg == 0) {
+        for (int k = 1; k < ng; ++k) acc += red[k * C + c];
+        partial[blockIdx.x * (long)C + c] = (float)acc;
     }
-}
-
-__global__ void k_bf16_to_f32(const uint16_t *__restrict__ x, float *__restrict__ y, long n) {
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i < n) y[i] = bf(x[i]);
 }
 
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
@@ -399,11 +423,12 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     // layer 4
     const long vchunk = 4096;
     const int nvb = (int)((n + vchunk - 1) / vchunk);
-    k_wgrad_valu<4><<<nvb, 256, 0, s>>>(nullptr, B.h3, B.dout, B.partial, d, vchunk);
-    k_sum_partials<<<blocks(865), 256, 0, s>>>(B.partial, nvb, 865, grads + kW4, 0);
+    const int rows = ny * nz;
+    const int wrpc = 16, nwb = (nx / 32) * ((rows + wrpc - 1) / wrpc);
+    k_wgrad_valu<4><<<nwb, 256, 0, s>>>(nullptr, B.h3, nullptr, B.dout, B.partial, d, wrpc);
+    k_sum_partials<<<blocks(865), 256, 0, s>>>(B.partial, nwb, 865, grads + kW4, 0);
     k_conv4_bwd_input<<<vb, 256, 0, s>>>(B.dout, S.master, B.z3, B.dz3, d);
     // layer 3: weights (channels-first copies), bias, input gradient -> dz2
-    const int rows = ny * nz;
     const int rpc = 16, nch = (rows + rpc - 1) / rpc;
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz3, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 32), 256, 0, s>>>(B.h2, B.xT, 32, d);
@@ -421,9 +446,8 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     k_sum_partials<<<1, 256, 0, s>>>(B.partial, nvb, 32, grads + kB2, 0);
     k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz2, S.p2d, nullptr, B.z1, nullptr, B.dz1, 16, d);
     // layer 1 (input gradient not needed); dz1 holds GELU' * dh1 in BF16
-    k_bf16_to_f32<<<blocks(n * 16), 256, 0, s>>>(B.dz1, B.dz1f, n * 16);
-    k_wgrad_valu<1><<<nvb, 256, 0, s>>>(u, nullptr, B.dz1f, B.partial, d, vchunk);
-    k_sum_partials<<<blocks(448), 256, 0, s>>>(B.partial, nvb, 448, grads + kW1, 0);
+    k_wgrad_valu<1><<<nwb, 256, 0, s>>>(u, nullptr, B.dz1, nullptr, B.partial, d, wrpc);
+    k_sum_partials<<<blocks(448), 256, 0, s>>>(B.partial, nwb, 448, grads + kW1, 0);
     return hipGetLastError();
 }
 

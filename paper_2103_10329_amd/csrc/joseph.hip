@@ -465,7 +465,109 @@ hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, void *
     return hipGetLastError();
 }
 
+// OS-EMTR subset terms (eq. 3) fused with the transposition for the
+// back-projector: for ray (v = view0 + vl*step, a, b) with projection l,
+// data y and support projection pi, num = e^-l - e^-y and den = e^-l pi;
+// pt_num[vl][a][b] = num * L and pt_den[vl][a][b] = den * L with
+// L = h|D|/|D_m| (the ray-length factor of A^T).  l is [nsub][nv][nu];
+// y and pi are full stacks [V][nv][nu].
+__global__ __launch_bounds__(256) void k_emtr_terms_t(const float *__restrict__ l, const float *__restrict__ y,
+                                                      const float *__restrict__ pi, float *__restrict__ pt_num,
+                                                      float *__restrict__ pt_den, const ViewIdx *__restrict__ views,
+                                                      const uint8_t *__restrict__ axis, long axis_view_stride,
+                                                      long axis_row_stride, int nu, int nv, double h, int view0,
+                                                      int view_step) {
+    __shared__ float tn[64][65], td[64][65];
+    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64, vl = blockIdx.z;
+    const int v = view0 + vl * view_step;
+    const ViewIdx &V = views[v];
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+        const int bl = (t >> 6) + 4 * r, al = t & 63;
+        const int b = b0 + bl, a = a0 + al;
+        float vn = 0.f, vd = 0.f;
+        if (a < nu && b < nv) {
+            double D[3];
+            const double len = ray_setup(V, nu, nv, a, b, D);
+            const int m = axis[v * axis_view_stride + b * axis_row_stride + a];
+            const float scale = (float)(h * len / fabs(D[m]));
+            const long g = ((long)v * nv + b) * nu + a;
+            const float e = expf(-l[((long)vl * nv + b) * nu + a]);
+            vn = (e - expf(-y[g])) * scale;
+            vd = (e * pi[g]) * scale;
+        }
+        tn[bl][al] = vn;
+        td[bl][al] = vd;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int al = (t >> 6) + 4 * r, bl = t & 63;
+        const int b = b0 + bl, a = a0 + al;
+        if (a < nu && b < nv) {
+            const long o = ((long)vl * nu + a) * nv + b;
+            pt_num[o] = tn[bl][al];
+            pt_den[o] = td[bl][al];
+        }
+    }
+}
+
+hipError_t launch_emtr_terms_t(const float *l, const float *y, const float *pi, float *pt_num, float *pt_den,
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
+    dim3 grid((L.nu + 63) / 64, (L.nv + 63) / 64, nviews_sub);
+    const long avs = L.separable ? (long)L.nu : (long)L.nu * L.nv;
+    k_emtr_terms_t<<<grid, 256, 0, s>>>(l, y, pi, pt_num, pt_den, L.d_views, L.d_axis, avs, L.axis_row_stride, L.nu,
+                                        L.nv, L.h, view0, view_step);
+    return hipGetLastError();
+}
+
 // -------------------------------------------------------- back-projector --
+
+// W consecutive values of one detector column from element i, as one access.
+template <int W> __device__ __forceinline__ void load_win(const float *p, uint32_t i, float (&v)[W]) {
+    if constexpr (W == 4) {
+        const float4 r = load_quad(p, i);
+        v[0] = r.x, v[1] = r.y, v[2] = r.z, v[3] = r.w;
+    } else {
+        __builtin_memcpy(v, __builtin_assume_aligned(reinterpret_cast<const char *>(p) + i * 4u, 4), 4 * W);
+    }
+}
+template <int W> __device__ __forceinline__ void load_win(const _Float16 *p, uint32_t i, float (&v)[W]) {
+    _Float16 h[W];
+    __builtin_memcpy(h, __builtin_assume_aligned(reinterpret_cast<const char *>(p) + i * 2u, 2), 2 * W);
+#pragma unroll
+    for (int t = 0; t < W; ++t) v[t] = (float)h[t];
+}
+
+// One column's contribution to the wave's KZ voxels: for voxel z = kd[q],
+// rows bs .. bs+W-1 with bs the first row above z - 1 (clamped to the
+// detector), hat weights 1 - |z_row - z| in FP32 from an FP64 anchor.
+template <int W, int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv, double zc, double tz, double rtz,
+                                          double hw, float wp, const double (&kd)[KZ], float (&pv)[NP][KZ]) {
+    const float tzf = (float)tz;
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        const double zk = zc - kd[q];
+        int bs = (int)ceil(-zk * rtz - hw);
+        bs = max(0, min(bs, nv - W));
+        const float d0 = (float)fma(tz, (double)bs, zk);
+        float v0[W], v1[W];
+        load_win<W>(col0, (uint32_t)bs, v0);
+        if (NP > 1) load_win<W>(col1, (uint32_t)bs, v1);
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const float d = (t == 0) ? d0 : fmaf((float)t, tzf, d0);
+            const float w = fmaxf(0.f, 1.f - fabsf(d));
+            s0 = fmaf(w, v0[t], s0);
+            if (NP > 1) s1 = fmaf(w, v1[t], s1);
+        }
+        pv[0][q] = fmaf(wp, s0, pv[0][q]);
+        if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
+    }
+}
 
 // Detector column of the ray through (px, py, .); only used to bound the
 // candidate columns (with a margin), so an approximate reciprocal will do.
@@ -480,7 +582,9 @@ __device__ __forceinline__ float column_coord(const SepView &S, float px, float 
 // the rows with |zk + tz*b| < 1 and weights the sum by the in-plane hat of
 // the column.  PART 0: x-major rays on plane x = i (in-plane offset along y);
 // PART 1: y-major rays on plane y = j (offset along x).
-template <int PART, int KZ, int NP, typename PT>
+// HALF: lanes 0-31 and 32-63 hold two different j (the candidate column
+// range is the union of both halves' ranges).
+template <int PART, int KZ, int NP, typename PT, bool HALF>
 __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict__ cv,
                                         const PT *base0, const PT *base1, int i, int j, int nu, int nv,
                                         const double (&kd)[KZ], float (&pv)[NP][KZ]) {
@@ -495,8 +599,15 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
     }
     int alo = (int)floorf(fminf(c1, c2) - 0.01f);
     int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
-    alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
-    ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+    alo = max(alo, 0);
+    ahi = min(ahi, nu - 1);
+    if (HALF) {
+        alo = min(__builtin_amdgcn_readlane(alo, 0), __builtin_amdgcn_readlane(alo, 32));
+        ahi = max(__builtin_amdgcn_readlane(ahi, 0), __builtin_amdgcn_readlane(ahi, 32));
+    } else {
+        alo = __builtin_amdgcn_readfirstlane(alo);
+        ahi = __builtin_amdgcn_readfirstlane(ahi);
+    }
     if (alo > ahi) return;
     // distance of the plane from the source along the major axis
     const double dm = (PART == 0) ? (double)i - S.sx : (double)j - S.sy;
@@ -514,30 +625,12 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
         const double hw = fabs(rtz);
         const PT *col0 = base0 + (long)a * nv;
         const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
-        if (hw < 2.0 && nv >= 4) {
-            // at most 4 rows lie within one voxel of any z: a fixed window
-            const float tzf = (float)tz;
-#pragma unroll
-            for (int q = 0; q < KZ; ++q) {
-                const double zk = zc - kd[q];
-                int bs = (int)ceil(-zk * rtz - hw);
-                bs = max(0, min(bs, nv - 4));
-                const float d0 = (float)fma(tz, (double)bs, zk);
-                const float4 r0 = load_quad(col0, (uint32_t)bs);
-                const float4 r1 = (NP > 1) ? load_quad(col1, (uint32_t)bs) : r0;
-                const float v0[4] = {r0.x, r0.y, r0.z, r0.w};
-                const float v1[4] = {r1.x, r1.y, r1.z, r1.w};
-                float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float d = (t == 0) ? d0 : fmaf((float)t, tzf, d0);
-                    const float w = fmaxf(0.f, 1.f - fabsf(d));
-                    s0 = fmaf(w, v0[t], s0);
-                    if (NP > 1) s1 = fmaf(w, v1[t], s1);
-                }
-                pv[0][q] = fmaf(wp, s0, pv[0][q]);
-                if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
-            }
+        // the rows within one voxel of z: fewer than 2 hw + 1, so a fixed
+        // window of 3 (hw < 1.5) or 4 (hw < 2) consecutive rows holds them
+        if (hw < 1.5 && nv >= 3) {
+            bp_window<3, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, wp, kd, pv);
+        } else if (hw < 2.0 && nv >= 4) {
+            bp_window<4, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, wp, kd, pv);
         } else {
             const int nb = (int)fmin(2.0 * hw + 1.0, (double)nv);
 #pragma unroll
@@ -564,7 +657,7 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
 // With one chunk the result goes straight to vol0/vol1 (type OT); with more,
 // each chunk writes FP32 partial volumes part0/part1 + chunk * nvox, summed
 // afterwards in a fixed order (deterministic).
-template <int KZ, int NP, typename OT, typename PT>
+template <int KZ, int NP, typename OT, typename PT, bool HALF>
 __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
                                                          OT *__restrict__ vol0, OT *__restrict__ vol1,
                                                          float *__restrict__ part0, float *__restrict__ part1,
@@ -575,14 +668,18 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
                                                          int per_chunk) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
+    // HALF (nz <= 32, KZ = 1): a wave covers z = lane % 32 of two rows
+    // j = 2 jp and 2 jp + 1; otherwise z = zc_id * 64 KZ + 64 q + lane of one row
+    const int zchunks = HALF ? 1 : (nz + 64 * KZ - 1) / (64 * KZ);
     const int zc_id = wave % zchunks;
     const int ij = wave / zchunks;
-    const int i = ij % nx, j = ij / nx;
-    if (j >= ny) return;  // whole wave; no barrier below
+    const int i = ij % nx;
+    const int jw = HALF ? 2 * (ij / nx) : ij / nx;  // the wave's first row
+    if (jw >= ny) return;  // whole wave; no barrier below
+    const int j = HALF ? jw + (lane >> 5) : jw;
     double kd[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
+    for (int q = 0; q < KZ; ++q) kd[q] = HALF ? (double)(lane & 31) : (double)(zc_id * 64 * KZ + q * 64 + lane);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][KZ];
 #pragma unroll
@@ -603,8 +700,8 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
         const ColD *cv = cols + (long)v * nu;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        if (S.flags & 1) bp_part<0, KZ, NP, PT>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
-        if (S.flags & 2) bp_part<1, KZ, NP, PT>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
+        if (S.flags & 1) bp_part<0, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
+        if (S.flags & 2) bp_part<1, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -613,8 +710,8 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
     const long nvox = (long)nx * ny * nz;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
-        const int k = zc_id * 64 * KZ + q * 64 + lane;
-        if (k < nz) {
+        const int k = (int)kd[q];
+        if (k < nz && j < ny) {
             const long o = ((long)k * ny + j) * nx + i;
             if (gridDim.y == 1) {
                 store_f(vol0, o, (float)acc[0][q]);
@@ -636,42 +733,57 @@ __global__ void k_sum_chunks(const float *__restrict__ part, OT *__restrict__ ou
     }
 }
 
-int bp_chunks(const Level &L, int nviews_sub) {
+// waves of the separable back-projector: one per (x, y) row and 64 KZ z
+// values, or one per two rows when nz <= 32
+long bp_waves(const Level &L, int *kz) {
     int KZ = 1;
     while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
-    const long waves = (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * L.nx * L.ny;
+    if (kz) *kz = KZ;
+    if (L.nz <= 32) return (long)L.nx * ((L.ny + 1) / 2);
+    return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * L.nx * L.ny;
+}
+
+int bp_chunks(const Level &L, int nviews_sub) {
+    const long waves = bp_waves(L, nullptr);
     long c = (16384 + waves - 1) / waves;
     if (c > 64) c = 64;
     if (c > nviews_sub) c = nviews_sub;
     return c < 1 ? 1 : (int)c;
 }
 
+// With more than one view chunk the chunks' partial volumes are summed into
+// vol0/vol1 here, unless `leave_chunks` is set (the caller then reads the
+// partials itself; *nchunks_out receives the chunk count).
 template <int NP, typename OT, typename PT>
 static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, float *part, const Level &L,
-                            int view0, int view_step, int nviews_sub, hipStream_t s) {
+                            int view0, int view_step, int nviews_sub, hipStream_t s, bool leave_chunks = false,
+                            int *nchunks_out = nullptr) {
     if (!L.separable) return hipErrorNotSupported;
     int KZ = 1;
-    while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
-    const long zchunks = (L.nz + 64 * KZ - 1) / (64 * KZ);
-    const long waves = zchunks * L.nx * L.ny;
+    const long waves = bp_waves(L, &KZ);
     const int nchunks = bp_chunks(L, nviews_sub);
     const int per = (nviews_sub + nchunks - 1) / nchunks;
     const long nvox = (long)L.nx * L.ny * L.nz;
     float *part0 = part, *part1 = part ? part + (long)nchunks * nvox : nullptr;
     if (nchunks > 1 && !part) return hipErrorInvalidValue;
     dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
-#define MGCT_BP(K)                                                                                                  \
-    k_backproject_sep<K, NP, OT, PT><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
+#define MGCT_BP(K, H)                                                                                               \
+    k_backproject_sep<K, NP, OT, PT, H><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
                                                       L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
                                                       view_step, per)
-    switch (KZ) {
-        case 1: MGCT_BP(1); break;
-        case 2: MGCT_BP(2); break;
-        case 4: MGCT_BP(4); break;
-        default: MGCT_BP(8); break;
+    if (L.nz <= 32) {
+        MGCT_BP(1, true);
+    } else {
+        switch (KZ) {
+            case 1: MGCT_BP(1, false); break;
+            case 2: MGCT_BP(2, false); break;
+            case 4: MGCT_BP(4, false); break;
+            default: MGCT_BP(8, false); break;
+        }
     }
 #undef MGCT_BP
-    if (nchunks > 1) {
+    if (nchunks_out) *nchunks_out = nchunks;
+    if (nchunks > 1 && !leave_chunks) {
         unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);
         k_sum_chunks<OT><<<g, 256, 0, s>>>(part0, vol0, nvox, nchunks);
         if (NP > 1) k_sum_chunks<OT><<<g, 256, 0, s>>>(part1, vol1, nvox, nchunks);
@@ -698,8 +810,10 @@ hipError_t launch_backproject(const void *pt, int pt_dtype, void *vol, int vol_d
 }
 
 hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, float *scratch,
-                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
-    return launch_bp<2, float, float>(pt0, pt1, vol0, vol1, scratch, L, view0, view_step, nviews_sub, s);
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s,
+                               int *nchunks_left) {
+    return launch_bp<2, float, float>(pt0, pt1, vol0, vol1, scratch, L, view0, view_step, nviews_sub, s,
+                                      nchunks_left != nullptr, nchunks_left);
 }
 
 }  // namespace mgct

@@ -76,7 +76,6 @@ struct CnnBuffers {
     uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;   // activations, BF16 [n][C]
     float *dout = nullptr;                                  // [n]
     uint16_t *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
-    float *dz1f = nullptr;
     uint16_t *gT = nullptr, *xT = nullptr;                  // channels-first copies for weight gradients
     float *partial = nullptr;
 };
@@ -104,6 +103,7 @@ struct Ctx {
     std::map<std::string, std::pair<void *, size_t>> ws;
     // cached step sizes keyed by a description of (level, filter, iters, seed)
     std::map<std::string, double> alpha_cache;
+    bool pi_valid[kMaxLevels] = {};  // OS-EMTR support projection A 1 cached per level
     // kernel timing records (start/stop events per launch)
     struct TimedLaunch {
         int op, level;
@@ -154,7 +154,8 @@ size_t backproject_scratch_bytes(const Level &L, int nviews_sub, int np);
 hipError_t launch_backproject(const void *pt, int pt_dtype, void *vol, int vol_dtype, float *scratch, const Level &L,
                               int view0, int view_step, int nviews_sub, hipStream_t s);
 hipError_t launch_backproject2(const float *pt0, const float *pt1, float *vol0, float *vol1, float *scratch,
-                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s,
+                               int *nchunks_left = nullptr);
 
 // general-geometry transpose (any detector orientation; F32 output)
 size_t backproject_gen_scratch_bytes(const Level &L, int nviews_sub);
@@ -185,12 +186,13 @@ hipError_t launch_restrict_volume(const float *fine, float *coarse, int nx, int 
 hipError_t launch_restrict_stack(const float *fine, float *coarse, int nviews, int nv, int nu, hipStream_t s);
 hipError_t launch_prolong_add(const float *cnew, const float *cold, float *fine, int nx, int ny, int nz,
                               hipStream_t s);
-hipError_t launch_emtr_terms(const float *l, const float *b, const float *pi, float *num_src, float *den_src,
-                             const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
 hipError_t launch_emtr_update(float *vol, const float *num, const float *den, size_t n, unsigned *maxbits,
                               hipStream_t s);
-hipError_t launch_max_reset(unsigned *maxbits, hipStream_t s);
-hipError_t launch_max_reduce(const float *x, size_t n, unsigned *maxbits, hipStream_t s);
+// OS-EMTR fused steps: subset terms + transposition for A^T; chunk sums + max
+hipError_t launch_emtr_terms_t(const float *l, const float *y, const float *pi, float *pt_num, float *pt_den,
+                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
+hipError_t launch_emtr_reduce(const float *part_num, const float *part_den, float *num, float *den, size_t n,
+                              int nchunks, unsigned *maxbits, hipStream_t s);
 hipError_t launch_splitmix_uniform(float *x, size_t n, uint64_t seed, hipStream_t s);
 
 hipError_t launch_scale(const float *x, float *y, float a, size_t n, hipStream_t s);

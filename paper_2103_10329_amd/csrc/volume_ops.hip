@@ -320,36 +320,31 @@ hipError_t launch_prolong_add(const float *cnew, const float *cold, float *fine,
 
 // OS-EMTR terms for the views of one subset: e = exp(-l),
 // num_src = e - exp(-b), den_src = e * (A 1).
-__global__ void k_emtr_terms(const float *l, const float *b, const float *pi, float *num, float *den, int nu, int nv,
-                             int nsub, int view0, int view_step) {
-    const size_t per = (size_t)nu * nv;
-    const size_t n = per * nsub;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t vl = idx / per, r = idx % per;
-        const size_t g = (size_t)(view0 + vl * view_step) * per + r;
-        const float e = expf(-l[idx]);
-        num[idx] = e - expf(-b[g]);
-        den[idx] = e * pi[g];
-    }
-}
-hipError_t launch_emtr_terms(const float *l, const float *b, const float *pi, float *num_src, float *den_src,
-                             const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
-    size_t n = (size_t)L.nu * L.nv * nviews_sub;
-    k_emtr_terms<<<grid_for(n), 256, 0, s>>>(l, b, pi, num_src, den_src, L.nu, L.nv, nviews_sub, view0, view_step);
-    return hipGetLastError();
-}
-
-__global__ void k_max_reset(unsigned *m) { m[0] = 0u; }
-hipError_t launch_max_reset(unsigned *maxbits, hipStream_t s) {
-    k_max_reset<<<1, 1, 0, s>>>(maxbits);
-    return hipGetLastError();
-}
-
-// max of non-negative floats via their bit patterns (monotone for x >= 0).
-__global__ __launch_bounds__(256) void k_max_reduce(const float *x, size_t n, unsigned *m) {
+// OS-EMTR: num and den from the back-projector's view-chunk partials
+// (summed in FP64 in chunk order; nchunks <= 1: num/den already final) and
+// the max of den, folded into *maxbits with an ordered-integer atomic max
+// (den >= 0, so its bit pattern orders like its value).
+__global__ __launch_bounds__(256) void k_emtr_reduce(const float *__restrict__ part_num,
+                                                     const float *__restrict__ part_den, float *__restrict__ num,
+                                                     float *__restrict__ den, size_t n, int nchunks,
+                                                     unsigned *maxbits) {
     float acc = 0.f;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        acc = fmaxf(acc, x[i]);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float d;
+        if (nchunks > 1) {
+            double sn = 0.0, sd = 0.0;
+            for (int c = 0; c < nchunks; ++c) {
+                sn += (double)part_num[c * n + i];
+                sd += (double)part_den[c * n + i];
+            }
+            num[i] = (float)sn;
+            d = (float)sd;
+            den[i] = d;
+        } else {
+            d = den[i];
+        }
+        acc = fmaxf(acc, d);
+    }
     __shared__ float red[256];
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -357,10 +352,11 @@ __global__ __launch_bounds__(256) void k_max_reduce(const float *x, size_t n, un
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(m, __float_as_uint(fmaxf(red[0], 0.f)));
+    if (threadIdx.x == 0) atomicMax(maxbits, __float_as_uint(fmaxf(red[0], 0.f)));
 }
-hipError_t launch_max_reduce(const float *x, size_t n, unsigned *maxbits, hipStream_t s) {
-    k_max_reduce<<<grid_for(n, 256, 1024), 256, 0, s>>>(x, n, maxbits);
+hipError_t launch_emtr_reduce(const float *part_num, const float *part_den, float *num, float *den, size_t n,
+                              int nchunks, unsigned *maxbits, hipStream_t s) {
+    k_emtr_reduce<<<grid_for(n, 256, 1024), 256, 0, s>>>(part_num, part_den, num, den, n, nchunks, maxbits);
     return hipGetLastError();
 }
 

@@ -7,7 +7,9 @@ integrals into measured data.  It contains none of the reconstruction
 method's arithmetic (no projector, no back-projector, no filter, no solver).
 """
 
-from .geometry import CONFIGS, ScanConfig, trajectory, perturb_geometry, volume_axes  # noqa: F401
+from .geometry import (  # noqa: F401
+    CONFIGS, ScanConfig, trajectory, perturb_geometry, volume_axes, evaluation_mask, masked_rel_error,
+)
 from .phantom import (  # noqa: F401
     Phantom,
     random_phantom,

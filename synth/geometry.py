@@ -127,3 +127,19 @@ def volume_axes(n: int, h: float, origin=(0.0, 0.0, 0.0)):
     c = (n - 1) / 2.0
     idx = np.arange(n, dtype=np.float64)
     return tuple(origin[k] + (idx - c) * h for k in range(3))
+
+
+def evaluation_mask(n: int, h: float, radius: float = 0.9 * FOV / 2, half_height: float = 12.0) -> np.ndarray:
+    """Boolean [z][y][x] mask of the region every view sees well: a cylinder
+    about the rotation axis (radius 0.9 of the half field of view, |z| below
+    12 units), used to score reconstructions against the phantom."""
+    x, y, z = volume_axes(n, h)
+    r2 = y[:, None] ** 2 + x[None, :] ** 2
+    return (np.abs(z)[:, None, None] <= half_height) & (r2 <= radius * radius)[None, :, :]
+
+
+def masked_rel_error(vol, truth, mask) -> float:
+    """||mask (vol - truth)|| / ||mask truth|| in FP64."""
+    d = (np.asarray(vol, np.float64) - np.asarray(truth, np.float64))[mask]
+    t = np.asarray(truth, np.float64)[mask]
+    return float(np.linalg.norm(d) / max(np.linalg.norm(t), 1e-300))

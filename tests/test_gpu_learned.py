@@ -110,3 +110,64 @@ def test_short_training_gains_over_plain_filter():
     acc, rej = ctx.learned_stats()
     say("held-out image error plain vs learned", gains, "accepted", acc, "rejected", rej)
     assert np.mean([e[1] for e in gains]) < np.mean([e[0] for e in gains])
+
+
+def _masked_err(v, truth, mask):
+    import torch
+    t = truth[mask].double()
+    return float(torch.linalg.vector_norm(v[mask].double() - t) / torch.linalg.vector_norm(t))
+
+
+def test_trained_weights_gain_at_128():
+    """The shipped weights (trained on 900 phantoms of the 128^3 / 360-view
+    distribution) on 4 phantoms outside the training seeds: masked image
+    error after 2 iterations below the plain method's on every one."""
+    import torch
+    from paper_2103_10329_amd import learned as L
+    cfg = synth.CONFIGS["c4"]
+    ctx = L.make_context(cfg, synth.trajectory(cfg.n_views, cfg.z_levels, cfg.pixel))
+    t, r = mg.ramp_table(cfg.n)
+    filt = mg.filter_radial(t, r)
+    alphas = [ctx.estimate_step(filt, level=lv, iters=30) for lv in range(cfg.levels - 1)]
+    ctx.cnn_set_weights(L.load_weights())
+    rows, acc, rej = L.evaluate(ctx, cfg, range(40000, 40004), cfg.levels, filt, alphas)
+    say("shipped weights at 128^3: (seed, plain, learned)", rows, "accepted", acc, "rejected", rej)
+    assert all(lr < pl for _, pl, lr in rows)
+
+
+def test_trained_weights_at_512_mixed_precision():
+    """The same weights run inside Algorithm 1 at 512^3 with 1440 views of
+    768^2 (4 grids, BF16 volume copy and FP16 stacks): the residual judge keeps
+    the learned iteration no worse in residual than the plain one; image
+    errors and wall times are reported."""
+    import time
+    import torch
+    from paper_2103_10329_amd import learned as L
+    cfg = synth.CONFIGS["c2"]
+    n = cfg.n
+    ctx = L.make_context(cfg, synth.trajectory(cfg.n_views, cfg.z_levels, cfg.pixel))
+    ctx.set_precision("bfloat16", "float16")
+    ph = synth.random_phantom(cfg, 1002)
+    truth = ctx.synth_voxelize(ph, ss=2)
+    gen = torch.Generator(device="cuda").manual_seed(2002)
+    b = L.poisson_data(ctx.synth_line_integrals(ph), cfg.noise_level, gen).half()
+    t, r = mg.ramp_table(n)
+    filt = mg.filter_radial(t, r)
+    alphas = [ctx.estimate_step(filt, level=lv, iters=20) for lv in range(cfg.levels - 1)]
+    ctx.cnn_set_weights(L.load_weights())
+    mask = torch.from_numpy(synth.evaluation_mask(n, cfg.h)).cuda()
+    bf = b.float()
+    out = {}
+    for learned in (False, True):
+        v = torch.zeros((n, n, n), device="cuda")
+        ctx.learned_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.multigrid_solve(v, b, cfg.levels, 2, filt, alphas=alphas, want_hist=False, learned=learned)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = float(torch.linalg.vector_norm((bf - ctx.project(v)).double()) / torch.linalg.vector_norm(bf.double()))
+        out[learned] = (res, _masked_err(v, truth, mask), dt, ctx.learned_stats())
+        del v
+    say("512^3 (rel residual, masked error, seconds, (accepted, rejected)) plain", out[False], "learned", out[True])
+    assert out[True][0] <= out[False][0] * 1.01
