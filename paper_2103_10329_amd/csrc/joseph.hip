@@ -540,12 +540,12 @@ template <int W> __device__ __forceinline__ void load_win(const _Float16 *p, uin
     for (int t = 0; t < W; ++t) v[t] = (float)h[t];
 }
 
-// One column's contribution to the wave's KZ voxels: for voxel z = kd[q],
-// rows bs .. bs+W-1 with bs the first row above z - 1 (clamped to the
-// detector), hat weights 1 - |z_row - z| in FP32 from an FP64 anchor.
+// One column's detector-row sums for the wave's KZ voxels: for voxel
+// z = kd[q], rows bs .. bs+W-1 with bs the first row above z - 1 (clamped to
+// the detector), hat weights 1 - |z_row - z| in FP32 from an FP64 anchor.
 template <int W, int KZ, int NP, typename PT>
 __device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv, double zc, double tz, double rtz,
-                                          double hw, float wp, const double (&kd)[KZ], float (&pv)[NP][KZ]) {
+                                          double hw, const double (&kd)[KZ], float (&s)[NP][KZ]) {
     const float tzf = (float)tz;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
@@ -564,8 +564,39 @@ __device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv
             s0 = fmaf(w, v0[t], s0);
             if (NP > 1) s1 = fmaf(w, v1[t], s1);
         }
-        pv[0][q] = fmaf(wp, s0, pv[0][q]);
-        if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
+        s[0][q] = s0;
+        if (NP > 1) s[NP - 1][q] = s1;
+    }
+}
+
+// The same sums for any row spacing: the rows within one voxel of z are
+// fewer than 2 hw + 1, so a fixed window of 3 (hw < 1.5) or 4 (hw < 2)
+// consecutive rows holds them, else a window of floor(2 hw + 1) rows.
+template <int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_column_sums(const PT *col0, const PT *col1, int nv, double zc, double tz,
+                                               double rtz, double hw, const double (&kd)[KZ], float (&s)[NP][KZ]) {
+    if (hw < 1.5 && nv >= 3) {
+        bp_window<3, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, s);
+    } else if (hw < 2.0 && nv >= 4) {
+        bp_window<4, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, s);
+    } else {
+        const int nb = (int)fmin(2.0 * hw + 1.0, (double)nv);
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) {
+            const double zk = zc - kd[q];
+            int bs = (int)ceil(-zk * rtz - hw);
+            bs = max(0, min(bs, nv - nb));
+            float s0 = 0.f, s1 = 0.f;
+            for (int t = 0; t < nb; ++t) {
+                const int b = bs + t;
+                const float d = (float)fma(tz, (double)b, zk);
+                const float w = fmaxf(0.f, 1.f - fabsf(d));
+                s0 = fmaf(w, load_f(col0, b), s0);
+                if (NP > 1) s1 = fmaf(w, load_f(col1, b), s1);
+            }
+            s[0][q] = s0;
+            if (NP > 1) s[NP - 1][q] = s1;
+        }
     }
 }
 
@@ -625,29 +656,149 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
         const double hw = fabs(rtz);
         const PT *col0 = base0 + (long)a * nv;
         const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
-        // the rows within one voxel of z: fewer than 2 hw + 1, so a fixed
-        // window of 3 (hw < 1.5) or 4 (hw < 2) consecutive rows holds them
-        if (hw < 1.5 && nv >= 3) {
-            bp_window<3, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, wp, kd, pv);
-        } else if (hw < 2.0 && nv >= 4) {
-            bp_window<4, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, wp, kd, pv);
-        } else {
-            const int nb = (int)fmin(2.0 * hw + 1.0, (double)nv);
+        float sums[NP][KZ];
+        bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
 #pragma unroll
-            for (int q = 0; q < KZ; ++q) {
-                const double zk = zc - kd[q];
-                int bs = (int)ceil(-zk * rtz - hw);
-                bs = max(0, min(bs, nv - nb));
-                float s0 = 0.f, s1 = 0.f;
-                for (int t = 0; t < nb; ++t) {
-                    const int b = bs + t;
-                    const float d = (float)fma(tz, (double)b, zk);
-                    const float w = fmaxf(0.f, 1.f - fabsf(d));
-                    s0 = fmaf(w, load_f(col0, b), s0);
-                    if (NP > 1) s1 = fmaf(w, load_f(col1, b), s1);
+        for (int q = 0; q < KZ; ++q) {
+            pv[0][q] = fmaf(wp, sums[0][q], pv[0][q]);
+            if (NP > 1) pv[NP - 1][q] = fmaf(wp, sums[NP - 1][q], pv[NP - 1][q]);
+        }
+    }
+}
+
+// Blocked variant of bp_part: the wave covers BI x BJ rows (i, j).  A plane
+// (x = i for PART 0, y = j for PART 1) is shared by the block's rows lying in
+// it, so each column's detector-row sums are formed once per plane and
+// weighted into every row the column reaches (the in-plane hat 1 - |off|).
+// Same arithmetic per (voxel, column) as bp_part.
+template <int PART, int KZ, int NP, typename PT, int BI, int BJ>
+__device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
+                                            const PT *base1, int i0, int j0, int nu, int nv,
+                                            const double (&kd)[KZ], float (&pv)[NP][BI * BJ][KZ]) {
+    constexpr int NPL = PART == 0 ? BI : BJ;  // planes in the block
+    constexpr int NR = PART == 0 ? BJ : BI;   // rows per plane
+    const int r0 = PART == 0 ? j0 : i0;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+        const int P = (PART == 0 ? i0 : j0) + pl;
+        const float fp = (float)P, flo = (float)(r0 - 1), fhi = (float)(r0 + NR);
+        const float c1 = PART == 0 ? column_coord(S, fp, flo) : column_coord(S, flo, fp);
+        const float c2 = PART == 0 ? column_coord(S, fp, fhi) : column_coord(S, fhi, fp);
+        int alo = (int)floorf(fminf(c1, c2) - 0.01f);
+        int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
+        alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
+        ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+        // distance of the plane from the source along the major axis
+        const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
+        const double inv_dm = 1.0 / dm;
+        for (int a = alo; a <= ahi; ++a) {
+            const ColD C = cv[a];
+            if (C.axis != PART) continue;
+            const double tau = dm * (PART == 0 ? C.rdx : C.rdy);  // ray parameter at the plane
+            if (tau < 0.0 || tau > 1.0) continue;
+            const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
+            float w[NR];
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                w[r] = 1.f - (float)fabs(pos - (double)(r0 + r));
+                any |= w[r] > 0.f;
+            }
+            if (!any) continue;
+            const double tz = tau * S.vz;                                // row spacing along z at the plane
+            const double zc = fma(tau, S.dz0, S.sz);                     // z of row 0 at the plane
+            const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;     // 1 / tz
+            const double hw = fabs(rtz);
+            const PT *col0 = base0 + (long)a * nv;
+            const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
+            float sums[NP][KZ];
+            bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (!(w[r] > 0.f)) continue;
+                const int idx = PART == 0 ? pl * BJ + r : r * BJ + pl;
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) {
+                    pv[0][idx][q] = fmaf(w[r], sums[0][q], pv[0][idx][q]);
+                    if (NP > 1) pv[NP - 1][idx][q] = fmaf(w[r], sums[NP - 1][q], pv[NP - 1][idx][q]);
                 }
-                pv[0][q] = fmaf(wp, s0, pv[0][q]);
-                if (NP > 1) pv[NP - 1][q] = fmaf(wp, s1, pv[NP - 1][q]);
+            }
+        }
+    }
+}
+
+// Back-projector over BI x BJ blocks of rows: wave -> (block, z chunk), lane
+// -> z = zc_id * 64 KZ + 64 q + lane.  Views and chunks as k_backproject_sep.
+template <int KZ, int NP, typename OT, typename PT, int BI, int BJ>
+__global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
+                                                         OT *__restrict__ vol0, OT *__restrict__ vol1,
+                                                         float *__restrict__ part0, float *__restrict__ part1,
+                                                         const SepView *__restrict__ sep,
+                                                         const ColD *__restrict__ cols,
+                                                         const uint8_t *__restrict__ axis, int nx, int ny, int nz,
+                                                         int nu, int nv, int nviews_sub, int view0, int view_step,
+                                                         int per_chunk) {
+    constexpr int NB = BI * BJ;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
+    const int nbi = (nx + BI - 1) / BI;
+    const int zc_id = wave % zchunks;
+    const int blk = wave / zchunks;
+    const int i0 = (blk % nbi) * BI, j0 = (blk / nbi) * BJ;
+    if (j0 >= ny) return;  // whole wave; no barrier below
+    double kd[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
+    // per-view partial sums in FP32, summed over views in FP64
+    double acc[NP][NB][KZ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) acc[p][b][q] = 0.0;
+
+    const int vbeg = blockIdx.y * per_chunk;
+    const int vend = min(nviews_sub, vbeg + per_chunk);
+    for (int vl = vbeg; vl < vend; ++vl) {
+        float pv[NP][NB][KZ];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) pv[p][b][q] = 0.f;
+        const int v = view0 + vl * view_step;
+        const SepView S = sep[v];
+        const ColD *cv = cols + (long)v * nu;
+        const PT *base0 = pt0 + (long)vl * nu * nv;
+        const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
+        if (S.flags & 1) bp_part_blk<0, KZ, NP, PT, BI, BJ>(S, cv, base0, base1, i0, j0, nu, nv, kd, pv);
+        if (S.flags & 2) bp_part_blk<1, KZ, NP, PT, BI, BJ>(S, cv, base0, base1, i0, j0, nu, nv, kd, pv);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) acc[p][b][q] += (double)pv[p][b][q];
+    }
+    const long nvox = (long)nx * ny * nz;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int i = i0 + b / BJ, j = j0 + b % BJ;
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) {
+            const int k = (int)kd[q];
+            if (i < nx && j < ny && k < nz) {
+                const long o = ((long)k * ny + j) * nx + i;
+                if (gridDim.y == 1) {
+                    store_f(vol0, o, (float)acc[0][b][q]);
+                    if (NP > 1) store_f(vol1, o, (float)acc[NP - 1][b][q]);
+                } else {
+                    part0[blockIdx.y * nvox + o] = (float)acc[0][b][q];
+                    if (NP > 1) part1[blockIdx.y * nvox + o] = (float)acc[NP - 1][b][q];
+                }
             }
         }
     }
@@ -733,14 +884,28 @@ __global__ void k_sum_chunks(const float *__restrict__ part, OT *__restrict__ ou
     }
 }
 
-// waves of the separable back-projector: one per (x, y) row and 64 KZ z
-// values, or one per two rows when nz <= 32
+// row block of the separable back-projector's waves (nz > 32)
+#ifndef MGCT_BP_BI
+#define MGCT_BP_BI 2
+#endif
+#ifndef MGCT_BP_BJ
+#define MGCT_BP_BJ 2
+#endif
+#ifndef MGCT_BP_KZMAX
+#define MGCT_BP_KZMAX 2
+#endif
+constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
+
+// waves of the separable back-projector: one per kBpBI x kBpBJ block of
+// (x, y) rows and 64 KZ z values, or one per two rows when nz <= 32
 long bp_waves(const Level &L, int *kz) {
+    // KZ = 2 where the depth allows (more z per wave raises the register
+    // count of the four-row block beyond what keeps 6 waves per SIMD)
     int KZ = 1;
-    while (KZ < 8 && 64 * KZ * 2 <= L.nz) KZ *= 2;
+    if (MGCT_BP_KZMAX >= 2 && 2 * 64 <= L.nz) KZ = 2;
     if (kz) *kz = KZ;
     if (L.nz <= 32) return (long)L.nx * ((L.ny + 1) / 2);
-    return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * L.nx * L.ny;
+    return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
 }
 
 int bp_chunks(const Level &L, int nviews_sub) {
@@ -767,6 +932,10 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     float *part0 = part, *part1 = part ? part + (long)nchunks * nvox : nullptr;
     if (nchunks > 1 && !part) return hipErrorInvalidValue;
     dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
+#define MGCT_BPB(K)                                                                                                 \
+    k_backproject_blk<K, NP, OT, PT, kBpBI, kBpBJ><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep,  \
+                                                                      L.d_cols, L.d_axis, L.nx, L.ny, L.nz, L.nu,    \
+                                                                      L.nv, nviews_sub, view0, view_step, per)
 #define MGCT_BP(K, H)                                                                                               \
     k_backproject_sep<K, NP, OT, PT, H><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
                                                       L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
@@ -774,14 +943,11 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     if (L.nz <= 32) {
         MGCT_BP(1, true);
     } else {
-        switch (KZ) {
-            case 1: MGCT_BP(1, false); break;
-            case 2: MGCT_BP(2, false); break;
-            case 4: MGCT_BP(4, false); break;
-            default: MGCT_BP(8, false); break;
-        }
+        if (KZ == 2) MGCT_BPB(2);
+        else MGCT_BPB(1);
     }
 #undef MGCT_BP
+#undef MGCT_BPB
     if (nchunks_out) *nchunks_out = nchunks;
     if (nchunks > 1 && !leave_chunks) {
         unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);
