@@ -105,20 +105,28 @@ bool vol_dtype_ok(int d) { return d == MGCT_F32 || d == MGCT_BF16; }
 bool stack_dtype_ok(int d) { return d == MGCT_F32 || d == MGCT_F16; }
 
 // ---- projector and transpose on a subset of views (view0 + k*step, k < nsub)
+// The separable projector's pair copies of grid g in dtype vt_dtype, filled
+// from vol (zero pads survive: allocated zeroed, never written).
+int pair_copies(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, int vt_dtype, void **vtx, void **vty,
+                hipStream_t s) {
+    const bool f32 = vt_dtype == MGCT_F32;
+    const size_t es = f32 ? 4 : 2;
+    *vtx = workspace(c, lvl(f32 ? "vtx32" : "vtx16", g), pair_copy_elems(L) * es, true);
+    *vty = workspace(c, lvl(f32 ? "vty32" : "vty16", g), pair_copy_elems(L) * es, true);
+    if (!*vtx || !*vty) return MGCT_ERR_OOM;
+    KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
+    HIPCHK(launch_transpose_pairs(vol, vol_dtype, *vtx, *vty, vt_dtype, L, s));
+    return MGCT_OK;
+}
+
 int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *proj, int proj_dtype, int view0,
                int step, int nsub, hipStream_t s, int vt_dtype = -1) {
     // the projector's volume copy: BF16 when the input is BF16 or when asked
     if (vt_dtype < 0 || vol_dtype == MGCT_BF16) vt_dtype = vol_dtype;
     const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
     if (L.separable) {
-        const bool f32 = vt_dtype == MGCT_F32;
-        void *vtx = workspace(c, lvl(f32 ? "vtx32" : "vtx16", g), pair_copy_elems(L) * es, true);
-        void *vty = workspace(c, lvl(f32 ? "vty32" : "vty16", g), pair_copy_elems(L) * es, true);
-        if (!vtx || !vty) return MGCT_ERR_OOM;
-        {
-            KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
-            HIPCHK(launch_transpose_pairs(vol, vol_dtype, vtx, vty, vt_dtype, L, s));
-        }
+        void *vtx, *vty;
+        MGCHK(pair_copies(c, L, g, vol, vol_dtype, vt_dtype, &vtx, &vty, s));
         KernelTimer t(c, MGCT_OP_PROJECT, g, s);
         HIPCHK(launch_project_sep(vtx, vty, vt_dtype, proj, proj_dtype, L, view0, step, nsub, s));
         return MGCT_OK;
@@ -134,6 +142,9 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
     return MGCT_OK;
 }
 
+int do_backproject_pt(Ctx &c, Level &L, int g, const void *pt, int pt_dtype, void *vol, int vol_dtype, int view0,
+                      int step, int nsub, hipStream_t s);
+
 int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, void *vol, int vol_dtype, int view0,
                    int step, int nsub, hipStream_t s, int pt_dtype = -1) {
     if (!L.separable && vol_dtype != MGCT_F32) return MGCT_ERR_NOT_IMPLEMENTED;
@@ -145,6 +156,13 @@ int do_backproject(Ctx &c, Level &L, int g, const void *proj, int proj_dtype, vo
         KernelTimer t(c, MGCT_OP_DATA_PRESCALE, g, s);
         HIPCHK(launch_scale_transpose_stack(proj, proj_dtype, pt, pt_dtype, L, view0, step, nsub, s));
     }
+    return do_backproject_pt(c, L, g, pt, pt_dtype, vol, vol_dtype, view0, step, nsub, s);
+}
+
+// A^T from the scaled, transposed copy pt ([view][column][row], ray-length
+// factors applied) of a stack.
+int do_backproject_pt(Ctx &c, Level &L, int g, const void *pt, int pt_dtype, void *vol, int vol_dtype, int view0,
+                      int step, int nsub, hipStream_t s) {
     const size_t sb = L.separable ? backproject_scratch_bytes(L, nsub, 1) : backproject_gen_scratch_bytes(L, nsub);
     float *scratch = nullptr;
     if (sb) {
@@ -222,6 +240,31 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
     // accumulation stay FP32 (FP64 for the norm)
     const int sd = c.stack_dtype;
     const size_t es = sd == MGCT_F32 ? 4 : 2;
+    if (L.separable) {
+        // fused: the projector writes the transposed, scaled residual that
+        // A^T reads, and the partial sums of its squared norm
+        WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
+        WS(pt, char, lvl(sd == MGCT_F32 ? "pt" : "pt16", g), L.rays() * es, false);
+        const size_t nblk = project_sep_blocks(L, L.nviews);
+        WS(pp, double, "proj_partials", nblk * 8, false);
+        WS(nrm, double, "red_scratch", 8, false);
+        const int vtd = c.vt_dtype;
+        void *vtx, *vty;
+        MGCHK(pair_copies(c, L, g, vol, MGCT_F32, vtd, &vtx, &vty, s));
+        {
+            KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+            HIPCHK(launch_project_sep_mode(vtx, vty, vtd, 1, pt, nullptr, sd, b, b_dtype, nullptr, pp, L, 0, 1,
+                                           L.nviews, s));
+        }
+        HIPCHK(launch_finish_sum(pp, (int)nblk, norm2_out ? norm2_out : nrm, s));
+        MGCHK(do_backproject_pt(c, L, g, pt, sd, grad, MGCT_F32, 0, 1, L.nviews, s));
+        MGCHK(do_precondition(c, L, g, grad, grad, f, s));
+        if (update_out)
+            HIPCHK(launch_scale(grad, update_out, (float)alpha, L.vox(), s));
+        else
+            HIPCHK(launch_axpy(vol, grad, alpha, L.vox(), s));
+        return MGCT_OK;
+    }
     WS(ax, char, lvl(sd == MGCT_F32 ? "lw_ax" : "lw_ax16", g), L.rays() * es, false);
     WS(r, char, lvl(sd == MGCT_F32 ? "lw_r" : "lw_r16", g), L.rays() * es, false);
     WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
@@ -240,6 +283,19 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
 }
 
 int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out, hipStream_t s) {
+    if (L.separable) {
+        const size_t nblk = project_sep_blocks(L, L.nviews);
+        WS(pp, double, "proj_partials", nblk * 8, false);
+        void *vtx, *vty;
+        MGCHK(pair_copies(c, L, g, vol, MGCT_F32, MGCT_F32, &vtx, &vty, s));
+        {
+            KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+            HIPCHK(launch_project_sep_mode(vtx, vty, MGCT_F32, 3, nullptr, nullptr, MGCT_F32, b, MGCT_F32, nullptr,
+                                           pp, L, 0, 1, L.nviews, s));
+        }
+        HIPCHK(launch_finish_sum(pp, (int)nblk, norm2_out, s));
+        return MGCT_OK;
+    }
     WS(ax, float, lvl("lw_ax", g), L.rays() * 4, false);
     WS(r, float, lvl("lw_r", g), L.rays() * 4, false);
     WS(part, double, "red_partials", kRedBlocks * 8, false);
@@ -270,6 +326,36 @@ int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int pa
     }
     // one max slot per subset step, cleared once (0.0f has all-zero bits)
     HIPCHK(launch_fill(reinterpret_cast<float *>(mx), nsteps, 0.f, s));
+    if (L.separable) {
+        // fused: the projector writes the subset's transposed, scaled EMTR
+        // terms; the update refreshes the projector's pair copies in place
+        void *vtx, *vty;
+        MGCHK(pair_copies(c, L, g, vol, MGCT_F32, MGCT_F32, &vtx, &vty, s));
+        int step = 0;
+        for (int p = 0; p < passes; ++p) {
+            for (int m = 0; m < M && m < L.nviews; ++m, ++step) {
+                const int nsub = (L.nviews - m + M - 1) / M;
+                {
+                    KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+                    HIPCHK(launch_project_sep_mode(vtx, vty, MGCT_F32, 2, pt0, pt1, MGCT_F32, b, MGCT_F32, pi,
+                                                   nullptr, L, m, M, nsub, s));
+                }
+                const size_t sb = backproject_scratch_bytes(L, nsub, 2);
+                float *scratch = nullptr;
+                if (sb) {
+                    scratch = static_cast<float *>(workspace(c, lvl("bp_scratch2", g), sb, false));
+                    if (!scratch) return MGCT_ERR_OOM;
+                }
+                int nchunks = 1;
+                HIPCHK(launch_backproject2(pt0, pt1, num, den, scratch, L, m, M, nsub, s, &nchunks));
+                const float *pn = nchunks > 1 ? scratch : nullptr;
+                const float *pd = nchunks > 1 ? scratch + (size_t)nchunks * n : nullptr;
+                HIPCHK(launch_emtr_reduce(pn, pd, num, den, n, nchunks, mx + step, s));
+                HIPCHK(launch_emtr_update_pairs(vol, num, den, mx + step, vtx, vty, MGCT_F32, L, s));
+            }
+        }
+        return MGCT_OK;
+    }
     int step = 0;
     for (int p = 0; p < passes; ++p) {
         for (int m = 0; m < M && m < L.nviews; ++m, ++step) {

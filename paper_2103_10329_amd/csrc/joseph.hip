@@ -202,6 +202,50 @@ __global__ __launch_bounds__(256) void k_transpose_pairs(const TI *__restrict__ 
     }
 }
 
+// OS-EMTR update mu += num/den where den > 1e-6 max(den) (eq. 3), also
+// writing each new value into the pair copies so the next subset's
+// projection needs no fresh transposition.  Voxel (x, y, z) sits in vtx pair
+// (x, y) first and (x, y-1) second, and in vty pair (y, x) first and
+// (y, x-1) second (pairs exist from -1, so every neighbour is in range).
+template <typename TO>
+__global__ void k_emtr_update_pairs(float *__restrict__ vol, const float *__restrict__ num,
+                                    const float *__restrict__ den, const unsigned *__restrict__ maxbits,
+                                    TO *__restrict__ vtx, TO *__restrict__ vty, int nx, int ny, int nz) {
+    const float thr = 1e-6f * __uint_as_float(maxbits[0]);
+    const size_t n = (size_t)nx * ny * nz;
+    const long PX = nx + 2 * kVolPad, PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float m = vol[i];
+        const float d = den[i];
+        if (d > thr) {
+            m += num[i] / d;
+            vol[i] = m;
+        }
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((size_t)nx * ny));
+        const long ox = (((long)(x + kVolPad) * PY + (y + kVolPad)) * PZ + (z + kVolPad)) * 2;
+        store_f(vtx, ox, m);
+        store_f(vtx, ox - 2 * PZ + 1, m);
+        const long oy = (((long)(y + kVolPad) * PX + (x + kVolPad)) * PZ + (z + kVolPad)) * 2;
+        store_f(vty, oy, m);
+        store_f(vty, oy - 2 * PZ + 1, m);
+    }
+}
+
+hipError_t launch_emtr_update_pairs(float *vol, const float *num, const float *den, const unsigned *maxbits,
+                                    void *vtx, void *vty, int vt_dtype, const Level &L, hipStream_t s) {
+    const size_t n = L.vox();
+    const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 65535);
+    if (vt_dtype == MGCT_F32)
+        k_emtr_update_pairs<float><<<g, 256, 0, s>>>(vol, num, den, maxbits, (float *)vtx, (float *)vty, L.nx, L.ny,
+                                                     L.nz);
+    else if (vt_dtype == MGCT_BF16)
+        k_emtr_update_pairs<uint16_t><<<g, 256, 0, s>>>(vol, num, den, maxbits, (uint16_t *)vtx, (uint16_t *)vty,
+                                                        L.nx, L.ny, L.nz);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,
                                   hipStream_t s) {
     dim3 grid((L.nx + 63) / 64, (L.nz + 63) / 64, L.ny + 1);
@@ -303,9 +347,26 @@ struct PlaneEntry {
     double tau;  // ray parameter at the plane
 };
 
-template <typename VT, typename PT>
+// Epilogue of the separable projector, for ray (v, a, b) with value
+// l = (A mu)[ray] and ray-length factor L = h|D|/|D_m|:
+//   kProjPlain:    out[vl][b][a] = l;
+//   kProjResidual: r = y[v][b][a] - l rounded to PT, out[vl][a][b] = r * L
+//                  (the transposed, scaled copy A^T reads) and the block's
+//                  sum of r^2 (FP64) in partials[block];
+//   kProjEmtr:     OS-EMTR subset terms (eq. 3): out[vl][a][b] =
+//                  (e^-l - e^-y) L and out2[vl][a][b] = e^-l pi[v][b][a] L;
+//   kProjNorm:     only the block's sum of (y - l)^2.
+// vl is the view's index in the launched subset, v = view0 + vl * step.
+constexpr int kProjPlain = 0, kProjResidual = 1, kProjEmtr = 2, kProjNorm = 3;
+
+template <typename T> __device__ __forceinline__ float round_as(float x) { return x; }
+template <> __device__ __forceinline__ float round_as<_Float16>(float x) { return (float)(_Float16)x; }
+
+template <typename VT, typename PT, int MODE, typename TB>
 __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
-                                                     PT *__restrict__ proj, const ViewIdx *__restrict__ views,
+                                                     PT *__restrict__ out, PT *__restrict__ out2,
+                                                     const TB *__restrict__ y, const float *__restrict__ pi,
+                                                     double *__restrict__ partials, const ViewIdx *__restrict__ views,
                                                      const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
                                                      int nv, double h, int view0, int view_step, int tab_len) {
     extern __shared__ PlaneEntry tab[];
@@ -346,53 +407,115 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
         }
     }
     __syncthreads();
-    if (a >= nu || b >= nv) return;  // no barrier below
-
-    double D[3];
-    const double len = ray_setup(V, nu, nv, a, b, D);
-    const double Dz = D[2];
-    // planes whose z sample lies within the padded grid, for this row
-    const double Bz = Dz * rDm;
-    double zlo = (double)l0, zhi = (double)l1;
-    clip_range(zlo, zhi, V.s[2] - sm * Bz, Bz, -1.5, nz + 0.5);
-    const float scale = (float)(h * len / fabs(D[m]));
-    const double szp = V.s[2] + kVolPad;
-    float acc = 0.f;
-    if (zlo <= zhi && isfinite(Bz)) {
-        const int lz0 = (int)zlo, lz1 = (int)zhi;
+    const bool valid = a < nu && b < nv;
+    double r2 = 0.0;
+    if (valid) {
+        double D[3];
+        const double len = ray_setup(V, nu, nv, a, b, D);
+        const double Dz = D[2];
+        // planes whose z sample lies within the padded grid, for this row
+        const double Bz = Dz * rDm;
+        double zlo = (double)l0, zhi = (double)l1;
+        clip_range(zlo, zhi, V.s[2] - sm * Bz, Bz, -1.5, nz + 0.5);
+        const float scale = (float)(h * len / fabs(D[m]));
+        const double szp = V.s[2] + kVolPad;
+        float acc = 0.f;
+        if (zlo <= zhi && isfinite(Bz)) {
+            const int lz0 = (int)zlo, lz1 = (int)zhi;
 #pragma unroll 2
-        for (int l = lz0; l <= lz1; ++l) {
-            const PlaneEntry e = T[l];
-            const double fz = fma(e.tau, Dz, szp);
-            const double gz = floor(fz);
-            const float wz = (float)(fz - gz);
-            // taps (a0,z0) (a1,z0) (a0,z1) (a1,z1)
-            const float4 r = load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
-            const float q0 = fmaf(wz, r.z - r.x, r.x), q1 = fmaf(wz, r.w - r.y, r.y);
-            acc += fmaf(e.wa, q1 - q0, q0);
+            for (int l = lz0; l <= lz1; ++l) {
+                const PlaneEntry e = T[l];
+                const double fz = fma(e.tau, Dz, szp);
+                const double gz = floor(fz);
+                const float wz = (float)(fz - gz);
+                // taps (a0,z0) (a1,z0) (a0,z1) (a1,z1)
+                const float4 r = load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
+                const float q0 = fmaf(wz, r.z - r.x, r.x), q1 = fmaf(wz, r.w - r.y, r.y);
+                acc += fmaf(e.wa, q1 - q0, q0);
+            }
+        }
+        const float l = acc * scale;
+        if (MODE == kProjPlain) {
+            store_f(out, ((long)blockIdx.z * nv + b) * nu + a, l);
+        } else {
+            const long gi = ((long)v * nv + b) * nu + a;           // this ray in the full stack
+            const long ot = ((long)blockIdx.z * nu + a) * nv + b;  // transposed output
+            const float yv = load_f(y, gi);
+            if (MODE == kProjEmtr) {
+                const float e = expf(-l);
+                store_f(out, ot, (e - expf(-yv)) * scale);
+                store_f(out2, ot, (e * pi[gi]) * scale);
+            } else {
+                const float r = round_as<PT>(yv - l);
+                if (MODE == kProjResidual) store_f(out, ot, r * scale);
+                r2 = (double)r * (double)r;
+            }
         }
     }
-    store_f(proj, ((long)blockIdx.z * nv + b) * nu + a, acc * scale);
+    if (MODE == kProjResidual || MODE == kProjNorm) {
+        // fixed-order block sum of r^2: within each wave, then over the 4 waves
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+        __shared__ double wsum[4];
+        if (lane == 0) wsum[w] = r2;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            partials[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
+                (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    }
 }
 
 hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, void *proj, int proj_dtype,
                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
+    return launch_project_sep_mode(vtx, vty, vt_dtype, kProjPlain, proj, nullptr, proj_dtype, nullptr, MGCT_F32,
+                                   nullptr, nullptr, L, view0, view_step, nviews_sub, s);
+}
+
+size_t project_sep_blocks(const Level &L, int nviews_sub) {
+    return (size_t)((L.nu + 3) / 4) * ((L.nv + 63) / 64) * nviews_sub;
+}
+
+hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtype, int mode, void *out, void *out2,
+                                   int out_dtype, const void *y, int y_dtype, const float *pi, double *partials,
+                                   const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
     dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
-    {
-        const int tab_len = std::max(L.nx, L.ny);
-        const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
-#define MGCT_PROJS(VT, PT)                                                                                      \
-    k_project_sep<VT, PT><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)proj, L.d_views,        \
-                                                 L.d_cols, L.nx, L.ny, L.nz, L.nu, L.nv, L.h, view0, view_step,  \
-                                                 tab_len)
-        if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F32) MGCT_PROJS(float, float);
-        else if (vt_dtype == MGCT_F32 && proj_dtype == MGCT_F16) MGCT_PROJS(float, _Float16);
-        else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F32) MGCT_PROJS(uint16_t, float);
-        else if (vt_dtype == MGCT_BF16 && proj_dtype == MGCT_F16) MGCT_PROJS(uint16_t, _Float16);
+    const int tab_len = std::max(L.nx, L.ny);
+    const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
+#define MGCT_PROJS(VT, PT, MODE, TB)                                                                             \
+    k_project_sep<VT, PT, MODE, TB><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)out, (PT *)out2, \
+                                                           (const TB *)y, pi, partials, L.d_views, L.d_cols, L.nx,  \
+                                                           L.ny, L.nz, L.nu, L.nv, L.h, view0, view_step, tab_len)
+#define MGCT_PROJ_VT(PT, MODE, TB)                                                                               \
+    do {                                                                                                        \
+        if (vt_dtype == MGCT_F32) MGCT_PROJS(float, PT, MODE, TB);                                              \
+        else if (vt_dtype == MGCT_BF16) MGCT_PROJS(uint16_t, PT, MODE, TB);                                     \
+        else return hipErrorInvalidValue;                                                                       \
+    } while (0)
+    const bool of32 = out_dtype == MGCT_F32, of16 = out_dtype == MGCT_F16;
+    const bool yf32 = y_dtype == MGCT_F32, yf16 = y_dtype == MGCT_F16;
+    if (mode == kProjPlain) {
+        if (of32) MGCT_PROJ_VT(float, kProjPlain, float);
+        else if (of16) MGCT_PROJ_VT(_Float16, kProjPlain, float);
         else return hipErrorInvalidValue;
-#undef MGCT_PROJS
-        return hipGetLastError();
+    } else if (mode == kProjResidual) {
+        if (of32 && yf32) MGCT_PROJ_VT(float, kProjResidual, float);
+        else if (of32 && yf16) MGCT_PROJ_VT(float, kProjResidual, _Float16);
+        else if (of16 && yf32) MGCT_PROJ_VT(_Float16, kProjResidual, float);
+        else if (of16 && yf16) MGCT_PROJ_VT(_Float16, kProjResidual, _Float16);
+        else return hipErrorInvalidValue;
+    } else if (mode == kProjEmtr) {
+        if (of32 && yf32) MGCT_PROJ_VT(float, kProjEmtr, float);
+        else return hipErrorInvalidValue;
+    } else if (mode == kProjNorm) {
+        if (yf32) MGCT_PROJ_VT(float, kProjNorm, float);
+        else if (yf16) MGCT_PROJ_VT(float, kProjNorm, _Float16);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
     }
+#undef MGCT_PROJ_VT
+#undef MGCT_PROJS
+    return hipGetLastError();
 }
 
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
@@ -908,11 +1031,13 @@ long bp_waves(const Level &L, int *kz) {
     return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
 }
 
+// View chunks (partial volumes summed afterwards) so that about 16384 waves
+// run, each over at least 8 views.
 int bp_chunks(const Level &L, int nviews_sub) {
     const long waves = bp_waves(L, nullptr);
     long c = (16384 + waves - 1) / waves;
     if (c > 64) c = 64;
-    if (c > nviews_sub) c = nviews_sub;
+    if (c > nviews_sub / 8) c = nviews_sub / 8;
     return c < 1 ? 1 : (int)c;
 }
 

@@ -146,6 +146,17 @@ hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, voi
                                   hipStream_t s);
 hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, void *proj, int proj_dtype,
                               const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
+// The separable projector with a fused epilogue (mode: 0 plain, 1 residual
+// y - A mu transposed and scaled for A^T plus block partial sums of its
+// square, 2 OS-EMTR subset terms, 3 block partial sums of (y - A mu)^2 only);
+// partials holds project_sep_blocks() doubles.
+hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtype, int mode, void *out, void *out2,
+                                   int out_dtype, const void *y, int y_dtype, const float *pi, double *partials,
+                                   const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
+size_t project_sep_blocks(const Level &L, int nviews_sub);
+// OS-EMTR update that also refreshes the separable projector's pair copies
+hipError_t launch_emtr_update_pairs(float *vol, const float *num, const float *den, const unsigned *maxbits,
+                                    void *vtx, void *vty, int vt_dtype, const Level &L, hipStream_t s);
 hipError_t launch_scale_transpose_stack(const void *proj, int proj_dtype, void *pt, int pt_dtype, const Level &L,
                                         int view0, int view_step, int nviews_sub, hipStream_t s);
 // scratch: backproject_scratch_bytes() bytes (partial volumes when the views
