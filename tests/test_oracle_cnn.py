@@ -76,3 +76,28 @@ def test_identity_at_initialisation(rng):
     u = rng.normal(size=(4, 4, 4))
     out, _ = cnn.forward(u, params)
     assert np.array_equal(out, u)
+
+
+def test_adam_constant_gradient_closed_form(rng):
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step, so each Adam step moves a parameter by -lr g/(|g| + eps);
+    a sign flip in either moment, a missing bias correction or a wrong power
+    of beta breaks this."""
+    params = [[rng.normal(size=(2, 3)), rng.normal(size=2)]]
+    grads = [[rng.normal(size=(2, 3)) * 10.0 ** rng.integers(-3, 3, size=(2, 3)), rng.normal(size=2)]]
+    p0 = [[p.copy() for p in layer] for layer in params]
+    state = {}
+    lr, eps = 3e-3, 1e-8
+    for _ in range(5):
+        cnn.adam_step(params, grads, state, lr=lr, eps=eps)
+    for p, q, g in zip(params[0], p0[0], grads[0]):
+        assert np.allclose(p, q - 5 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-12)
+    # a changing gradient: the second step from the moments written out
+    params = [[np.array([1.0])]]
+    state = {}
+    cnn.adam_step(params, [[np.array([2.0])]], state, lr=0.1)
+    cnn.adam_step(params, [[np.array([-1.0])]], state, lr=0.1)
+    m = 0.9 * 0.1 * 2.0 + 0.1 * -1.0
+    v = 0.999 * 0.001 * 4.0 + 0.001 * 1.0
+    step2 = 0.1 * (m / (1 - 0.81)) / (math.sqrt(v / (1 - 0.999 ** 2)) + 1e-8)
+    assert abs(params[0][0][0] - (1.0 - 0.1 * 2.0 / (2.0 + 1e-8) - step2)) < 1e-12
