@@ -122,7 +122,7 @@ def main():
     dom = "backproject@0" if tB >= tA else "project@0"
     t_dom = kt[dom]["ms_avg"] * 1e-3
     achieved = bytes_per_launch / t_dom / 1e9
-    kname = "k_backproject_sep" if dom.startswith("back") else "k_project_sep"
+    kname = "k_backproject_blk" if dom.startswith("back") else "k_project_sep"
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
@@ -255,7 +255,10 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes, scaled by the same counters on a plain copy of known size, per
 # launch; valid only for the kernel source it was measured on.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/backproject_project_128cube_360x192_counters.md
+    "k_backproject_blk": {"source_sha256": "11256a576cd8009fe7d2315870dfe8a1520ef4672834e8ea553d57e61407bbe6", "bytes_per_launch": 502778466},
+}
 
 
 def measured_traffic(kernel):

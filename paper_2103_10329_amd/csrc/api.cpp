@@ -247,6 +247,7 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
         WS(pt, char, lvl(sd == MGCT_F32 ? "pt" : "pt16", g), L.rays() * es, false);
         const size_t nblk = project_sep_blocks(L, L.nviews);
         WS(pp, double, "proj_partials", nblk * 8, false);
+        WS(pp2, double, "proj_partials2", 256 * 8, false);
         WS(nrm, double, "red_scratch", 8, false);
         const int vtd = c.vt_dtype;
         void *vtx, *vty;
@@ -256,7 +257,7 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
             HIPCHK(launch_project_sep_mode(vtx, vty, vtd, 1, pt, nullptr, sd, b, b_dtype, nullptr, pp, L, 0, 1,
                                            L.nviews, s));
         }
-        HIPCHK(launch_finish_sum(pp, (int)nblk, norm2_out ? norm2_out : nrm, s));
+        HIPCHK(launch_finish_sum_wide(pp, (int)nblk, pp2, norm2_out ? norm2_out : nrm, s));
         MGCHK(do_backproject_pt(c, L, g, pt, sd, grad, MGCT_F32, 0, 1, L.nviews, s));
         MGCHK(do_precondition(c, L, g, grad, grad, f, s));
         if (update_out)
@@ -286,6 +287,7 @@ int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b,
     if (L.separable) {
         const size_t nblk = project_sep_blocks(L, L.nviews);
         WS(pp, double, "proj_partials", nblk * 8, false);
+        WS(pp2, double, "proj_partials2", 256 * 8, false);
         void *vtx, *vty;
         MGCHK(pair_copies(c, L, g, vol, MGCT_F32, MGCT_F32, &vtx, &vty, s));
         {
@@ -293,7 +295,7 @@ int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b,
             HIPCHK(launch_project_sep_mode(vtx, vty, MGCT_F32, 3, nullptr, nullptr, MGCT_F32, b, MGCT_F32, nullptr,
                                            pp, L, 0, 1, L.nviews, s));
         }
-        HIPCHK(launch_finish_sum(pp, (int)nblk, norm2_out, s));
+        HIPCHK(launch_finish_sum_wide(pp, (int)nblk, pp2, norm2_out, s));
         return MGCT_OK;
     }
     WS(ax, float, lvl("lw_ax", g), L.rays() * 4, false);

@@ -2,7 +2,8 @@
 // 3-D DFT sized to the grid (circular convolution), for power-of-two edges.
 //
 // Five passes over the volume, each batching whole lines of one axis in LDS
-// (radix-2 Stockham, ping-pong buffers, 4096 complex values per block):
+// (radix-2 Stockham, ping-pong buffers, up to 4096 complex values per block,
+// fewer when that keeps at least 2048 blocks in flight):
 //   1. along x: real input -> complex work array (forward)
 //   2. along y: forward
 //   3. along z: forward, multiply by H, inverse (same lines, one kernel)
@@ -145,52 +146,66 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     RadialH R{table, n_table, rho_max, nx, ny, nz};
     RadialH none{nullptr, 0, 1.f, nx, ny, nz};
     const long nvox = (long)nx * ny * nz;
-    auto pick_B = [&](int n, long lines) {
+    // lines per block: as many as fit kFftElems, fewer while that leaves
+    // under 2048 blocks (down to 8 lines on strided axes, so that a block's
+    // global accesses still cover 64 contiguous bytes)
+    auto pick_B = [&](int n, long lines, bool strided) {
         long B = kFftElems / n;
         if (B > lines) B = lines;
+        const long bmin = strided ? 8 : 1;
+        while (B > bmin && lines / B < 2048) B >>= 1;
         if (B < 1) B = 1;
         return ilog2(B);
     };
-    const size_t lds = 2 * (size_t)kFftElems * sizeof(float2);
+    auto lds_of = [](int logN, int logB) { return 2 * (sizeof(float2) << (logN + logB)); };
+    auto threads_of = [](int logN, int logB) {
+        const int half = 1 << (logN + logB - 1);
+        return half >= 256 ? 256 : (half < 64 ? 64 : half);
+    };
     // pass 1: x, real -> complex
     {
-        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz);
+        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz, false);
         LineMap m{1, 1L << 40, nx, 0};
         const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
         k_fft_pass<true, true, false, false>
-            <<<grid, 256, lds, s>>>(in, nullptr, nullptr, work, logN, logB, m, twx, +1, 1.f, none);
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                in, nullptr, nullptr, work, logN, logB, m, twx, +1, 1.f, none);
     }
     // pass 2: y forward
     {
-        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz);
+        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz, true);
         LineMap m{nx, nx, 1, (long)nx * ny};
         const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
         k_fft_pass<false, false, false, false>
-            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twy, +1, 1.f, none);
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                nullptr, work, nullptr, work, logN, logB, m, twy, +1, 1.f, none);
     }
     // pass 3: z forward, * H, z inverse
     {
-        const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny);
+        const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny, true);
         LineMap m{(long)nx * ny, 1L << 40, 1, 0};
         const unsigned grid = (unsigned)(((long)nx * ny) >> logB);
         k_fft_pass<false, false, false, true>
-            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twz, +1, 1.f, R);
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                nullptr, work, nullptr, work, logN, logB, m, twz, +1, 1.f, R);
     }
     // pass 4: y inverse
     {
-        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz);
+        const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz, true);
         LineMap m{nx, nx, 1, (long)nx * ny};
         const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
         k_fft_pass<false, false, false, false>
-            <<<grid, 256, lds, s>>>(nullptr, work, nullptr, work, logN, logB, m, twy, -1, 1.f, none);
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                nullptr, work, nullptr, work, logN, logB, m, twy, -1, 1.f, none);
     }
     // pass 5: x inverse -> real, scaled
     {
-        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz);
+        const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz, false);
         LineMap m{1, 1L << 40, nx, 0};
         const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
         k_fft_pass<true, false, true, false>
-            <<<grid, 256, lds, s>>>(nullptr, work, out, nullptr, logN, logB, m, twx, -1, (float)(1.0 / (double)nvox), none);
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                nullptr, work, out, nullptr, logN, logB, m, twx, -1, (float)(1.0 / (double)nvox), none);
     }
     return hipGetLastError();
 }

@@ -1017,6 +1017,12 @@ __global__ void k_sum_chunks(const float *__restrict__ part, OT *__restrict__ ou
 #ifndef MGCT_BP_KZMAX
 #define MGCT_BP_KZMAX 2
 #endif
+#ifndef MGCT_BP_HALF_MAXNZ
+#define MGCT_BP_HALF_MAXNZ 32  // grids at most this deep use the paired-row kernel
+#endif
+#ifndef MGCT_BP_MIN_VIEWS
+#define MGCT_BP_MIN_VIEWS 2    // fewest views per view chunk
+#endif
 constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 
 // waves of the separable back-projector: one per kBpBI x kBpBJ block of
@@ -1027,17 +1033,17 @@ long bp_waves(const Level &L, int *kz) {
     int KZ = 1;
     if (MGCT_BP_KZMAX >= 2 && 2 * 64 <= L.nz) KZ = 2;
     if (kz) *kz = KZ;
-    if (L.nz <= 32) return (long)L.nx * ((L.ny + 1) / 2);
+    if (L.nz <= MGCT_BP_HALF_MAXNZ) return (long)L.nx * ((L.ny + 1) / 2);
     return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
 }
 
 // View chunks (partial volumes summed afterwards) so that about 16384 waves
-// run, each over at least 8 views.
+// run, each over at least MGCT_BP_MIN_VIEWS views.
 int bp_chunks(const Level &L, int nviews_sub) {
     const long waves = bp_waves(L, nullptr);
     long c = (16384 + waves - 1) / waves;
     if (c > 64) c = 64;
-    if (c > nviews_sub / 8) c = nviews_sub / 8;
+    if (c > nviews_sub / MGCT_BP_MIN_VIEWS) c = nviews_sub / MGCT_BP_MIN_VIEWS;
     return c < 1 ? 1 : (int)c;
 }
 
@@ -1065,7 +1071,7 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     k_backproject_sep<K, NP, OT, PT, H><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
                                                       L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
                                                       view_step, per)
-    if (L.nz <= 32) {
+    if (L.nz <= MGCT_BP_HALF_MAXNZ) {
         MGCT_BP(1, true);
     } else {
         if (KZ == 2) MGCT_BPB(2);

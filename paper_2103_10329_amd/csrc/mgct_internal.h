@@ -185,6 +185,8 @@ hipError_t launch_residual(const void *b, int b_dtype, const void *ax, void *r, 
                            double *partials, int nblocks, hipStream_t s);
 hipError_t launch_sumsq(const float *x, size_t n, double *partials, int nblocks, hipStream_t s);
 hipError_t launch_finish_sum(const double *partials, int n, double *out, hipStream_t s);
+// The same for many partials (two fixed-order stages; tmp holds 256 doubles).
+hipError_t launch_finish_sum_wide(const double *partials, int n, double *tmp, double *out, hipStream_t s);
 hipError_t launch_axpy(float *y, const float *x, double alpha, size_t n, hipStream_t s);
 hipError_t launch_scale_by_inv_sqrt(float *x, size_t n, const double *sumsq, double *lambda_out,
                                     hipStream_t s);

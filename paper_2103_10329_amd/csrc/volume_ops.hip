@@ -104,8 +104,24 @@ __global__ __launch_bounds__(256) void k_finish_sum(const double *partials, int 
     double t = block_sum(acc);
     if (threadIdx.x == 0) out[0] = t;
 }
+// Stage one of a wide sum: block b adds partials [b*per, (b+1)*per) in a fixed
+// order into tmp[b].
+__global__ __launch_bounds__(256) void k_sum_stage(const double *partials, int n, int per, double *tmp) {
+    double acc = 0.0;
+    const int beg = blockIdx.x * per, end = min(n, beg + per);
+    for (int i = beg + threadIdx.x; i < end; i += 256) acc += partials[i];
+    double t = block_sum(acc);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = t;
+}
 hipError_t launch_finish_sum(const double *partials, int n, double *out, hipStream_t s) {
     k_finish_sum<<<1, 256, 0, s>>>(partials, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_finish_sum_wide(const double *partials, int n, double *tmp, double *out, hipStream_t s) {
+    if (n <= 4096) return launch_finish_sum(partials, n, out, s);
+    const int nb = 256, per = (n + nb - 1) / nb;
+    k_sum_stage<<<nb, 256, 0, s>>>(partials, n, per, tmp);
+    k_finish_sum<<<1, 256, 0, s>>>(tmp, nb, out);
     return hipGetLastError();
 }
 
