@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--sirt-cap", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
+    ap.add_argument("--paper-shaped", action="store_true",
+                    help="only run the 640x640x2304 / 3600 x 760^2 workload (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (views would shard across "
@@ -55,6 +57,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.paper_shaped:
+        paper_shaped()
         return
 
     import torch
@@ -271,6 +276,92 @@ def measured_traffic(kernel):
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
     return t["bytes_per_launch"]
+
+
+def paper_shaped():
+    """The paper's data shape on one GPU (Sec. 2: 3600 radiographs of 760^2,
+    a 640 x 640 x 2304 volume), FP32: one A and one A^T over all views, then
+    two iterations of Algorithm 1 on 4 grids with eq. 5's stencil (the FFT
+    filter needs power-of-two edges), a synthetic tall phantom and Poisson
+    data.  Step sizes: power iteration on every 10th view, scaled by the view
+    ratio (A^T A sums over views) and by 0.95.  Image error per height band
+    inside the evaluation cylinder shows the sample's ends, seen by fewer
+    views, reconstructing worse."""
+    import torch
+
+    import paper_2103_10329_amd as mg
+    import synth
+    cfg = synth.PAPER_SHAPED
+    nx, nz, V = cfg.n, synth.PAPER_SHAPED_NZ, cfg.n_views
+    views = synth.helix_trajectory(V, cfg.pixel)
+    ctx = mg.Context(0)
+    ctx.set_geometry(nx, nx, nz, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views)
+    t0 = time.time()
+    ph = synth.random_phantom(cfg, 5000, extent=(32.0, 32.0, nz * cfg.h))
+    truth = ctx.synth_voxelize(ph, ss=2)
+    gen = torch.Generator(device="cuda").manual_seed(6000)
+    b_true = ctx.synth_line_integrals(ph)
+    counts = torch.poisson(cfg.noise_level * torch.exp(-b_true.double()), generator=gen)
+    b = torch.log(cfg.noise_level / torch.clamp(counts, min=1.0)).float()
+    del counts, b_true
+    torch.cuda.synchronize()
+    log("paper-shaped data %.1fs" % (time.time() - t0))
+    out = {"workload": "paper-shaped 640x640x2304, 3600 views of 760^2, FP32", "voxel_views": nx * nx * nz * V}
+    # one A and one A^T (after a warm-up of each), HIP-event kernel times
+    vol = truth.clone()
+    p = ctx.project(vol)
+    ctx.backproject(p)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True)
+    ctx.project(vol, out=p)
+    q = ctx.backproject(p)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(False)
+    tA = ctx.kernel_time(mg.MGCT_OP_PROJECT, 0)[0]
+    tB = ctx.kernel_time(mg.MGCT_OP_BACKPROJECT, 0)[0]
+    n4 = nx * nx * nz * V
+    out["A_ms"], out["At_ms"] = tA, tB
+    out["A_gvox_views_s"] = n4 / (tA * 1e-3) / 1e9
+    out["At_gvox_views_s"] = n4 / (tB * 1e-3) / 1e9
+    out["a_plus_at_gvox_views_s"] = n4 / ((tA + tB) * 1e-3) / 1e9
+    log("paper-shaped A %.1f ms, A^T %.1f ms" % (tA, tB))
+    del p, q
+    # step sizes from every 10th view
+    filt = mg.filter_eq5()
+    sub = mg.Context(0)
+    sub.set_geometry(nx, nx, nz, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views[::10])
+    alphas = [0.95 * sub.estimate_step(filt, level=g, iters=10, seed=0) / 10.0 for g in range(cfg.levels - 1)]
+    sub.close()
+    out["alphas"] = alphas
+    log("paper-shaped alphas", alphas)
+    # two iterations of Algorithm 1 from zero
+    xc = (np.arange(nx) - (nx - 1) / 2.0) * cfg.h
+    mask = torch.from_numpy(xc[None, :] ** 2 + xc[:, None] ** 2 <= 14.4 ** 2).cuda()[None]  # cylinder, [1][y][x]
+    zc = torch.from_numpy((np.arange(nz) - (nz - 1) / 2.0) * cfg.h).cuda()
+    # a height z is seen from source heights within ~17.6 of it (the detector's
+    # half-height at the axis) inside [-48, 48]: every view angle for |z| <= 30,
+    # about 70-55 % of them at 36 <= |z| <= 46 (the phantom reaches |z| ~ 44)
+    bands = {"middle |z|<=20": zc.abs() <= 20.0, "ends 36<=|z|<=46": (zc.abs() >= 36.0) & (zc.abs() <= 46.0)}
+    bn = float(torch.linalg.vector_norm(b.double()))
+    vol.zero_()
+    iters = []
+    for it in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.multigrid_solve(vol, b, cfg.levels, 1, filt, alphas=alphas, want_hist=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        r = float(torch.linalg.vector_norm((b - ctx.project(vol)).double())) / bn
+        errs = {}
+        for name, zb in bands.items():
+            m = mask & zb[:, None, None]
+            t = truth[m].double()
+            errs[name] = float(torch.linalg.vector_norm(vol[m].double() - t) / torch.linalg.vector_norm(t))
+        iters.append({"seconds": dt, "rel_residual": r, "masked_error": errs})
+        log("paper-shaped iteration", it + 1, iters[-1])
+    out["pmg_iterations"] = iters
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def copy_calibration(size_mib=1024, reps=5):

@@ -184,6 +184,8 @@ int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_d
  * d/d(view) sum_rays cot * (A vol) for each view's s, d, u, v (physical
  * units), differentiating the Joseph sums with their major axes and plane
  * sets held fixed (the sum is piecewise smooth).  Synchronises the stream.
+ * Returns MGCT_ERR_NOT_IMPLEMENTED when the grid's padded FP32 copy would
+ * exceed 4 GiB (about 1020^3 voxels).
  */
 int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *cot, double *dviews,
                            hipStream_t stream);

@@ -824,6 +824,8 @@ int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *
     Level *Lp;
     MGCHK(get_level(c, level, &Lp));
     Level &L = *Lp;
+    // the derivative kernel addresses its padded FP32 copy with 32-bit byte offsets
+    if (L.padded_vox() * 4 > 0xFFFFFFF0ull) return MGCT_ERR_NOT_IMPLEMENTED;
     void *vt = workspace(c, lvl("vt32", level), L.padded_vox() * 4, true);
     if (!vt) return MGCT_ERR_OOM;
     WS(partial, double, lvl("gg_partial", level), geom_grad_partial_bytes(L), false);

@@ -158,6 +158,8 @@ int build_level(Ctx &c, int g, Level &L) {
             o.ad2 = (float)ad2;
             o.flags = 0;
             o.pad = 0;
+            o.r0lo = o.r1lo = HUGE_VAL;
+            o.r0hi = o.r1hi = -HUGE_VAL;
             for (int a = 0; a < nu; ++a) {
                 double ca = a - 0.5 * (nu - 1);
                 double Dx = q.d[0] + ca * q.u[0] - q.s[0];
@@ -165,6 +167,13 @@ int build_level(Ctx &c, int g, Level &L) {
                 cols[(size_t)v * nu + a] = ColD{Dx, Dy, 1.0 / Dx, 1.0 / Dy, Dx / q.v[2], Dy / q.v[2],
                                                 (int)axis[(size_t)v * nu + a], {0, 0, 0}};
                 o.flags |= axis[(size_t)v * nu + a] == 0 ? 1 : 2;
+                if (axis[(size_t)v * nu + a] == 0) {
+                    o.r0lo = std::min(o.r0lo, 1.0 / Dx);
+                    o.r0hi = std::max(o.r0hi, 1.0 / Dx);
+                } else {
+                    o.r1lo = std::min(o.r1lo, 1.0 / Dy);
+                    o.r1hi = std::max(o.r1hi, 1.0 / Dy);
+                }
             }
         }
     }

@@ -362,7 +362,8 @@ constexpr int kProjPlain = 0, kProjResidual = 1, kProjEmtr = 2, kProjNorm = 3;
 template <typename T> __device__ __forceinline__ float round_as(float x) { return x; }
 template <> __device__ __forceinline__ float round_as<_Float16>(float x) { return (float)(_Float16)x; }
 
-template <typename VT, typename PT, int MODE, typename TB>
+// WIDE: the pair copies exceed 4 GiB, so sample addresses are formed in 64 bits.
+template <typename VT, typename PT, int MODE, typename TB, bool WIDE>
 __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
                                                      PT *__restrict__ out, PT *__restrict__ out2,
                                                      const TB *__restrict__ y, const float *__restrict__ pi,
@@ -429,7 +430,8 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
                 const double gz = floor(fz);
                 const float wz = (float)(fz - gz);
                 // taps (a0,z0) (a1,z0) (a0,z1) (a1,z1)
-                const float4 r = load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
+                const float4 r = WIDE ? load_quad(vt + 2L * ((long)e.off + (long)gz), 0u)
+                                      : load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
                 const float q0 = fmaf(wz, r.z - r.x, r.x), q1 = fmaf(wz, r.w - r.y, r.y);
                 acc += fmaf(e.wa, q1 - q0, q0);
             }
@@ -481,10 +483,19 @@ hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtyp
     dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
     const int tab_len = std::max(L.nx, L.ny);
     const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
+    const size_t copy_bytes = pair_copy_elems(L) * (vt_dtype == MGCT_F32 ? 4 : 2);
+    const bool wide = copy_bytes > 0xFFFFFFF0ull;
+    if (wide && mode == kProjEmtr) return hipErrorNotSupported;  // coarse grids only
+#define MGCT_PROJS_W(VT, PT, MODE, TB, W)                                                                        \
+    k_project_sep<VT, PT, MODE, TB, W><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)out,         \
+                                                              (PT *)out2, (const TB *)y, pi, partials, L.d_views,    \
+                                                              L.d_cols, L.nx, L.ny, L.nz, L.nu, L.nv, L.h, view0,    \
+                                                              view_step, tab_len)
 #define MGCT_PROJS(VT, PT, MODE, TB)                                                                             \
-    k_project_sep<VT, PT, MODE, TB><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)out, (PT *)out2, \
-                                                           (const TB *)y, pi, partials, L.d_views, L.d_cols, L.nx,  \
-                                                           L.ny, L.nz, L.nu, L.nv, L.h, view0, view_step, tab_len)
+    do {                                                                                                        \
+        if (wide && MODE != kProjEmtr) MGCT_PROJS_W(VT, PT, MODE, TB, (MODE != kProjEmtr));                     \
+        else MGCT_PROJS_W(VT, PT, MODE, TB, false);                                                             \
+    } while (0)
 #define MGCT_PROJ_VT(PT, MODE, TB)                                                                               \
     do {                                                                                                        \
         if (vt_dtype == MGCT_F32) MGCT_PROJS(float, PT, MODE, TB);                                              \
@@ -515,6 +526,7 @@ hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtyp
     }
 #undef MGCT_PROJ_VT
 #undef MGCT_PROJS
+#undef MGCT_PROJS_W
     return hipGetLastError();
 }
 
@@ -793,17 +805,35 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
 // (x = i for PART 0, y = j for PART 1) is shared by the block's rows lying in
 // it, so each column's detector-row sums are formed once per plane and
 // weighted into every row the column reaches (the in-plane hat 1 - |off|).
-// Same arithmetic per (voxel, column) as bp_part.
-template <int PART, int KZ, int NP, typename PT, int BI, int BJ>
+// Same arithmetic per (voxel, column) as bp_part.  ZS (grids with more than
+// one z chunk per row): [zw0, zw1] is the wave's z range, and planes and
+// columns whose detector rows stay more than a voxel away from it are
+// skipped (tall volumes, where a view's cone covers part of the height).
+template <int PART, int KZ, int NP, typename PT, int BI, int BJ, bool ZS>
 __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
                                             const PT *base1, int i0, int j0, int nu, int nv,
-                                            const double (&kd)[KZ], float (&pv)[NP][BI * BJ][KZ]) {
+                                            const double (&kd)[KZ], double zw0, double zw1,
+                                            float (&pv)[NP][BI * BJ][KZ]) {
     constexpr int NPL = PART == 0 ? BI : BJ;  // planes in the block
     constexpr int NR = PART == 0 ? BJ : BI;   // rows per plane
     const int r0 = PART == 0 ? j0 : i0;
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl) {
         const int P = (PART == 0 ? i0 : j0) + pl;
+        // distance of the plane from the source along the major axis
+        const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
+        if (ZS) {
+            // rows 0 and nv-1 lie at z = s_z + tau dz0 and s_z + tau dzn at the
+            // plane, tau = dm / D over the view's columns of this part: if even
+            // the extremes stay a voxel away from the wave's z range, skip the plane
+            const double ta = dm * (PART == 0 ? S.r0lo : S.r1lo), tb = dm * (PART == 0 ? S.r0hi : S.r1hi);
+            const double dzn = fma(S.vz, (double)(nv - 1), S.dz0);
+            const double z1 = fma(ta, S.dz0, S.sz), z2 = fma(tb, S.dz0, S.sz);
+            const double z3 = fma(ta, dzn, S.sz), z4 = fma(tb, dzn, S.sz);
+            if (fmax(fmax(z1, z2), fmax(z3, z4)) <= zw0 - 1.0 || fmin(fmin(z1, z2), fmin(z3, z4)) >= zw1 + 1.0)
+                continue;
+        }
+        const double inv_dm = 1.0 / dm;
         const float fp = (float)P, flo = (float)(r0 - 1), fhi = (float)(r0 + NR);
         const float c1 = PART == 0 ? column_coord(S, fp, flo) : column_coord(S, flo, fp);
         const float c2 = PART == 0 ? column_coord(S, fp, fhi) : column_coord(S, fhi, fp);
@@ -811,9 +841,6 @@ __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__rest
         int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
         alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
         ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
-        // distance of the plane from the source along the major axis
-        const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
-        const double inv_dm = 1.0 / dm;
         for (int a = alo; a <= ahi; ++a) {
             const ColD C = cv[a];
             if (C.axis != PART) continue;
@@ -830,6 +857,10 @@ __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__rest
             if (!any) continue;
             const double tz = tau * S.vz;                                // row spacing along z at the plane
             const double zc = fma(tau, S.dz0, S.sz);                     // z of row 0 at the plane
+            // the column's rows span [zc, zc + (nv-1) tz] at the plane: no
+            // voxel of the wave within one voxel of it, no contribution
+            const double zend = fma(tz, (double)(nv - 1), zc);
+            if (ZS && (fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0)) continue;
             const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;     // 1 / tz
             const double hw = fabs(rtz);
             const PT *col0 = base0 + (long)a * nv;
@@ -852,7 +883,7 @@ __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__rest
 
 // Back-projector over BI x BJ blocks of rows: wave -> (block, z chunk), lane
 // -> z = zc_id * 64 KZ + 64 q + lane.  Views and chunks as k_backproject_sep.
-template <int KZ, int NP, typename OT, typename PT, int BI, int BJ>
+template <int KZ, int NP, typename OT, typename PT, int BI, int BJ, bool ZS>
 __global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
                                                          OT *__restrict__ vol0, OT *__restrict__ vol1,
                                                          float *__restrict__ part0, float *__restrict__ part1,
@@ -873,6 +904,7 @@ __global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ 
     double kd[KZ];
 #pragma unroll
     for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
+    const double zw0 = (double)(zc_id * 64 * KZ), zw1 = zw0 + (double)(64 * KZ - 1);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][NB][KZ];
 #pragma unroll
@@ -897,8 +929,8 @@ __global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ 
         const ColD *cv = cols + (long)v * nu;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        if (S.flags & 1) bp_part_blk<0, KZ, NP, PT, BI, BJ>(S, cv, base0, base1, i0, j0, nu, nv, kd, pv);
-        if (S.flags & 2) bp_part_blk<1, KZ, NP, PT, BI, BJ>(S, cv, base0, base1, i0, j0, nu, nv, kd, pv);
+        if (S.flags & 1) bp_part_blk<0, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, kd, zw0, zw1, pv);
+        if (S.flags & 2) bp_part_blk<1, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, kd, zw0, zw1, pv);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1063,10 +1095,16 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     float *part0 = part, *part1 = part ? part + (long)nchunks * nvox : nullptr;
     if (nchunks > 1 && !part) return hipErrorInvalidValue;
     dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
+#define MGCT_BPB_Z(K, Z)                                                                                            \
+    k_backproject_blk<K, NP, OT, PT, kBpBI, kBpBJ, Z><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1,       \
+                                                                         L.d_sep, L.d_cols, L.d_axis, L.nx, L.ny,   \
+                                                                         L.nz, L.nu, L.nv, nviews_sub, view0,       \
+                                                                         view_step, per)
 #define MGCT_BPB(K)                                                                                                 \
-    k_backproject_blk<K, NP, OT, PT, kBpBI, kBpBJ><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep,  \
-                                                                      L.d_cols, L.d_axis, L.nx, L.ny, L.nz, L.nu,    \
-                                                                      L.nv, nviews_sub, view0, view_step, per)
+    do {                                                                                                            \
+        if (L.nz > 64 * (K)) MGCT_BPB_Z(K, true);                                                                   \
+        else MGCT_BPB_Z(K, false);                                                                                  \
+    } while (0)
 #define MGCT_BP(K, H)                                                                                               \
     k_backproject_sep<K, NP, OT, PT, H><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
                                                       L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
@@ -1079,6 +1117,7 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     }
 #undef MGCT_BP
 #undef MGCT_BPB
+#undef MGCT_BPB_Z
     if (nchunks_out) *nchunks_out = nchunks;
     if (nchunks > 1 && !leave_chunks) {
         unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);

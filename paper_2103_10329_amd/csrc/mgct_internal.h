@@ -25,6 +25,8 @@ struct ViewIdx {
 // ray through (px, py, .) is (an0 + an1 px + an2 py)/(ad0 + ad1 px + ad2 py).
 struct SepView {
     double sx, sy, sz, dz0, vz;
+    double r0lo, r0hi;  // range of 1/Dx over the view's x-major columns
+    double r1lo, r1hi;  // range of 1/Dy over its y-major columns
     float an0, an1, an2, ad0, ad1, ad2;
     int flags;  // bit 0: the view has x-major columns, bit 1: y-major columns
     int pad;

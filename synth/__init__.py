@@ -9,6 +9,7 @@ method's arithmetic (no projector, no back-projector, no filter, no solver).
 
 from .geometry import (  # noqa: F401
     CONFIGS, ScanConfig, trajectory, perturb_geometry, volume_axes, evaluation_mask, masked_rel_error,
+    PAPER_SHAPED, PAPER_SHAPED_NZ, PAPER_SHAPED_Z_RANGE, helix_trajectory,
 )
 from .phantom import (  # noqa: F401
     Phantom,

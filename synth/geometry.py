@@ -76,6 +76,27 @@ CONFIGS = {
 }
 
 
+# Paper-shaped workload (the scan of Sec. 2: 3600 radiographs binned to 760^2
+# and a 640 x 640 x 2304 volume of a tall sample): the same physical width as
+# the workloads above (32 units, h = 0.05), height 115.2 units, 216 ellipsoids
+# (60 per 32^3 units), Poisson I0 = 1e4, a golden-angle helix over source
+# heights [-48, 48] (the detector covers 36 units of height at the axis, so the
+# sample's ends are seen by fewer views than its middle).
+PAPER_SHAPED = ScanConfig("paper", 640, 760, 760, 3600, 1, 216, (0.01, 0.3), "poisson", 1e4, levels=4)
+PAPER_SHAPED_NZ = 2304
+PAPER_SHAPED_Z_RANGE = (-48.0, 48.0)
+
+
+def helix_trajectory(n_views: int, pixel: float, z_range=PAPER_SHAPED_Z_RANGE) -> np.ndarray:
+    """Golden-angle azimuths with the source height rising linearly with the
+    view index over z_range (a helix), shape (n_views, 12) float64."""
+    views = trajectory(n_views, 2, pixel)
+    z = np.linspace(z_range[0], z_range[1], n_views)
+    views[:, 2] = z
+    views[:, 5] = z
+    return views
+
+
 def trajectory(n_views: int, z_levels: int, pixel: float, z_range=(-8.0, 8.0)) -> np.ndarray:
     """Golden-angle + height-lattice trajectory, shape (n_views, 12) float64."""
     i = np.arange(n_views, dtype=np.float64)

@@ -72,27 +72,30 @@ def _random_rotation(rng: np.random.Generator) -> np.ndarray:
     ])
 
 
-def random_phantom(cfg: ScanConfig, seed: int, fov: float = FOV) -> Phantom:
+def random_phantom(cfg: ScanConfig, seed: int, fov: float = FOV, extent=None) -> Phantom:
     """Ellipsoids with centres in the inner 70% of the box, random rotations,
     semi-axes in ``cfg.semi_axis_range`` and attenuation in ``cfg.kappa``;
     plus axis-aligned cubes (side U[0.25, 1]) until ``cfg.cube_fraction`` of
-    the box is covered in expectation."""
+    the box is covered in expectation.  The box is fov^3 centred at the
+    origin, or extent = (ex, ey, ez) for a box of another shape (the
+    semi-axis range is then taken as is)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    ext = np.array((fov, fov, fov) if extent is None else extent, dtype=np.float64)
     K = cfg.n_ellipsoids
     ell = np.zeros((K, 16))
-    lo, hi = cfg.semi_axis_range
+    lo, hi = cfg.semi_axis_range if extent is None else (2.0 * (10.0 / 60) ** (1 / 3), 8.0 * (10.0 / 60) ** (1 / 3))
     for k in range(K):
-        ell[k, 0:3] = rng.uniform(-0.35 * fov, 0.35 * fov, size=3)
+        ell[k, 0:3] = rng.uniform(-0.35 * ext, 0.35 * ext)
         ell[k, 3:12] = _random_rotation(rng).reshape(-1)
         ell[k, 12:15] = rng.uniform(lo, hi, size=3)
         ell[k, 15] = rng.uniform(*cfg.kappa)
     boxes = np.zeros((0, 7))
     if cfg.cube_fraction > 0:
         mean_vol = (1.0 ** 4 - 0.25 ** 4) / (4 * 0.75)  # E[s^3], s ~ U[0.25, 1]
-        J = int(round(cfg.cube_fraction * fov ** 3 / mean_vol))
+        J = int(round(cfg.cube_fraction * float(np.prod(ext)) / mean_vol))
         boxes = np.zeros((J, 7))
         side = rng.uniform(0.25, 1.0, size=J)
-        cen = rng.uniform(-0.5 * fov, 0.5 * fov, size=(J, 3))
+        cen = rng.uniform(-0.5 * ext, 0.5 * ext, size=(J, 3))
         boxes[:, 0:3] = cen - side[:, None] / 2
         boxes[:, 3:6] = cen + side[:, None] / 2
         boxes[:, 6] = rng.uniform(*cfg.kappa, size=J)
