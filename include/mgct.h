@@ -60,7 +60,8 @@ typedef enum { MGCT_F32 = 0, MGCT_F16 = 1, MGCT_BF16 = 2 } mgct_dtype;
 typedef enum {
     MGCT_FILTER_IDENTITY = 0,  /* p = delta: plain Landweber / SIRT, eq. 2 */
     MGCT_FILTER_STENCIL27 = 1, /* circular 3^3 convolution, eq. 5 taps (or any 27 taps) */
-    MGCT_FILTER_RADIAL = 2     /* circular convolution applied in Fourier space: H(rho) */
+    MGCT_FILTER_RADIAL = 2,    /* circular convolution applied in Fourier space: H(rho) */
+    MGCT_FILTER_TRANSFER = 3   /* circular convolution applied in Fourier space: H(k) per grid */
 } mgct_filter_kind;
 
 /*
@@ -72,6 +73,11 @@ typedef enum {
  *   frequencies k_a in [-N_a/2, N_a/2), and H is linear interpolation of
  *   `radial_table` (host, n_table >= 2 samples uniformly on [0, rho_max],
  *   clamped beyond).  Every grid edge must be a power of two, 2..1024.
+ * TRANSFER: as RADIAL with an arbitrary real transfer function: the DFT is
+ *   multiplied by transfer[level][(kz*ny + ky)*nx + kx] (device F32 array of
+ *   the grid's size, unsigned frequency indices as the DFT orders them), one
+ *   array per grid the filter is used on (see mgct_psf_spectrum for the one
+ *   derived from the scan).  The caller owns the arrays.
  */
 typedef struct {
     int kind;
@@ -79,6 +85,7 @@ typedef struct {
     const float *radial_table;
     int n_table;
     float rho_max;
+    const float *transfer[8];
 } mgct_filter;
 
 /* Parameters of Algorithm 1 (mgct_multigrid_solve). */
@@ -201,6 +208,37 @@ int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *
  */
 int mgct_geometry_param_grad(int n_views, const double *views0, const double *dviews, double voxel, double dx,
                              double dz, double tilt_deg, double grad[3]);
+
+/*
+ * Derived preconditioners (Sec. 3 leaves more rigorously derived kernels to
+ * later work; this measures the one the scan implies).  T = the transfer
+ * function of A^T A on grid `level`: the real part of the 3-D DFT of
+ * A^T A applied to a unit impulse at voxel (nx/2, ny/2, nz/2), phase-shifted
+ * to the origin (A^T A is symmetric, so the spectrum of its impulse
+ * response is real up to rounding).  T: device F32 [nz][ny][nx], DFT order.
+ * Every grid edge must be a power of two, 2..1024.
+ */
+int mgct_psf_spectrum(void *ctx, int level, float *T, hipStream_t stream);
+
+/*
+ * H = 1 / max(T, floor_rel * T[0]) elementwise (T[0] = the DC gain): the
+ * approximate deconvolution of the measured point-spread function, bounded
+ * where the scan transmits little.  T, H: device F32 arrays of grid `level`
+ * (must not alias: every element reads T[0]; INVALID_ARG if T == H).
+ */
+int mgct_transfer_from_spectrum(void *ctx, int level, const float *T, double floor_rel, float *H,
+                                hipStream_t stream);
+
+/*
+ * Shell averages of a spectrum on grid `level`: profile[i] (host, n_table
+ * doubles) = mean of T over the frequencies whose rho (as for RADIAL) rounds
+ * to sample i of n_table samples on [0, rho_max]; counts (host, may be NULL)
+ * receives the number in each shell (0: profile NaN).  Sums are accumulated in
+ * 64-bit fixed point (2^-24 units), so the result does not depend on
+ * scheduling.  Synchronises the stream.
+ */
+int mgct_radial_profile(void *ctx, int level, const float *T, int n_table, double rho_max, double *profile,
+                        int *counts, hipStream_t stream);
 
 /* Restrict (Algorithm 1): coarse = 2x2x2 block mean of fine (grid level -> level+1). */
 int mgct_restrict_volume(void *ctx, int level, const float *fine, float *coarse, hipStream_t stream);

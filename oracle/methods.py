@@ -19,6 +19,7 @@ __all__ = [
     "bilateral", "splitmix64_uniform", "power_iteration", "landweber_step", "osemtr",
     "multigrid", "filter_identity", "filter_stencil27", "filter_radial",
     "perturbation_jacobian", "geometry_param_grad",
+    "psf_spectrum", "transfer_from_spectrum", "radial_profile", "transfer_filter",
 ]
 
 
@@ -344,3 +345,57 @@ def geometry_param_grad(views0, dviews, h, dx, dz, tilt_deg) -> np.ndarray:
     gradient with respect to (s, d, u, v)."""
     J = perturbation_jacobian(np.asarray(views0, dtype=np.float64), h, dx, dz, tilt_deg)
     return np.einsum("vk,vkp->p", np.asarray(dviews, dtype=np.float64), J)
+
+
+# ---------------------------------------------------------------------------
+# Preconditioners derived from the scan (Sec. 3 leaves more rigorously derived
+# kernels to later work; these measure the one the scan implies).
+
+def psf_spectrum(geom: Geom) -> np.ndarray:
+    """Transfer function of A^T A: the real part of the 3-D DFT of
+    A^T A applied to a unit impulse at voxel (nx/2, ny/2, nz/2), multiplied by
+    exp(+2 pi i k.c/n) to move the impulse to the origin (shift theorem).  The
+    real part is the transfer function of the even part of that response.
+    [kz][ky][kx] in DFT order.  parity pinned: the dense matrix's column,
+    sum_k T = N^3 ||A e_c||^2 and T[0] = sum of the response."""
+    c = (geom.nx // 2, geom.ny // 2, geom.nz // 2)
+    delta = np.zeros(geom.vol_shape)
+    delta[c[2], c[1], c[0]] = 1.0
+    psf = backproject(geom, project(geom, delta))
+    X = np.fft.fftn(psf)
+    kz, ky, kx = np.meshgrid(np.arange(geom.nz), np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
+    phase = 2.0 * np.pi * (kx * c[0] / geom.nx + ky * c[1] / geom.ny + kz * c[2] / geom.nz)
+    return np.real(X * np.exp(1j * phase))
+
+
+def transfer_from_spectrum(T: np.ndarray, floor_rel: float) -> np.ndarray:
+    """H = 1 / max(T, floor_rel * T[0]) (T[0] = the DC gain)."""
+    return 1.0 / np.maximum(T, floor_rel * T.flat[0])
+
+
+def radial_profile(T: np.ndarray, n_table: int, rho_max: float):
+    """Mean of T over each shell of frequencies whose rho = 2 |k/N| (signed
+    frequencies) rounds to sample i of n_table on [0, rho_max]; rho and the
+    rounding are evaluated in FP32 as the library does, so both sides assign
+    every frequency to the same shell.  Returns (means with NaN for empty
+    shells, counts).  parity pinned: constants, rho itself."""
+    nz, ny, nx = T.shape
+    def signed(n):
+        k = np.arange(n)
+        return np.where(k < n // 2, k, k - n).astype(np.float32) / np.float32(n)
+    fz, fy, fx = np.meshgrid(signed(nz), signed(ny), signed(nx), indexing="ij")
+    rho = np.float32(2.0) * np.sqrt(fx * fx + fy * fy + fz * fz, dtype=np.float32)
+    t = rho / np.float32(rho_max) * np.float32(n_table - 1)
+    b = (t + np.float32(0.5)).astype(np.int64)
+    keep = b < n_table
+    sums = np.bincount(b[keep], weights=T[keep].astype(np.float64), minlength=n_table)
+    cnt = np.bincount(b[keep], minlength=n_table)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        prof = np.where(cnt > 0, sums / np.maximum(cnt, 1), np.nan)
+    return prof, cnt
+
+
+def transfer_filter(x: np.ndarray, H: np.ndarray) -> np.ndarray:
+    """Circular convolution with transfer function H (DFT order): real part
+    of IDFT(DFT(x) H)."""
+    return np.real(np.fft.ifftn(np.fft.fftn(x) * H))

@@ -29,7 +29,7 @@ MGCT_ERR_NOT_IMPLEMENTED = -7
 MGCT_ERR_NO_GEOMETRY = -8
 
 MGCT_F32, MGCT_F16, MGCT_BF16 = 0, 1, 2
-MGCT_FILTER_IDENTITY, MGCT_FILTER_STENCIL27, MGCT_FILTER_RADIAL = 0, 1, 2
+MGCT_FILTER_IDENTITY, MGCT_FILTER_STENCIL27, MGCT_FILTER_RADIAL, MGCT_FILTER_TRANSFER = 0, 1, 2, 3
 
 
 class mgct_filter(ctypes.Structure):
@@ -39,6 +39,7 @@ class mgct_filter(ctypes.Structure):
         ("radial_table", ctypes.POINTER(ctypes.c_float)),
         ("n_table", ctypes.c_int),
         ("rho_max", ctypes.c_float),
+        ("transfer", ctypes.c_void_p * 8),
     ]
 
 
@@ -77,6 +78,9 @@ SIGNATURES = {
     "mgct_precondition": (_ci, [_vp, _ci, _vp, _vp, _fp, _vp]),
     "mgct_estimate_step": (_ci, [_vp, _ci, _fp, _ci, _u64, _dp, _vp]),
     "mgct_landweber_step": (_ci, [_vp, _ci, _vp, _vp, _ci, _cd, _fp, _dp, _vp]),
+    "mgct_psf_spectrum": (_ci, [_vp, _ci, _vp, _vp]),
+    "mgct_transfer_from_spectrum": (_ci, [_vp, _ci, _vp, _cd, _vp, _vp]),
+    "mgct_radial_profile": (_ci, [_vp, _ci, _vp, _ci, _cd, _dp, ctypes.POINTER(_ci), _vp]),
     "mgct_restrict_volume": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "mgct_restrict_stack": (_ci, [_vp, _ci, _vp, _vp, _vp]),
     "mgct_prolong_add": (_ci, [_vp, _ci, _vp, _vp, _vp, _vp]),
@@ -176,6 +180,19 @@ def filter_radial(table, rho_max: float) -> mgct_filter:
     f.n_table = t.size
     f.rho_max = float(rho_max)
     f._keep = t
+    return f
+
+
+def filter_transfer(arrays) -> mgct_filter:
+    """Fourier filter with a full transfer function per grid: arrays[g] is a
+    device F32 tensor of grid g's shape (DFT order) or None (the tensors are
+    kept alive on the returned structure)."""
+    f = mgct_filter()
+    f.kind = MGCT_FILTER_TRANSFER
+    for g, a in enumerate(arrays):
+        if a is not None:
+            f.transfer[g] = a.data_ptr()
+    f._keep = list(arrays)
     return f
 
 
@@ -314,6 +331,45 @@ class Context:
     def osemtr(self, vol, b, subsets=8, passes=2, level: int = 0):
         check(mgct_osemtr(self.handle, level, _ptr(vol), _ptr(b), subsets, passes, _stream()),  # noqa: F821
               "mgct_osemtr")
+
+    # ---- preconditioners derived from the scan
+    def psf_spectrum(self, level: int = 0, out=None):
+        """Transfer function of A^T A on grid `level` (device F32, DFT order)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.shapes(level)[0], dtype=torch.float32, device="cuda")
+        check(mgct_psf_spectrum(self.handle, level, _ptr(out), _stream()), "mgct_psf_spectrum")  # noqa: F821
+        return out
+
+    def transfer_from_spectrum(self, T, floor_rel: float, level: int = 0, out=None):
+        """H = 1 / max(T, floor_rel * T[0]) (device F32; out must not be T)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(T)
+        check(mgct_transfer_from_spectrum(self.handle, level, _ptr(T), float(floor_rel), _ptr(out),  # noqa: F821
+                                          _stream()), "mgct_transfer_from_spectrum")
+        return out
+
+    def derived_filter(self, levels: int, floor_rel: float = 0.03):
+        """TRANSFER filter 1/max(T, floor_rel T[0]) from the measured transfer
+        function T of A^T A on each of grids 0 .. levels-1 (one A and one A^T
+        of an impulse and a forward DFT per grid, computed once per geometry)."""
+        hs = []
+        for g in range(levels):
+            T = self.psf_spectrum(level=g)
+            hs.append(self.transfer_from_spectrum(T, floor_rel, level=g))
+            del T
+        return filter_transfer(hs)
+
+    def radial_profile(self, T, level: int = 0, n_table: int = 1025, rho_max: float = math.sqrt(3.0)):
+        """Shell means of a spectrum (host float64, NaN for empty shells) and counts."""
+        prof = np.zeros(n_table)
+        cnt = np.zeros(n_table, dtype=np.int32)
+        check(mgct_radial_profile(self.handle, level, _ptr(T), n_table, float(rho_max),  # noqa: F821
+                                  prof.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream()),
+              "mgct_radial_profile")
+        return prof, cnt
 
     def project_geom_grad(self, vol, cot, level: int = 0) -> np.ndarray:
         """d/d(views) of sum(cot * A vol): (n_views, 12) float64 (s, d, u, v)."""

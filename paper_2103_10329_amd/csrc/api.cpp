@@ -177,19 +177,41 @@ int do_backproject_pt(Ctx &c, Level &L, int g, const void *pt, int pt_dtype, voi
     return MGCT_OK;
 }
 
-int check_filter(const mgct_filter *f, const Level &L) {
+int check_filter(const mgct_filter *f, const Level &L, int g) {
     if (!f) return MGCT_OK;
     if (f->kind == MGCT_FILTER_IDENTITY || f->kind == MGCT_FILTER_STENCIL27) return MGCT_OK;
-    if (f->kind == MGCT_FILTER_RADIAL) {
-        if (!f->radial_table || f->n_table < 2 || !(f->rho_max > 0.f)) return MGCT_ERR_INVALID_ARG;
+    if (f->kind == MGCT_FILTER_RADIAL || f->kind == MGCT_FILTER_TRANSFER) {
+        if (f->kind == MGCT_FILTER_RADIAL && (!f->radial_table || f->n_table < 2 || !(f->rho_max > 0.f)))
+            return MGCT_ERR_INVALID_ARG;
+        if (f->kind == MGCT_FILTER_TRANSFER && (g < 0 || g >= 8 || !f->transfer[g])) return MGCT_ERR_INVALID_ARG;
         if (!fft_size_ok(L.nx) || !fft_size_ok(L.ny) || !fft_size_ok(L.nz)) return MGCT_ERR_NOT_IMPLEMENTED;
         return MGCT_OK;
     }
     return MGCT_ERR_INVALID_ARG;
 }
 
+// Twiddles of grid L's three edges, uploaded once per size.
+int fft_twiddles(Ctx &c, const Level &L, float2 **tw_out) {
+    const size_t ntw = L.nx / 2 + L.ny / 2 + L.nz / 2;
+    std::string twname = "tw_" + std::to_string(L.nx) + "_" + std::to_string(L.ny) + "_" + std::to_string(L.nz);
+    bool fresh = c.ws.find(twname) == c.ws.end();
+    WS(tw, float2, twname, ntw * sizeof(float2), false);
+    if (fresh) {
+        std::vector<float2> all, t;
+        host_twiddles(L.nx, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.nx / 2);
+        host_twiddles(L.ny, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.ny / 2);
+        host_twiddles(L.nz, t);
+        all.insert(all.end(), t.begin(), t.begin() + L.nz / 2);
+        HIPCHK(hipMemcpy(tw, all.data(), ntw * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    *tw_out = tw;
+    return MGCT_OK;
+}
+
 int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const mgct_filter *f, hipStream_t s) {
-    MGCHK(check_filter(f, L));
+    MGCHK(check_filter(f, L, g));
     const size_t n = L.vox();
     if (!f || f->kind == MGCT_FILTER_IDENTITY) {
         if (in != out) HIPCHK(launch_copy(in, out, n, s));
@@ -208,24 +230,17 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
         HIPCHK(launch_stencil27(src, out, L.nx, L.ny, L.nz, taps, s));
         return MGCT_OK;
     }
-    // RADIAL
+    // RADIAL or TRANSFER
+    float2 *tw;
+    MGCHK(fft_twiddles(c, L, &tw));
+    WS(work, float2, "fft_work", n * sizeof(float2), false);
+    if (f->kind == MGCT_FILTER_TRANSFER) {
+        KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
+        HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, nullptr, 0, 1.f, tw, s, f->transfer[g]));
+        return MGCT_OK;
+    }
     WS(table, float, "radial_table", (size_t)f->n_table * 4, false);
     HIPCHK(hipMemcpyAsync(table, f->radial_table, (size_t)f->n_table * 4, hipMemcpyHostToDevice, s));
-    const size_t ntw = L.nx / 2 + L.ny / 2 + L.nz / 2;
-    std::string twname = "tw_" + std::to_string(L.nx) + "_" + std::to_string(L.ny) + "_" + std::to_string(L.nz);
-    bool fresh = c.ws.find(twname) == c.ws.end();
-    WS(tw, float2, twname, ntw * sizeof(float2), false);
-    if (fresh) {
-        std::vector<float2> all, t;
-        host_twiddles(L.nx, t);
-        all.insert(all.end(), t.begin(), t.begin() + L.nx / 2);
-        host_twiddles(L.ny, t);
-        all.insert(all.end(), t.begin(), t.begin() + L.ny / 2);
-        host_twiddles(L.nz, t);
-        all.insert(all.end(), t.begin(), t.begin() + L.nz / 2);
-        HIPCHK(hipMemcpy(tw, all.data(), ntw * sizeof(float2), hipMemcpyHostToDevice));
-    }
-    WS(work, float2, "fft_work", n * sizeof(float2), false);
     KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
     HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, table, f->n_table, f->rho_max, tw, s));
     return MGCT_OK;
@@ -397,6 +412,8 @@ std::string filter_key(const mgct_filter *f) {
     o << f->kind << ":";
     if (f->kind == MGCT_FILTER_STENCIL27)
         for (int i = 0; i < 27; ++i) o << f->taps[i] << ",";
+    else if (f->kind == MGCT_FILTER_TRANSFER)
+        for (int i = 0; i < 8; ++i) o << (const void *)f->transfer[i] << ",";  // by array, not contents
     else {
         o << f->n_table << "," << f->rho_max << ",";
         uint64_t hsh = 1469598103934665603ull;
@@ -409,7 +426,7 @@ std::string filter_key(const mgct_filter *f) {
 
 int do_estimate(Ctx &c, Level &L, int g, const mgct_filter *f, int iters, uint64_t seed, double *alpha,
                 hipStream_t s) {
-    MGCHK(check_filter(f, L));
+    MGCHK(check_filter(f, L, g));
     const size_t n = L.vox();
     WS(x, float, lvl("pw_x", g), n * 4, false);
     WS(y, float, lvl("pw_y", g), n * 4, false);
@@ -805,7 +822,7 @@ int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_d
     HIPCHK(hipSetDevice(c.device));
     Level *L;
     MGCHK(get_level(c, level, &L));
-    MGCHK(check_filter(f, *L));
+    MGCHK(check_filter(f, *L, level));
     WS(d, double, "lw_norm2", 8, false);
     MGCHK(do_landweber(c, *L, level, vol, b, b_dtype, alpha, f, d, s));
     if (resid_norm) {
@@ -857,6 +874,67 @@ int mgct_geometry_param_grad(int n_views, const double *views0, const double *dv
     grad[0] = g0;
     grad[1] = g1;
     grad[2] = g2;
+    return MGCT_OK;
+}
+
+int mgct_psf_spectrum(void *ctx, int level, float *T, hipStream_t s) {
+    if (!ctx || !T) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *Lp;
+    MGCHK(get_level(c, level, &Lp));
+    Level &L = *Lp;
+    if (!fft_size_ok(L.nx) || !fft_size_ok(L.ny) || !fft_size_ok(L.nz)) return MGCT_ERR_NOT_IMPLEMENTED;
+    const size_t n = L.vox();
+    WS(delta, float, lvl("psf_delta", level), n * 4, false);
+    WS(proj, float, lvl("psf_proj", level), L.rays() * 4, false);
+    WS(work, float2, "fft_work", n * sizeof(float2), false);
+    float2 *tw;
+    MGCHK(fft_twiddles(c, L, &tw));
+    HIPCHK(launch_fill(delta, n, 0.f, s));
+    const float one = 1.f;
+    const size_t centre = ((size_t)(L.nz / 2) * L.ny + L.ny / 2) * L.nx + L.nx / 2;
+    HIPCHK(hipMemcpyAsync(delta + centre, &one, 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // `one` lives on this stack frame
+    MGCHK(do_project(c, L, level, delta, MGCT_F32, proj, MGCT_F32, 0, 1, L.nviews, s));
+    MGCHK(do_backproject(c, L, level, proj, MGCT_F32, delta, MGCT_F32, 0, 1, L.nviews, s));
+    HIPCHK(launch_radial_filter(delta, nullptr, work, L.nx, L.ny, L.nz, nullptr, 0, 1.f, tw, s, nullptr, true));
+    HIPCHK(launch_spectrum_real(work, T, L.nx, L.ny, L.nz, s));
+    return MGCT_OK;
+}
+
+int mgct_transfer_from_spectrum(void *ctx, int level, const float *T, double floor_rel, float *H, hipStream_t s) {
+    if (!ctx || !T || !H || T == H || !(floor_rel > 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    HIPCHK(launch_transfer_inverse(T, H, (long)L->vox(), floor_rel, s));
+    return MGCT_OK;
+}
+
+int mgct_radial_profile(void *ctx, int level, const float *T, int n_table, double rho_max, double *profile,
+                        int *counts, hipStream_t s) {
+    if (!ctx || !T || !profile || n_table < 2 || !(rho_max > 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    Level *L;
+    MGCHK(get_level(c, level, &L));
+    WS(sums, unsigned long long, "prof_sums", (size_t)n_table * 8, false);
+    WS(cnt, unsigned, "prof_counts", (size_t)n_table * 4, false);
+    HIPCHK(launch_fill(reinterpret_cast<float *>(sums), (size_t)n_table * 2, 0.f, s));
+    HIPCHK(launch_fill(reinterpret_cast<float *>(cnt), (size_t)n_table, 0.f, s));
+    const double scale = 16777216.0;  // 2^24
+    HIPCHK(launch_radial_bin(T, L->nx, L->ny, L->nz, n_table, (float)rho_max, scale, sums, cnt, s));
+    std::vector<unsigned long long> hs(n_table);
+    std::vector<unsigned> hc(n_table);
+    HIPCHK(hipMemcpyAsync(hs.data(), sums, (size_t)n_table * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc.data(), cnt, (size_t)n_table * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < n_table; ++i) {
+        profile[i] = hc[i] ? (double)(long long)hs[i] / scale / (double)hc[i] : NAN;
+        if (counts) counts[i] = (int)hc[i];
+    }
     return MGCT_OK;
 }
 
@@ -936,7 +1014,7 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
     std::vector<Level *> Ls(NL);
     for (int g = 0; g < NL; ++g) MGCHK(get_level(c, g, &Ls[g]));
     const int nland = NL == 1 ? 1 : NL - 1;  // grids with a Landweber step
-    for (int g = 0; g < nland; ++g) MGCHK(check_filter(&p->filter, *Ls[g]));
+    for (int g = 0; g < nland; ++g) MGCHK(check_filter(&p->filter, *Ls[g], g));
     if (p->learned && (!c.cnn.ready || Ls[0]->nx % 32)) return MGCT_ERR_INVALID_ARG;
 
     // step sizes

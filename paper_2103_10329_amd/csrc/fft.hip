@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "mgct_internal.h"
@@ -76,9 +77,11 @@ struct RadialH {
     int n_table;
     float rho_max;
     int nx, ny, nz;
+    const float *hk;  // when set: the transfer function itself, [ez][ey][ex]
 };
 
 __device__ __forceinline__ float radial_gain(const RadialH &R, int ex, int ey, int ez) {
+    if (R.hk) return R.hk[((long)ez * R.ny + ey) * R.nx + ex];
     const int kx = ex < R.nx / 2 ? ex : ex - R.nx;
     const int ky = ey < R.ny / 2 ? ey : ey - R.ny;
     const int kz = ez < R.nz / 2 ? ez : ez - R.nz;
@@ -140,11 +143,12 @@ static int ilog2(long n) {
 }
 
 hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int nx, int ny, int nz, const float *table,
-                                int n_table, float rho_max, const float2 *tw_all, hipStream_t s) {
+                                int n_table, float rho_max, const float2 *tw_all, hipStream_t s, const float *hk,
+                                bool forward_only) {
     // tw_all holds the twiddles for nx, then ny, then nz (nx/2 + ny/2 + nz/2 entries)
     const float2 *twx = tw_all, *twy = tw_all + nx / 2, *twz = tw_all + nx / 2 + ny / 2;
-    RadialH R{table, n_table, rho_max, nx, ny, nz};
-    RadialH none{nullptr, 0, 1.f, nx, ny, nz};
+    RadialH R{table, n_table, rho_max, nx, ny, nz, hk};
+    RadialH none{nullptr, 0, 1.f, nx, ny, nz, nullptr};
     const long nvox = (long)nx * ny * nz;
     // lines per block: as many as fit kFftElems, fewer while that leaves
     // under 2048 blocks (down to 8 lines on strided axes, so that a block's
@@ -180,6 +184,16 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
                 nullptr, work, nullptr, work, logN, logB, m, twy, +1, 1.f, none);
     }
+    if (forward_only) {
+        // pass 3 without the filter: the forward DFT is left in `work`
+        const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny, true);
+        LineMap m{(long)nx * ny, 1L << 40, 1, 0};
+        const unsigned grid = (unsigned)(((long)nx * ny) >> logB);
+        k_fft_pass<false, false, false, false>
+            <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
+                nullptr, work, nullptr, work, logN, logB, m, twz, +1, 1.f, none);
+        return hipGetLastError();
+    }
     // pass 3: z forward, * H, z inverse
     {
         const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny, true);
@@ -207,6 +221,67 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
                 nullptr, work, out, nullptr, logN, logB, m, twx, -1, (float)(1.0 / (double)nvox), none);
     }
+    return hipGetLastError();
+}
+
+// T[k] = Re(X[k] e^{+2 pi i k.c / n}) with X the forward DFT of an impulse
+// response centred at voxel c (phase in FP64).
+__global__ void k_spectrum_real(const float2 *__restrict__ X, float *__restrict__ T, int nx, int ny, int nz,
+                                int cx, int cy, int cz) {
+    const long n = (long)nx * ny * nz;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % nx), ky = (int)((i / nx) % ny), kz = (int)(i / ((long)nx * ny));
+        const double ph = 2.0 * M_PI * ((double)((long)kx * cx % nx) / nx + (double)((long)ky * cy % ny) / ny +
+                                        (double)((long)kz * cz % nz) / nz);
+        const float2 x = X[i];
+        T[i] = (float)((double)x.x * cos(ph) - (double)x.y * sin(ph));
+    }
+}
+
+// H = 1 / max(T, floor_rel * T[0])
+__global__ void k_transfer_inverse(const float *T, float *H, long n, double floor_rel) {
+    const double fl = floor_rel * (double)T[0];
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        H[i] = (float)(1.0 / fmax((double)T[i], fl));
+}
+
+// Shell sums of T by the nearest rho sample (rho as radial_gain computes it),
+// in 64-bit fixed point so that the atomics' order does not matter.
+__global__ void k_radial_bin(const float *__restrict__ T, int nx, int ny, int nz, int n_table, float rho_max,
+                             double scale, unsigned long long *sums, unsigned *counts) {
+    const long n = (long)nx * ny * nz;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int ex = (int)(i % nx), ey = (int)((i / nx) % ny), ez = (int)(i / ((long)nx * ny));
+        const int kx = ex < nx / 2 ? ex : ex - nx;
+        const int ky = ey < ny / 2 ? ey : ey - ny;
+        const int kz = ez < nz / 2 ? ez : ez - nz;
+        const float fx = (float)kx / nx, fy = (float)ky / ny, fz = (float)kz / nz;
+        const float rho = 2.f * sqrtf(fx * fx + fy * fy + fz * fz);
+        const float t = rho / rho_max * (float)(n_table - 1);
+        const int b = (int)(t + 0.5f);
+        if (b >= n_table) continue;
+        const long long q = llrint((double)T[i] * scale);
+        atomicAdd(sums + b, (unsigned long long)q);
+        atomicAdd(counts + b, 1u);
+    }
+}
+
+hipError_t launch_spectrum_real(const float2 *X, float *T, int nx, int ny, int nz, hipStream_t s) {
+    const long n = (long)nx * ny * nz;
+    const unsigned g = (unsigned)std::min<long>((n + 255) / 256, 65535);
+    k_spectrum_real<<<g, 256, 0, s>>>(X, T, nx, ny, nz, nx / 2, ny / 2, nz / 2);
+    return hipGetLastError();
+}
+hipError_t launch_transfer_inverse(const float *T, float *H, long n, double floor_rel, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<long>((n + 255) / 256, 65535);
+    k_transfer_inverse<<<g, 256, 0, s>>>(T, H, n, floor_rel);
+    return hipGetLastError();
+}
+hipError_t launch_radial_bin(const float *T, int nx, int ny, int nz, int n_table, float rho_max, double scale,
+                             unsigned long long *sums, unsigned *counts, hipStream_t s) {
+    const long n = (long)nx * ny * nz;
+    const unsigned g = (unsigned)std::min<long>((n + 255) / 256, 65535);
+    k_radial_bin<<<g, 256, 0, s>>>(T, nx, ny, nz, n_table, rho_max, scale, sums, counts);
     return hipGetLastError();
 }
 

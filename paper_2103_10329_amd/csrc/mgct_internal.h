@@ -224,8 +224,14 @@ hipError_t launch_synth_voxelize(int nx, int ny, int nz, double h, const double 
 // FFT preconditioner (fft.hip)
 bool fft_size_ok(int n);
 hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int nx, int ny, int nz,
-                                const float *table, int n_table, float rho_max, const float2 *tw,
-                                hipStream_t s);
+                                const float *table, int n_table, float rho_max, const float2 *tw_all, hipStream_t s,
+                                const float *hk = nullptr, bool forward_only = false);
+// transfer function of an impulse response centred at (nx/2, ny/2, nz/2)
+// from its forward DFT; H = 1/max(T, floor T[0]); fixed-point shell sums
+hipError_t launch_spectrum_real(const float2 *X, float *T, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_transfer_inverse(const float *T, float *H, long n, double floor_rel, hipStream_t s);
+hipError_t launch_radial_bin(const float *T, int nx, int ny, int nz, int n_table, float rho_max, double scale,
+                             unsigned long long *sums, unsigned *counts, hipStream_t s);
 void host_twiddles(int n, std::vector<float2> &tw);  // exp(-2 pi i k / n), k < n/2
 
 }  // namespace mgct
