@@ -210,6 +210,22 @@ int fft_twiddles(Ctx &c, const Level &L, float2 **tw_out) {
     return MGCT_OK;
 }
 
+// Device copy of a small host table (filter taps or radial profile), one
+// per distinct content: uploaded (synchronously) the first time its bytes are
+// seen, reused afterwards, so steady-state filtering issues no host copies.
+int device_table(Ctx &c, const char *kind, const float *host, int n, float **dev) {
+    uint64_t hsh = 1469598103934665603ull;
+    const unsigned char *p = (const unsigned char *)host;
+    for (size_t i = 0; i < (size_t)n * 4; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
+    const std::string key = std::string(kind) + "_" + std::to_string(n) + "_" + std::to_string(hsh);
+    const bool fresh = c.ws.find(key) == c.ws.end();
+    float *d = static_cast<float *>(workspace(c, key, (size_t)n * 4, false));
+    if (!d) return MGCT_ERR_OOM;
+    if (fresh) HIPCHK(hipMemcpy(d, host, (size_t)n * 4, hipMemcpyHostToDevice));
+    *dev = d;
+    return MGCT_OK;
+}
+
 int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const mgct_filter *f, hipStream_t s) {
     MGCHK(check_filter(f, L, g));
     const size_t n = L.vox();
@@ -218,8 +234,8 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
         return MGCT_OK;
     }
     if (f->kind == MGCT_FILTER_STENCIL27) {
-        WS(taps, float, "taps27", 27 * 4, false);
-        HIPCHK(hipMemcpyAsync(taps, f->taps, 27 * 4, hipMemcpyHostToDevice, s));
+        float *taps;
+        MGCHK(device_table(c, "taps27", f->taps, 27, &taps));
         KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
         const float *src = in;
         if (in == out) {
@@ -239,8 +255,8 @@ int do_precondition(Ctx &c, Level &L, int g, const float *in, float *out, const 
         HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, nullptr, 0, 1.f, tw, s, f->transfer[g]));
         return MGCT_OK;
     }
-    WS(table, float, "radial_table", (size_t)f->n_table * 4, false);
-    HIPCHK(hipMemcpyAsync(table, f->radial_table, (size_t)f->n_table * 4, hipMemcpyHostToDevice, s));
+    float *table;
+    MGCHK(device_table(c, "radial_table", f->radial_table, f->n_table, &table));
     KernelTimer t(c, MGCT_OP_PRECONDITION, g, s);
     HIPCHK(launch_radial_filter(in, out, work, L.nx, L.ny, L.nz, table, f->n_table, f->rho_max, tw, s));
     return MGCT_OK;
