@@ -74,3 +74,52 @@ def test_joint_estimation_recovers_misalignment():
     # for this trajectory is nearly equivalent to a z-translation of the object
     # (absorbed by the reconstruction), so it is reported, not required
     assert err[0] <= 0.5 * err0[0] + 0.05 and err[2] <= 0.5 * err0[2] + 0.02
+
+
+def test_joint_estimation_full_size():
+    """256^3, 720 views of 384^2 (the full geometry-estimation workload):
+    data from the device phantom generators under a hidden misalignment,
+    Poisson noise, then Adam on (dx, dz, tilt) alternating with one warm-started
+    iteration of Algorithm 1 (3 grids, radial filter; step sizes from the
+    unperturbed geometry) per geometry update.  dx and the tilt move toward
+    the hidden values.  A tilted detector takes the general-geometry kernels."""
+    import time
+    import torch
+    from paper_2103_10329_amd.learned import poisson_data
+    cfg = synth.CONFIGS["c3"]
+    n, nu, V = cfg.n, cfg.nu, cfg.n_views
+    views0 = synth.trajectory(V, cfg.z_levels, cfg.pixel)
+    rng = np.random.Generator(np.random.PCG64(3003))
+    p_true = np.array([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(-0.5, 0.5)])
+    ph = synth.random_phantom(cfg, 1003)
+    ctx_true = mg.Context(0)
+    ctx_true.set_geometry(n, n, n, cfg.h, (0, 0, 0), nu, nu, synth.perturb_geometry(views0, cfg.h, *p_true))
+    gen = torch.Generator(device="cuda").manual_seed(2003)
+    b = poisson_data(ctx_true.synth_line_integrals(ph), cfg.noise_level, gen)
+    ctx_true.close()
+    ctx = mg.Context(0)
+    ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), nu, nu, views0)
+    t, rm = oracle.radial_table(n)
+    filt = mg.filter_radial(t, rm)
+    alphas = [ctx.estimate_step(filt, level=lv, iters=20) for lv in range(2)]
+    vol = torch.zeros((n, n, n), device="cuda")
+    ctx.multigrid_solve(vol, b, 3, 2, filt, alphas=alphas, want_hist=False)
+    say("joint estimation 256^3: data and first reconstruction ready")
+    p = np.zeros(3)
+    m1, m2 = np.zeros(3), np.zeros(3)
+    lr, beta1, beta2 = 0.12, 0.9, 0.999
+    err0 = np.abs(p - p_true)
+    t0 = time.time()
+    for it in range(1, 11):
+        if it > 1:
+            ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), nu, nu, synth.perturb_geometry(views0, cfg.h, *p))
+            ctx.multigrid_solve(vol, b, 3, 1, filt, alphas=alphas, want_hist=False)
+        r = (ctx.project(vol) - b).contiguous()
+        gp = mg.geometry_param_grad(views0, ctx.project_geom_grad(vol, r), cfg.h, *p)
+        m1 = beta1 * m1 + (1 - beta1) * gp
+        m2 = beta2 * m2 + (1 - beta2) * gp * gp
+        p = p - lr * (m1 / (1 - beta1 ** it)) / (np.sqrt(m2 / (1 - beta2 ** it)) + 1e-12)
+        say("  step", it, "p", p, "%.1fs" % (time.time() - t0))
+    err = np.abs(p - p_true)
+    say("joint estimation 256^3: hidden", p_true, "estimated", p, "error", err, "initial", err0)
+    assert err[0] <= 0.5 * err0[0] + 0.05 and err[2] <= 0.5 * err0[2] + 0.02
