@@ -1299,14 +1299,98 @@ hipError_t launch_geom_grad(const void *vt, int vt_dtype, const float *cot, doub
 
 // ---------------------------------------- general-geometry back-projector --
 //
-// Any detector orientation (no z-major rays).  For each voxel and view, the
-// rays whose Joseph samples can touch the voxel pass through the cube of
-// half-width one voxel around it; the bounding box of the cube's eight
-// corners projected on the detector (plus one pixel) gives the candidate
-// pixels.  Each candidate's weight is recomputed exactly as the projector
-// forms it: its major axis from the per-ray table, the sample on the
-// voxel's own plane of that axis, and the two hat functions.  One lane per
-// voxel, lanes along z; per-view partial sums in FP32, summed in FP64.
+// Any detector orientation (no z-major rays).  The projector samples a ray of
+// major axis m on the voxel-centre planes of m; voxel P receives from such a
+// ray the product of the two hat weights of the sample on the plane through
+// P.  With g = P - s and the ray direction D(a, b) = E + a u + b v (E the
+// direction to pixel (0, 0)), that sample's offsets from P along the other
+// in-plane axis o and along z are
+//     n_o / D_m  with  n_o = g_m D_o - g_o D_m,
+//     n_z / D_m  with  n_z = g_m D_z - g_z D_m,
+// ratios of affine functions of the pixel (a, b).  The rays with non-zero
+// weight are those inside the quadrilateral |n_o| < |D_m|, |n_z| < |D_m|
+// (the image of the voxel's square on the plane).  Its centre (n_o = n_z = 0)
+// is the voxel's central projection (a*, b*), and with J the Jacobian of
+// (n_o, n_z) in (a, b) every point of it lies within
+//     |a - a*| <= k_a |D_m(a*, b*)| / (1 - rho),  k_a = row sum of |J^-1|,
+// (likewise b) where rho bounds the relative change of D_m over the region;
+// that box, a few pixels wide, holds the candidate rays.  Per candidate the
+// three affine values are stepped in FP32 from the box corner (evaluated in
+// FP64), so one reciprocal gives both weights.
+//
+// A column of voxels (i, j) decides the axes: when |g_x| > |g_y| + 1 every ray
+// through the voxel's x-plane square is x-major and no y-major ray reaches the
+// voxel, so only the x-plane is visited and the axis table is not read
+// (likewise for y); within one voxel of the diagonal both planes are visited
+// and each candidate's axis comes from the table.  The samples lie between
+// the source and the pixel (0 <= g_m / D_m <= 1): when that holds with margin
+// at the box corners (D_m is affine) no per-candidate test is needed,
+// otherwise each candidate takes the projector's own FP64 plane-range test.
+template <int M, bool AX, typename PT>
+__device__ __forceinline__ float gen_plane(const PT *__restrict__ base, const uint8_t *__restrict__ axv, long ars,
+                                           const ViewIdx &V, const double E[3], double gm, double go, double gz,
+                                           double pm, int nu, int nv) {
+    constexpr int O = 1 - M;
+    const double um = V.u[M], vm = V.v[M];
+    const double O0 = gm * E[O] - go * E[M], Oa = gm * V.u[O] - go * um, Ob = gm * V.v[O] - go * vm;
+    const double Z0 = gm * E[2] - gz * E[M], Za = gm * V.u[2] - gz * um, Zb = gm * V.v[2] - gz * vm;
+    const float fdet = (float)(Oa * Zb - Ob * Za);
+    if (!(fabsf(fdet) > 0.f)) return 0.f;  // the square's image is degenerate
+    const float rdet = 1.f / fdet;
+    const float ac = (float)(Ob * Z0 - Zb * O0) * rdet;
+    const float bc = (float)(Za * O0 - Oa * Z0) * rdet;
+    const float ka = (fabsf((float)Zb) + fabsf((float)Ob)) * fabsf(rdet);
+    const float kb = (fabsf((float)Za) + fabsf((float)Oa)) * fabsf(rdet);
+    const float fum = (float)um, fvm = (float)vm;
+    const float dc = fmaf(fvm, bc, fmaf(fum, ac, (float)E[M]));
+    const float rho = fabsf(fum) * ka + fabsf(fvm) * kb;
+    float wa = 1e30f, wb = 1e30f;  // the whole detector when the bound fails
+    if (rho < 0.5f) {
+        const float sc = fabsf(dc) / (1.f - rho);
+        wa = ka * sc;
+        wb = kb * sc;
+    }
+    // margin for the FP32 centre (relative error ~1e-7 of |a*|)
+    const float ma = 2e-3f + 1e-5f * fabsf(ac), mb = 2e-3f + 1e-5f * fabsf(bc);
+    const float fa0 = fmaxf(ceilf(ac - wa - ma), 0.f), fa1 = fminf(floorf(ac + wa + ma), (float)(nu - 1));
+    const float fb0 = fmaxf(ceilf(bc - wb - mb), 0.f), fb1 = fminf(floorf(bc + wb + mb), (float)(nv - 1));
+    if (!(fa0 <= fa1 && fb0 <= fb1)) return 0.f;  // off the detector (or NaN)
+    const int a0 = (int)fa0, a1 = (int)fa1, b0 = (int)fb0, b1 = (int)fb1;
+    const double da0 = a0, db0 = b0;
+    const float no0 = (float)(O0 + Oa * da0 + Ob * db0);
+    const float nz0 = (float)(Z0 + Za * da0 + Zb * db0);
+    const float d0 = (float)(E[M] + um * da0 + vm * db0);
+    const float oa = (float)Oa, ob = (float)Ob, za = (float)Za, zb = (float)Zb;
+    // 0 <= g_m / D_m <= 1 over the whole box?
+    const float sg = gm > 0.0 ? 1.f : -1.f, agm = fabsf((float)gm);
+    const float pa = (float)(a1 - a0), pb = (float)(b1 - b0);
+    const float dmin = fminf(fminf(sg * d0, sg * fmaf(pa, fum, d0)),
+                             fminf(sg * fmaf(pb, fvm, d0), sg * fmaf(pb, fvm, fmaf(pa, fum, d0))));
+    const bool inside = gm != 0.0 && dmin > agm * (1.f + 1e-5f) + 1e-6f;
+    const double ccu = 0.5 * (nu - 1), ccv = 0.5 * (nv - 1);
+    float sum = 0.f;
+    for (int a = a0; a <= a1; ++a) {
+        const float p = (float)(a - a0);
+        const float no_r = fmaf(p, oa, no0), nz_r = fmaf(p, za, nz0), d_r = fmaf(p, fum, d0);
+        const PT *col = base + (long)a * nv;
+        for (int b = b0; b <= b1; ++b) {
+            const float q = (float)(b - b0);
+            const float r = __builtin_amdgcn_rcpf(fmaf(q, fvm, d_r));
+            const float wo = 1.f - fabsf(fmaf(q, ob, no_r) * r);
+            const float wz = 1.f - fabsf(fmaf(q, zb, nz_r) * r);
+            bool ok = wo > 0.f && wz > 0.f;
+            if (AX && ok) ok = axv[b * ars + a] == M;
+            if (!inside && ok) {
+                const double Dm = (V.d[M] + (a - ccu) * um + (b - ccv) * vm) - V.s[M];
+                ok = pm >= fmin(V.s[M], V.s[M] + Dm) && pm <= fmax(V.s[M], V.s[M] + Dm);
+            }
+            if (ok) sum = fmaf(wo * wz, load_f(col, b), sum);
+        }
+    }
+    return sum;
+}
+
+// One lane per voxel, lanes along z; per-view sums in FP32, summed in FP64.
 template <typename PT>
 __global__ __launch_bounds__(256) void k_backproject_gen(const PT *__restrict__ pt, float *__restrict__ vol,
                                                          float *__restrict__ part, const ViewIdx *__restrict__ views,
@@ -1320,64 +1404,28 @@ __global__ __launch_bounds__(256) void k_backproject_gen(const PT *__restrict__ 
     const int ij = wave / zchunks;
     const int i = ij % nx, j = ij / nx;
     if (j >= ny) return;  // whole wave; no barrier below
-    const double P[3] = {(double)i, (double)j, (double)k};
     double acc = 0.0;
     const int vbeg = blockIdx.y * per_chunk;
     const int vend = min(nviews_sub, vbeg + per_chunk);
     for (int vl = vbeg; vl < vend && k < nz; ++vl) {
         const int v = view0 + vl * view_step;
         const ViewIdx &V = views[v];
-        // detector-plane projection of the cube corners
-        const double n0 = V.u[1] * V.v[2] - V.u[2] * V.v[1];
-        const double n1 = V.u[2] * V.v[0] - V.u[0] * V.v[2];
-        const double n2 = V.u[0] * V.v[1] - V.u[1] * V.v[0];
-        const double num = n0 * (V.d[0] - V.s[0]) + n1 * (V.d[1] - V.s[1]) + n2 * (V.d[2] - V.s[2]);
-        const double uu = V.u[0] * V.u[0] + V.u[1] * V.u[1] + V.u[2] * V.u[2];
-        const double uv = V.u[0] * V.v[0] + V.u[1] * V.v[1] + V.u[2] * V.v[2];
-        const double vv = V.v[0] * V.v[0] + V.v[1] * V.v[1] + V.v[2] * V.v[2];
-        const double det = uu * vv - uv * uv;
-        double amin = 1e30, amax = -1e30, bmin = 1e30, bmax = -1e30;
-        bool ok = true;
-        for (int c = 0; c < 8; ++c) {
-            const double Q[3] = {P[0] + ((c & 1) ? 1.0 : -1.0), P[1] + ((c & 2) ? 1.0 : -1.0),
-                                 P[2] + ((c & 4) ? 1.0 : -1.0)};
-            const double den = n0 * (Q[0] - V.s[0]) + n1 * (Q[1] - V.s[1]) + n2 * (Q[2] - V.s[2]);
-            const double t = num / den;
-            if (!(den != 0.0) || !(t > 0.0)) { ok = false; break; }
-            double X[3];
+        const double ccu = 0.5 * (nu - 1), ccv = 0.5 * (nv - 1);
+        double E[3];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) X[e] = V.s[e] + t * (Q[e] - V.s[e]) - V.d[e];
-            const double xu = X[0] * V.u[0] + X[1] * V.u[1] + X[2] * V.u[2];
-            const double xv = X[0] * V.v[0] + X[1] * V.v[1] + X[2] * V.v[2];
-            const double pa = (xu * vv - xv * uv) / det + 0.5 * (nu - 1);
-            const double pb = (xv * uu - xu * uv) / det + 0.5 * (nv - 1);
-            amin = fmin(amin, pa); amax = fmax(amax, pa);
-            bmin = fmin(bmin, pb); bmax = fmax(bmax, pb);
-        }
-        int a0 = 0, a1 = nu - 1, b0 = 0, b1 = nv - 1;
-        if (ok) {
-            a0 = max(0, (int)floor(fmax(amin, -2.0)) - 1);
-            a1 = min(nu - 1, (int)ceil(fmin(amax, (double)nu + 1.0)) + 1);
-            b0 = max(0, (int)floor(fmax(bmin, -2.0)) - 1);
-            b1 = min(nv - 1, (int)ceil(fmin(bmax, (double)nv + 1.0)) + 1);
-        }
+        for (int e = 0; e < 3; ++e) E[e] = (V.d[e] - ccu * V.u[e] - ccv * V.v[e]) - V.s[e];
+        const double gx = i - V.s[0], gy = j - V.s[1], gz = k - V.s[2];
+        const double ax = fabs(gx), ay = fabs(gy), tol = 1.0 + 1e-6 * (ax + ay);
         const PT *base = pt + (long)vl * nu * nv;
-        float pv = 0.f;
-        for (int a = a0; a <= a1; ++a) {
-            for (int b = b0; b <= b1; ++b) {
-                double D[3];
-                const double ca = a - 0.5 * (nu - 1), cb = b - 0.5 * (nv - 1);
-#pragma unroll
-                for (int e = 0; e < 3; ++e) D[e] = (V.d[e] + ca * V.u[e] + cb * V.v[e]) - V.s[e];
-                const int m = axis[v * axis_view_stride + b * axis_row_stride + a];
-                const int ia = (m == 0) ? 1 : 0;
-                const double t = (P[m] - V.s[m]) / D[m];
-                if (!(t >= 0.0 && t <= 1.0)) continue;
-                const float wa = 1.f - (float)fabs(fma(t, D[ia], V.s[ia]) - P[ia]);
-                const float wz = 1.f - (float)fabs(fma(t, D[2], V.s[2]) - P[2]);
-                if (wa > 0.f && wz > 0.f) pv = fmaf(wa * wz, load_f(base, (long)a * nv + b), pv);
-            }
-        }
+        const uint8_t *axv = axis + v * axis_view_stride;
+        float pv;
+        if (ax - ay > tol)
+            pv = gen_plane<0, false>(base, axv, axis_row_stride, V, E, gx, gy, gz, (double)i, nu, nv);
+        else if (ay - ax > tol)
+            pv = gen_plane<1, false>(base, axv, axis_row_stride, V, E, gy, gx, gz, (double)j, nu, nv);
+        else
+            pv = gen_plane<0, true>(base, axv, axis_row_stride, V, E, gx, gy, gz, (double)i, nu, nv) +
+                 gen_plane<1, true>(base, axv, axis_row_stride, V, E, gy, gx, gz, (double)j, nu, nv);
         acc += (double)pv;
     }
     if (k < nz) {

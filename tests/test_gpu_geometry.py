@@ -84,3 +84,48 @@ def test_parameter_gradient_central_differences_on_gpu():
         fd[k] = (f(p + e) - f(p - e)) / 2e-3
     say("param grad", grad, "fd", fd)
     assert np.allclose(grad, fd, rtol=1e-2, atol=1e-3 * np.abs(fd).max())
+
+
+def _awkward(kind):
+    """32^3 geometries off the usual path of the general kernels: a 25 degree
+    detector tilt (columns near the diagonal need both plane families), a
+    detector pitched by 0.5 rad about its column axis (rows no longer along
+    z), and a source 26 units from the axis with the detector cutting through
+    the volume (samples end at the pixel, inside the grid)."""
+    g = workload("c0", n=32, nu=48, nv=48, n_views=40)
+    vw = g.views.copy()
+    if kind == "tilt25":
+        vw = synth.perturb_geometry(vw, g.h, 0.3, 0.2, 25.0)
+    elif kind == "pitched":
+        for r in vw:
+            vv = r[9:12].copy()
+            lv = np.linalg.norm(vv)
+            nrm = np.cross(r[6:9] / np.linalg.norm(r[6:9]), vv / lv)
+            r[9:12] = lv * (np.cos(0.5) * vv / lv + np.sin(0.5) * nrm)
+    else:  # detector inside the volume
+        s = vw[:, 0:3].copy()
+        rad = np.linalg.norm(s[:, :2], axis=1, keepdims=True)
+        vw[:, 0:2] = s[:, :2] / rad * 26.0
+        vw[:, 3:5] = s[:, :2] / rad * 5.0
+        vw[:, 6:9] *= 0.5
+        vw[:, 9:12] *= 0.15
+    return oracle.Geom(g.nx, g.ny, g.nz, g.h, g.origin, g.nu, g.nv, vw)
+
+
+@pytest.mark.parametrize("kind", ["tilt25", "pitched", "detector_inside"])
+def test_awkward_general_geometries(kind):
+    g = _awkward(kind)
+    say("awkward geometry", kind)
+    rng = np.random.Generator(np.random.PCG64(33))
+    x = rng.random(g.vol_shape)
+    y = rng.random(g.stack_shape)
+    ctx = context(g)
+    Ax = to_host(ctx.project(to_dev(x)))
+    Aty = to_host(ctx.backproject(to_dev(y)))
+    e1 = rel_l2(Ax, oracle.project(g, x))
+    ref = oracle.backproject(g, y)
+    e2 = rel_l2(Aty, ref)
+    worst = float(np.max(np.abs(Aty - ref)) / np.max(np.abs(ref)))
+    adj = abs(np.vdot(Ax, y) - np.vdot(x, Aty)) / (np.linalg.norm(Ax) * np.linalg.norm(y))
+    say("  A", e1, "A^T", e2, "worst voxel / max", worst, "adjoint", adj)
+    assert e1 <= 1e-5 and e2 <= 1e-5 and worst <= 1e-5 and adj <= 1e-6
