@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_blk": {"source_sha256": "11256a576cd8009fe7d2315870dfe8a1520ef4672834e8ea553d57e61407bbe6", "bytes_per_launch": 502778466},
+    "k_backproject_blk": {"source_sha256": "40dc865dc5239b196526fcb22a8a982508d55e675e3c0eeeb8b608a2381bb8b2", "bytes_per_launch": 507191243},
 }
 
 
