@@ -127,7 +127,7 @@ def main():
     dom = "backproject@0" if tB >= tA else "project@0"
     t_dom = kt[dom]["ms_avg"] * 1e-3
     achieved = bytes_per_launch / t_dom / 1e9
-    kname = "k_backproject_blk" if dom.startswith("back") else "k_project_sep"
+    kname = "k_backproject_pl" if dom.startswith("back") else "k_project_sep"
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_blk": {"source_sha256": "40dc865dc5239b196526fcb22a8a982508d55e675e3c0eeeb8b608a2381bb8b2", "bytes_per_launch": 507191243},
+    "k_backproject_pl": {"source_sha256": "873be75896c8228eb1a9193a369e16c33b21115e9c5a2ee2f0fcdd921c615e5b", "bytes_per_launch": 391124759},
 }
 
 

@@ -1055,28 +1055,222 @@ __global__ void k_sum_chunks(const float *__restrict__ part, OT *__restrict__ ou
 #ifndef MGCT_BP_MIN_VIEWS
 #define MGCT_BP_MIN_VIEWS 2    // fewest views per view chunk
 #endif
+#ifndef MGCT_BP_PLANE
+#define MGCT_BP_PLANE 1        // grids deeper than MGCT_BP_HALF_MAXNZ: plane-blocked kernel (0: 2 x 2 row blocks)
+#endif
 constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 
-// waves of the separable back-projector: one per kBpBI x kBpBJ block of
-// (x, y) rows and 64 KZ z values, or one per two rows when nz <= 32
-long bp_waves(const Level &L, int *kz) {
-    // KZ = 2 where the depth allows (more z per wave raises the register
-    // count of the four-row block beyond what keeps 6 waves per SIMD)
+// ------------------------------------------ plane-blocked back-projector --
+//
+// One wave per (plane, kPlRows in-plane rows, 64 KZ z values) of one major
+// axis: PART 0 waves own the plane x = i with rows y = j0 .. j0+7 and take the
+// views' x-major columns, PART 1 waves own y = j with rows x = i0 .. i0+7 and
+// the y-major columns (blockIdx.z).  A column crossing the plane at in-plane
+// position pos reaches exactly the rows floor(pos) and floor(pos) + 1, both
+// wave-uniform, so the column's detector-row sums for the wave's z values
+// (bp_column_sums) are formed once and added, with the in-plane hat weights
+// 1 - f and f (f = pos - floor(pos)), to those two rows.  The rows are picked
+// by a runtime index, so the per-view sums live in LDS slots private to each
+// lane (no other lane touches them: no barriers), with two spare rows for the
+// taps that fall just outside the block; after each view they are added to
+// FP64 registers and cleared.  The parts write separate partial volumes,
+// summed with the view chunks afterwards.  Per voxel and view this forms
+// about 1.6 column sums against 2.5 for the 2 x 2 row blocks
+// (k_backproject_blk, kept for comparison builds).
+#ifndef MGCT_BP_PLROWS
+#define MGCT_BP_PLROWS 8
+#endif
+constexpr int kPlRows = MGCT_BP_PLROWS;
+constexpr int kPlSlots = kPlRows + 2;
+
+// A lane adds into its own slots only, so a plain LDS read-add-write is
+// exact; the LDS atomic add measured about five times slower in this loop.
+__device__ __forceinline__ void lds_add(float *p, float v) { *p += v; }
+
+template <int PART, int KZ, int NP, typename PT, bool ZS>
+__device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
+                                              const PT *base1, int P, int r0, int nu, int nv,
+                                              const double (&kd)[KZ], double zw0, double zw1, float *slot) {
+    // distance of the plane from the source along the major axis
+    const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
+    if (ZS) {
+        // the view's extreme rows at this plane stay a voxel away from the
+        // wave's z range: nothing to add
+        const double ta = dm * (PART == 0 ? S.r0lo : S.r1lo), tb = dm * (PART == 0 ? S.r0hi : S.r1hi);
+        const double dzn = fma(S.vz, (double)(nv - 1), S.dz0);
+        const double z1 = fma(ta, S.dz0, S.sz), z2 = fma(tb, S.dz0, S.sz);
+        const double z3 = fma(ta, dzn, S.sz), z4 = fma(tb, dzn, S.sz);
+        if (fmax(fmax(z1, z2), fmax(z3, z4)) <= zw0 - 1.0 || fmin(fmin(z1, z2), fmin(z3, z4)) >= zw1 + 1.0) return;
+    }
+    const double inv_dm = 1.0 / dm;
+    const float fp = (float)P, flo = (float)(r0 - 1), fhi = (float)(r0 + kPlRows);
+    const float c1 = PART == 0 ? column_coord(S, fp, flo) : column_coord(S, flo, fp);
+    const float c2 = PART == 0 ? column_coord(S, fp, fhi) : column_coord(S, fhi, fp);
+    int alo = (int)floorf(fminf(c1, c2) - 0.01f);
+    int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
+    alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
+    ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+    for (int a = alo; a <= ahi; ++a) {
+        const ColD C = cv[a];
+        if (C.axis != PART) continue;
+        const double tau = dm * (PART == 0 ? C.rdx : C.rdy);  // ray parameter at the plane
+        if (tau < 0.0 || tau > 1.0) continue;
+        const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
+        const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
+        const int rl = __builtin_amdgcn_readfirstlane((int)fl - r0);  // block row of the lower tap
+        if (rl < -1 || rl >= kPlRows) continue;
+        const float whi = (float)(pos - fl), wlo = 1.f - whi;
+        const double tz = tau * S.vz;             // row spacing along z at the plane
+        const double zc = fma(tau, S.dz0, S.sz);  // z of row 0 at the plane
+        if (ZS) {
+            const double zend = fma(tz, (double)(nv - 1), zc);
+            if (fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0) continue;
+        }
+        const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;  // 1 / tz
+        const double hw = fabs(rtz);
+        const PT *col0 = base0 + (long)a * nv;
+        const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
+        float sums[NP][KZ];
+        bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
+        float *sl = slot + (rl + 1) * KZ * 64;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) {
+                lds_add(sl + (p * kPlSlots * KZ + q) * 64, wlo * sums[p][q]);
+                lds_add(sl + ((p * kPlSlots + 1) * KZ + q) * 64, whi * sums[p][q]);
+            }
+    }
+}
+
+template <int PART, int KZ, int NP, typename PT, bool ZS>
+__device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
+                                              float *__restrict__ part, long np_stride, float *slot,
+                                              const SepView *__restrict__ sep, const ColD *__restrict__ cols,
+                                              int nx, int ny, int nz, int nu, int nv, int nviews_sub, int view0,
+                                              int view_step, int per_chunk, int nchunks) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nplanes = PART == 0 ? nx : ny, nrows = PART == 0 ? ny : nx;
+    const int nrb = (nrows + kPlRows - 1) / kPlRows;
+    const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
+    const int zc_id = wave % zchunks;
+    const int rb = (wave / zchunks) % nrb;
+    const int P = wave / zchunks / nrb;
+    if (P >= nplanes) return;  // whole wave; no barrier below
+    const int r0 = rb * kPlRows;
+    double kd[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
+    const double zw0 = (double)(zc_id * 64 * KZ), zw1 = zw0 + (double)(64 * KZ - 1);
+#pragma unroll
+    for (int t = 0; t < NP * kPlSlots * KZ; ++t) slot[t * 64] = 0.f;
+    double acc[NP][kPlRows][KZ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int r = 0; r < kPlRows; ++r)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) acc[p][r][q] = 0.0;
+    const int vbeg = blockIdx.y * per_chunk;
+    const int vend = min(nviews_sub, vbeg + per_chunk);
+    for (int vl = vbeg; vl < vend; ++vl) {
+        const int v = view0 + vl * view_step;
+        const SepView S = sep[v];
+        if (!(S.flags & (PART == 0 ? 1 : 2))) continue;
+        const PT *base0 = pt0 + (long)vl * nu * nv;
+        const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
+        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, kd, zw0, zw1, slot);
+        // the view's sums into FP64, slots cleared (spare rows too)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int r = 0; r < kPlRows; ++r)
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) {
+                    float *e = slot + ((p * kPlSlots + r + 1) * KZ + q) * 64;
+                    acc[p][r][q] += (double)*e;
+                    *e = 0.f;
+                }
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) {
+                slot[((p * kPlSlots) * KZ + q) * 64] = 0.f;
+                slot[((p * kPlSlots + kPlSlots - 1) * KZ + q) * 64] = 0.f;
+            }
+        }
+    }
+    const long nvox = (long)nx * ny * nz;
+    float *out = part + (long)(PART * nchunks + blockIdx.y) * nvox;
+#pragma unroll
+    for (int r = 0; r < kPlRows; ++r) {
+        const int row = r0 + r;
+        const int i = PART == 0 ? P : row, j = PART == 0 ? row : P;
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) {
+            const int k = (int)kd[q];
+            if (row < nrows && k < nz) {
+                const long o = ((long)k * ny + j) * nx + i;
+                out[o] = (float)acc[0][r][q];
+                if (NP > 1) out[np_stride + o] = (float)acc[NP - 1][r][q];
+            }
+        }
+    }
+}
+
+// Launch: grid (waves / 4, view chunks, 2 parts); part[] receives 2 x chunks
+// partial volumes per output (the second output np_stride floats further).
+#ifndef MGCT_BP_PL_MINW
+#define MGCT_BP_PL_MINW 5  // waves per SIMD the single-output variants' registers must allow
+#endif
+template <int KZ, int NP, typename PT, bool ZS>
+__global__ __launch_bounds__(256, NP == 1 ? MGCT_BP_PL_MINW : 1) void k_backproject_pl(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
+                                                        float *__restrict__ part, long np_stride,
+                                                        const SepView *__restrict__ sep,
+                                                        const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
+                                                        int nv, int nviews_sub, int view0, int view_step,
+                                                        int per_chunk, int nchunks) {
+    __shared__ float lds[4 * NP * kPlSlots * KZ * 64];
+    float *slot = lds + (threadIdx.x >> 6) * (NP * kPlSlots * KZ * 64) + (threadIdx.x & 63);
+    if (blockIdx.z == 0)
+        bp_plane_wave<0, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
+                                         view0, view_step, per_chunk, nchunks);
+    else
+        bp_plane_wave<1, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
+                                         view0, view_step, per_chunk, nchunks);
+}
+
+// waves of the separable back-projector: one per two rows when nz <= 32;
+// deeper grids one per (plane, kPlRows rows, 64 KZ z) of each part (both
+// parts counted), or one per kBpBI x kBpBJ block of rows and 64 KZ z values
+long bp_waves(const Level &L, int *kz, int np) {
+    // KZ = 2 where the depth allows (the dual-output variant keeps KZ = 1:
+    // its FP64 sums would take too many registers)
     int KZ = 1;
-    if (MGCT_BP_KZMAX >= 2 && 2 * 64 <= L.nz) KZ = 2;
+    if (MGCT_BP_KZMAX >= 2 && 2 * 64 <= L.nz && (np == 1 || !MGCT_BP_PLANE)) KZ = 2;
     if (kz) *kz = KZ;
     if (L.nz <= MGCT_BP_HALF_MAXNZ) return (long)L.nx * ((L.ny + 1) / 2);
-    return (long)((L.nz + 64 * KZ - 1) / (64 * KZ)) * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
+    const long zch = (L.nz + 64 * KZ - 1) / (64 * KZ);
+    if (MGCT_BP_PLANE)
+        return 2 * zch * std::max((long)L.nx * ((L.ny + kPlRows - 1) / kPlRows),
+                                  (long)L.ny * ((L.nx + kPlRows - 1) / kPlRows));
+    return zch * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
 }
 
 // View chunks (partial volumes summed afterwards) so that about 16384 waves
 // run, each over at least MGCT_BP_MIN_VIEWS views.
-int bp_chunks(const Level &L, int nviews_sub) {
-    const long waves = bp_waves(L, nullptr);
+int bp_chunks(const Level &L, int nviews_sub, int np) {
+    const long waves = bp_waves(L, nullptr, np);
     long c = (16384 + waves - 1) / waves;
     if (c > 64) c = 64;
     if (c > nviews_sub / MGCT_BP_MIN_VIEWS) c = nviews_sub / MGCT_BP_MIN_VIEWS;
     return c < 1 ? 1 : (int)c;
+}
+
+// partial volumes per output: the view chunks, times the two parts of the
+// plane-blocked kernel
+static bool bp_plane(const Level &L) { return MGCT_BP_PLANE && L.nz > MGCT_BP_HALF_MAXNZ; }
+static int bp_slices(const Level &L, int nviews_sub, int np) {
+    return bp_chunks(L, nviews_sub, np) * (bp_plane(L) ? 2 : 1);
 }
 
 // With more than one view chunk the chunks' partial volumes are summed into
@@ -1088,13 +1282,29 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
                             int *nchunks_out = nullptr) {
     if (!L.separable) return hipErrorNotSupported;
     int KZ = 1;
-    const long waves = bp_waves(L, &KZ);
-    const int nchunks = bp_chunks(L, nviews_sub);
+    const long waves = bp_waves(L, &KZ, NP);
+    const int nchunks = bp_chunks(L, nviews_sub, NP);
+    const int nslices = bp_slices(L, nviews_sub, NP);
     const int per = (nviews_sub + nchunks - 1) / nchunks;
     const long nvox = (long)L.nx * L.ny * L.nz;
-    float *part0 = part, *part1 = part ? part + (long)nchunks * nvox : nullptr;
-    if (nchunks > 1 && !part) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
+    float *part0 = part, *part1 = part ? part + (long)nslices * nvox : nullptr;
+    if (nslices > 1 && !part) return hipErrorInvalidValue;
+    if (bp_plane(L)) {
+        dim3 grid((unsigned)((waves / 2 + 3) / 4), (unsigned)nchunks, 2);
+        const long nps = (long)nslices * nvox;
+#define MGCT_BPL(K, Z)                                                                                              \
+    k_backproject_pl<K, NP, PT, Z><<<grid, 256, 0, s>>>(pt0, pt1, part, nps, L.d_sep, L.d_cols, L.nx, L.ny, L.nz,     \
+                                                        L.nu, L.nv, nviews_sub, view0, view_step, per, nchunks)
+        if (KZ == 2) {
+            if (L.nz > 128) MGCT_BPL(2, true);
+            else MGCT_BPL(2, false);
+        } else {
+            if (L.nz > 64) MGCT_BPL(1, true);
+            else MGCT_BPL(1, false);
+        }
+#undef MGCT_BPL
+    } else {
+        dim3 grid((unsigned)((waves + 3) / 4), (unsigned)nchunks);
 #define MGCT_BPB_Z(K, Z)                                                                                            \
     k_backproject_blk<K, NP, OT, PT, kBpBI, kBpBJ, Z><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1,       \
                                                                          L.d_sep, L.d_cols, L.d_axis, L.nx, L.ny,   \
@@ -1109,26 +1319,27 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     k_backproject_sep<K, NP, OT, PT, H><<<grid, 256, 0, s>>>(pt0, pt1, vol0, vol1, part0, part1, L.d_sep, L.d_cols,     \
                                                       L.d_axis, L.nx, L.ny, L.nz, L.nu, L.nv, nviews_sub, view0,      \
                                                       view_step, per)
-    if (L.nz <= MGCT_BP_HALF_MAXNZ) {
-        MGCT_BP(1, true);
-    } else {
-        if (KZ == 2) MGCT_BPB(2);
-        else MGCT_BPB(1);
-    }
+        if (L.nz <= MGCT_BP_HALF_MAXNZ) {
+            MGCT_BP(1, true);
+        } else {
+            if (KZ == 2) MGCT_BPB(2);
+            else MGCT_BPB(1);
+        }
 #undef MGCT_BP
 #undef MGCT_BPB
 #undef MGCT_BPB_Z
-    if (nchunks_out) *nchunks_out = nchunks;
-    if (nchunks > 1 && !leave_chunks) {
+    }
+    if (nchunks_out) *nchunks_out = nslices;
+    if (nslices > 1 && !leave_chunks) {
         unsigned g = (unsigned)std::min<long>((nvox + 255) / 256, 65535L * 4);
-        k_sum_chunks<OT><<<g, 256, 0, s>>>(part0, vol0, nvox, nchunks);
-        if (NP > 1) k_sum_chunks<OT><<<g, 256, 0, s>>>(part1, vol1, nvox, nchunks);
+        k_sum_chunks<OT><<<g, 256, 0, s>>>(part0, vol0, nvox, nslices);
+        if (NP > 1) k_sum_chunks<OT><<<g, 256, 0, s>>>(part1, vol1, nvox, nslices);
     }
     return hipGetLastError();
 }
 
 size_t backproject_scratch_bytes(const Level &L, int nviews_sub, int np) {
-    const int c = bp_chunks(L, nviews_sub);
+    const int c = bp_slices(L, nviews_sub, np);
     return c > 1 ? (size_t)c * L.vox() * sizeof(float) * np : 0;
 }
 
