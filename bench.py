@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "873be75896c8228eb1a9193a369e16c33b21115e9c5a2ee2f0fcdd921c615e5b", "bytes_per_launch": 391124759},
+    "k_backproject_pl": {"source_sha256": "0e58f229b5948477e264b308d1fa5759826e5c43d3c2ec8c8bc7acebf578f417", "bytes_per_launch": 380155598},
 }
 
 

@@ -1073,7 +1073,9 @@ constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 // by a runtime index, so the per-view sums live in LDS slots private to each
 // lane (no other lane touches them: no barriers), with two spare rows for the
 // taps that fall just outside the block; after each view they are added to
-// FP64 registers and cleared.  The parts write separate partial volumes,
+// FP64 registers and cleared.  The slot updates are plain LDS read-add-writes
+// (exact, as the slots are lane-private; the LDS atomic add measured about
+// five times slower here).  The parts write separate partial volumes,
 // summed with the view chunks afterwards.  Per voxel and view this forms
 // about 1.6 column sums against 2.5 for the 2 x 2 row blocks
 // (k_backproject_blk, kept for comparison builds).
@@ -1082,10 +1084,6 @@ constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 #endif
 constexpr int kPlRows = MGCT_BP_PLROWS;
 constexpr int kPlSlots = kPlRows + 2;
-
-// A lane adds into its own slots only, so a plain LDS read-add-write is
-// exact; the LDS atomic add measured about five times slower in this loop.
-__device__ __forceinline__ void lds_add(float *p, float v) { *p += v; }
 
 template <int PART, int KZ, int NP, typename PT, bool ZS>
 __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
@@ -1110,35 +1108,48 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
     int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
     alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
     ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+    // The next column's descriptor is loaded while this one is worked on, and
+    // every field is used before the one skip test, so that its scalar loads
+    // go out together; the two rows' slots are read before the detector
+    // window so that the LDS round trip overlaps the window's loads.
+    if (alo > ahi) return;  // no column reaches the block (also keeps cv[alo] in range)
+    ColD Cn = cv[alo];
     for (int a = alo; a <= ahi; ++a) {
-        const ColD C = cv[a];
-        if (C.axis != PART) continue;
+        const ColD C = Cn;
+        Cn = cv[min(a + 1, ahi)];
         const double tau = dm * (PART == 0 ? C.rdx : C.rdy);  // ray parameter at the plane
-        if (tau < 0.0 || tau > 1.0) continue;
         const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
         const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
         const int rl = __builtin_amdgcn_readfirstlane((int)fl - r0);  // block row of the lower tap
-        if (rl < -1 || rl >= kPlRows) continue;
-        const float whi = (float)(pos - fl), wlo = 1.f - whi;
-        const double tz = tau * S.vz;             // row spacing along z at the plane
-        const double zc = fma(tau, S.dz0, S.sz);  // z of row 0 at the plane
+        const double tz = tau * S.vz;                                 // row spacing along z at the plane
+        const double zc = fma(tau, S.dz0, S.sz);                      // z of row 0 at the plane
+        const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;      // 1 / tz
+        if (C.axis != PART || !(tau >= 0.0 && tau <= 1.0) || rl < -1 || rl >= kPlRows) continue;
         if (ZS) {
             const double zend = fma(tz, (double)(nv - 1), zc);
             if (fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0) continue;
         }
-        const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;  // 1 / tz
+        float *sl = slot + (rl + 1) * KZ * 64;
+        float old[NP][2][KZ];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < KZ; ++q) {
+                old[p][0][q] = sl[(p * kPlSlots * KZ + q) * 64];
+                old[p][1][q] = sl[((p * kPlSlots + 1) * KZ + q) * 64];
+            }
+        const float whi = (float)(pos - fl), wlo = 1.f - whi;
         const double hw = fabs(rtz);
         const PT *col0 = base0 + (long)a * nv;
         const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
         float sums[NP][KZ];
         bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
-        float *sl = slot + (rl + 1) * KZ * 64;
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int q = 0; q < KZ; ++q) {
-                lds_add(sl + (p * kPlSlots * KZ + q) * 64, wlo * sums[p][q]);
-                lds_add(sl + ((p * kPlSlots + 1) * KZ + q) * 64, whi * sums[p][q]);
+                sl[(p * kPlSlots * KZ + q) * 64] = fmaf(wlo, sums[p][q], old[p][0][q]);
+                sl[((p * kPlSlots + 1) * KZ + q) * 64] = fmaf(whi, sums[p][q], old[p][1][q]);
             }
     }
 }
@@ -1256,11 +1267,14 @@ long bp_waves(const Level &L, int *kz, int np) {
     return zch * ((L.nx + kBpBI - 1) / kBpBI) * ((L.ny + kBpBJ - 1) / kBpBJ);
 }
 
-// View chunks (partial volumes summed afterwards) so that about 16384 waves
-// run, each over at least MGCT_BP_MIN_VIEWS views.
+#ifndef MGCT_BP_WAVES
+#define MGCT_BP_WAVES 16384  // waves the view chunks aim for
+#endif
+// View chunks (partial volumes summed afterwards) so that about MGCT_BP_WAVES
+// waves run, each over at least MGCT_BP_MIN_VIEWS views.
 int bp_chunks(const Level &L, int nviews_sub, int np) {
     const long waves = bp_waves(L, nullptr, np);
-    long c = (16384 + waves - 1) / waves;
+    long c = (MGCT_BP_WAVES + waves - 1) / waves;
     if (c > 64) c = 64;
     if (c > nviews_sub / MGCT_BP_MIN_VIEWS) c = nviews_sub / MGCT_BP_MIN_VIEWS;
     return c < 1 ? 1 : (int)c;

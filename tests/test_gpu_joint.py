@@ -81,8 +81,8 @@ def test_joint_estimation_full_size():
     data from the device phantom generators under a hidden misalignment,
     Poisson noise, then Adam on (dx, dz, tilt) alternating with one warm-started
     iteration of Algorithm 1 (3 grids, radial filter; step sizes from the
-    unperturbed geometry) per geometry update.  dx and the tilt move toward
-    the hidden values.  A tilted detector takes the general-geometry kernels."""
+    unperturbed geometry) per geometry update, 24 updates (the step lowered
+    after 12).  dx and the tilt move toward the hidden values.  A tilted detector takes the general-geometry kernels."""
     import time
     import torch
     from paper_2103_10329_amd.learned import poisson_data
@@ -110,7 +110,9 @@ def test_joint_estimation_full_size():
     lr, beta1, beta2 = 0.12, 0.9, 0.999
     err0 = np.abs(p - p_true)
     t0 = time.time()
-    for it in range(1, 11):
+    for it in range(1, 25):
+        if it == 13:
+            lr = 0.04
         if it > 1:
             ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), nu, nu, synth.perturb_geometry(views0, cfg.h, *p))
             ctx.multigrid_solve(vol, b, 3, 1, filt, alphas=alphas, want_hist=False)
