@@ -109,6 +109,35 @@ def test_osemtr_coarse_grid():
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("case", ["64cube", "ragged"])
+def test_osemtr_deep_grids(case):
+    """OS-EMTR on grids deeper than 32 (the plane-blocked back-projector with
+    two outputs): 64^3 x 360 views of 96^2 (one pass of 8 subsets), and a
+    ragged 37 x 29 x 70 grid with a 53 x 71 detector (row blocks with tails,
+    z range split in two)."""
+    if case == "64cube":
+        g = workload("c1").level(1)
+        d = synth.make_dataset("c1", truth=False)
+        b = oracle.restrict_stack(d["b"])
+        M, passes = 8, 1
+    else:
+        views = synth.trajectory(48, 4, 72.0 / 53)
+        views[:, 9:12] = np.array([0.0, 0.0, 0.45])
+        g = oracle.Geom(37, 29, 70, 0.45, (0.3, -0.2, 0.1), 53, 71, views)
+        ph = synth.random_phantom(synth.CONFIGS["c0"], 1000)
+        b = 0.25 * synth.line_integrals(ph, g.views, g.nu, g.nv)  # line integrals up to about 3
+        M, passes = 4, 2
+    mu0 = np.zeros(g.vol_shape)
+    say("osemtr", case, g.vol_shape, g.stack_shape)
+    ref = oracle.osemtr(g, mu0, b, M=M, passes=passes)
+    ctx = context(g)
+    vol = to_dev(mu0)
+    ctx.osemtr(vol, to_dev(b), subsets=M, passes=passes)
+    err = rel_l2(to_host(vol), ref)
+    say("  rel L2", err)
+    assert err <= 1e-5
+
+
 def _mg_case(n, nu, n_views, levels, n_outer, lam, bil, kind="radial"):
     g = workload("c1", n=n, nu=nu, nv=nu, n_views=n_views)
     ph = synth.random_phantom(synth.CONFIGS["c1"], 1001)
