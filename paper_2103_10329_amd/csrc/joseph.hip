@@ -371,7 +371,10 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
                                                      const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
                                                      int nv, double h, int view0, int view_step, int tab_len) {
     extern __shared__ PlaneEntry tab[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // wave index made scalar: the column descriptor, the copy's base and the
+    // table's address then live in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int a = blockIdx.x * 4 + w;
     const int b = blockIdx.y * 64 + lane;
     const int v = view0 + blockIdx.z * view_step;
