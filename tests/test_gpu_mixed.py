@@ -66,7 +66,10 @@ def test_backproject_f16_stack_bf16_volume():
     ref_exact = oracle.backproject(g, y)
     e1, e2, e3 = rel_l2(out32, ref_stored), rel_l2(out32, ref_exact), rel_l2(out16, ref_exact)
     say("At f16 data: f32 out vs stored", e1, "vs exact", e2, "; bf16 out vs exact", e3)
-    assert e1 <= 5e-4 and e2 <= 1e-3 and e3 <= 3e-3
+    # the transposed, ray-scaled copy of an F16 stack is itself F16: each
+    # scaled value is rounded once more (2^-11 relative, random), which
+    # leaves about 1e-5 on the FP32 sums; BF16 output adds its own 2^-9
+    assert e1 <= 3e-5 and e2 <= 5e-5 and e3 <= 3e-3
 
 
 def test_mixed_sirt_c0():
