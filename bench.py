@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "0e58f229b5948477e264b308d1fa5759826e5c43d3c2ec8c8bc7acebf578f417", "bytes_per_launch": 380155598},
+    "k_backproject_pl": {"source_sha256": "3928058a26ff0e64c435a3fbca69427379478d7835d0f1a01c4ac9634ef5e43c", "bytes_per_launch": 380474060},
 }
 
 
