@@ -363,6 +363,15 @@ template <typename T> __device__ __forceinline__ float round_as(float x) { retur
 template <> __device__ __forceinline__ float round_as<_Float16>(float x) { return (float)(_Float16)x; }
 
 // WIDE: the pair copies exceed 4 GiB, so sample addresses are formed in 64 bits.
+#ifndef MGCT_PROJ_PW2_MIN
+#define MGCT_PROJ_PW2_MIN 512  // grid width from which blocks hold 2 columns instead of 4
+#endif
+// Waves (adjacent detector columns) per block of the separable projector,
+// chosen by measurement: 4 on grids up to 256 wide (2 was 4-7 % slower at
+// 128^3 and 256^3), 2 from 512 wide (4 was 1 % slower at 512^3 in FP32 and
+// 8 % with BF16 copies).
+static int proj_pw(const Level &L) { return std::max(L.nx, L.ny) >= MGCT_PROJ_PW2_MIN ? 2 : 4; }
+
 template <typename VT, typename PT, int MODE, typename TB, bool WIDE>
 __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
                                                      PT *__restrict__ out, PT *__restrict__ out2,
@@ -375,7 +384,8 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
     // wave index made scalar: the column descriptor, the copy's base and the
     // table's address then live in scalar registers
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int a = blockIdx.x * 4 + w;
+    const int pw = blockDim.x >> 6;  // waves per block: 2 or 4
+    const int a = blockIdx.x * pw + w;
     const int b = blockIdx.y * 64 + lane;
     const int v = view0 + blockIdx.z * view_step;
     PlaneEntry *T = tab + w * tab_len;
@@ -458,15 +468,17 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
         }
     }
     if (MODE == kProjResidual || MODE == kProjNorm) {
-        // fixed-order block sum of r^2: within each wave, then over the 4 waves
+        // fixed-order block sum of r^2: within each wave, then over the waves
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
         __shared__ double wsum[4];
         if (lane == 0) wsum[w] = r2;
         __syncthreads();
-        if (threadIdx.x == 0)
-            partials[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
-                (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < pw; ++q) t += wsum[q];
+            partials[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
+        }
     }
 }
 
@@ -477,20 +489,22 @@ hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, vo
 }
 
 size_t project_sep_blocks(const Level &L, int nviews_sub) {
-    return (size_t)((L.nu + 3) / 4) * ((L.nv + 63) / 64) * nviews_sub;
+    const int pw = proj_pw(L);
+    return (size_t)((L.nu + pw - 1) / pw) * ((L.nv + 63) / 64) * nviews_sub;
 }
 
 hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtype, int mode, void *out, void *out2,
                                    int out_dtype, const void *y, int y_dtype, const float *pi, double *partials,
                                    const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
-    dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);
+    const int pw = proj_pw(L);
+    dim3 grid((L.nu + pw - 1) / pw, (L.nv + 63) / 64, nviews_sub);
     const int tab_len = std::max(L.nx, L.ny);
-    const size_t lds = 4 * (size_t)tab_len * sizeof(PlaneEntry);
+    const size_t lds = pw * (size_t)tab_len * sizeof(PlaneEntry);
     const size_t copy_bytes = pair_copy_elems(L) * (vt_dtype == MGCT_F32 ? 4 : 2);
     const bool wide = copy_bytes > 0xFFFFFFF0ull;
     if (wide && mode == kProjEmtr) return hipErrorNotSupported;  // coarse grids only
 #define MGCT_PROJS_W(VT, PT, MODE, TB, W)                                                                        \
-    k_project_sep<VT, PT, MODE, TB, W><<<grid, 256, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)out,         \
+    k_project_sep<VT, PT, MODE, TB, W><<<grid, 64 * pw, lds, s>>>((const VT *)vtx, (const VT *)vty, (PT *)out,         \
                                                               (PT *)out2, (const TB *)y, pi, partials, L.d_views,    \
                                                               L.d_cols, L.nx, L.ny, L.nz, L.nu, L.nv, L.h, view0,    \
                                                               view_step, tab_len)
