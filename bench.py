@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "3928058a26ff0e64c435a3fbca69427379478d7835d0f1a01c4ac9634ef5e43c", "bytes_per_launch": 380474060},
+    "k_backproject_pl": {"source_sha256": "2c68459871cf78b2878c3e3a5bc0eb31e4678215d3d2cc0025f7bf6e7c9e69b5", "bytes_per_launch": 382573541},
 }
 
 
