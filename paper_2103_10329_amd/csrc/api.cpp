@@ -498,8 +498,10 @@ int cnn_train_scratch(Ctx &c, int nx, int ny, int nz, CnnBuffers &B) {
     std::string key = "cnn_xT_" + std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz);
     B.xT = (uint16_t *)workspace(c, key, padded, true);
     const long n = (long)nx * ny * nz;
-    const long rows = (long)ny * nz, nch = (rows + 15) / 16, nvb = (n + 4095) / 4096;
-    const size_t part = std::max({(size_t)nch * 27 * 1024, (size_t)nvb * 32, (size_t)(nx / 32) * nch * 865}) * 4;
+    const long rows = (long)ny * nz, nch = (rows + 15) / 16;
+    const long vchunk = std::max(512L, (n + 4095) / 4096), nvb = (n + vchunk - 1) / vchunk;  // as cnn_backward
+    const long wrb = (long)(nx / 32) * ((rows + 3) / 4);  // VALU weight-gradient blocks (4 rows each)
+    const size_t part = std::max({(size_t)nch * 27 * 1024, (size_t)nvb * 32, (size_t)wrb * 865}) * 4;
     B.partial = (float *)workspace(c, "cnn_partial", part);
     if (!B.xT || !B.partial) return MGCT_ERR_OOM;
     return MGCT_OK;

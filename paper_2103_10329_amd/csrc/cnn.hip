@@ -143,22 +143,42 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out, cons
 __global__ __launch_bounds__(256) void k_conv4_bwd_input(const float *__restrict__ dout, const float *__restrict__ w,
                                                          const float *__restrict__ z3, uint16_t *__restrict__ dz3,
                                                          Dims d) {
+    // a block covers 256 consecutive voxels; their z3 rows are read and
+    // their dz3 rows written through LDS, so the global accesses are
+    // contiguous (one thread per voxel would touch 64 rows per access)
+    __shared__ float zs[256 * 33];
     const long n = (long)d.nx * d.ny * d.nz;
-    const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
-    float g[27];
+    const long vb = blockIdx.x * 256L;
+    for (int e = threadIdx.x; e < 256 * 32; e += 256)
+        zs[(e >> 5) * 33 + (e & 31)] = vb + (e >> 5) < n ? z3[vb * 32 + e] : 0.f;
+    __syncthreads();
+    const long v = vb + threadIdx.x;
+    float o[32];
+    if (v < n) {
+        const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+        float g[27];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
-        long q;
-        g[t] = tap_voxel(d, x, y, z, 26 - t, q) ? dout[q] : 0.f;  // v - off_t = v + off_(26-t)
-    }
-    for (int ci = 0; ci < 32; ++ci) {
-        float acc = 0.f;
+        for (int t = 0; t < 27; ++t) {
+            long q;
+            g[t] = tap_voxel(d, x, y, z, 26 - t, q) ? dout[q] : 0.f;  // v - off_t = v + off_(26-t)
+        }
 #pragma unroll
-        for (int t = 0; t < 27; ++t) acc = fmaf(w[kW4 + ci * 27 + t], g[t], acc);
-        dz3[v * 32 + ci] = to_bf(acc * gelu_grad(z3[v * 32 + ci]));
+        for (int ci = 0; ci < 32; ++ci) {
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < 27; ++t) acc = fmaf(w[kW4 + ci * 27 + t], g[t], acc);
+            o[ci] = acc * gelu_grad(zs[threadIdx.x * 33 + ci]);
+        }
+    } else {
+#pragma unroll
+        for (int ci = 0; ci < 32; ++ci) o[ci] = 0.f;
     }
+    __syncthreads();
+#pragma unroll
+    for (int ci = 0; ci < 32; ++ci) zs[threadIdx.x * 33 + ci] = o[ci];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256 * 32; e += 256)
+        if (vb + (e >> 5) < n) dz3[vb * 32 + e] = to_bf(zs[(e >> 5) * 33 + (e & 31)]);
 }
 
 // Weight gradient of a layer with one input channel (layer 1: X = u FP32,
@@ -191,16 +211,29 @@ __global__ __launch_bounds__(256) void k_wgrad_valu(const float *__restrict__ xf
     for (int row = r0; row < r1; ++row) {
         const int y = row % d.ny, z = row / d.ny;
         __syncthreads();  // previous row's reads are done
-        for (int e = threadIdx.x; e < 9 * 34 * C; e += 256) {
-            const int tr = e / (34 * C), rem = e % (34 * C);
-            const int xl = rem / C, c = rem % C;
-            const int yy = y + tr % 3 - 1, zz = z + tr / 3 - 1, xx = x0 + xl - 1;
-            float val = 0.f;
-            if (yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx) {
-                const long q = ((long)zz * d.ny + yy) * d.nx + xx;
-                val = MODE == 1 ? xf[q] : bf(xh[q * 32 + c]);
+        if (MODE == 1) {
+            for (int e = threadIdx.x; e < 9 * 34; e += 256) {
+                const int tr = e / 34, xl = e % 34;
+                const int yy = y + tr % 3 - 1, zz = z + tr / 3 - 1, xx = x0 + xl - 1;
+                float val = 0.f;
+                if (yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx)
+                    val = xf[((long)zz * d.ny + yy) * d.nx + xx];
+                xs[tr][xl] = val;
             }
-            xs[tr][xl * CS + c] = val;
+        } else {
+            // eight channels (16 bytes) per load
+            for (int e = threadIdx.x; e < 9 * 34 * 4; e += 256) {
+                const int tr = e / (34 * 4), rem = e % (34 * 4);
+                const int xl = rem >> 2, c8 = (rem & 3) * 8;
+                const int yy = y + tr % 3 - 1, zz = z + tr / 3 - 1, xx = x0 + xl - 1;
+                uint16_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx) {
+                    const long q = ((long)zz * d.ny + yy) * d.nx + xx;
+                    __builtin_memcpy(h, __builtin_assume_aligned(xh + q * 32 + c8, 16), 16);
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) xs[tr][xl * CS + c8 + k] = bf(h[k]);
+            }
         }
         const long gv = (long)row * d.nx + x0;
         for (int e = threadIdx.x; e < 32 * CG; e += 256)
@@ -233,15 +266,19 @@ __global__ __launch_bounds__(256) void k_wgrad_valu(const float *__restrict__ xf
     }
 }
 
-// grads[dst + j] = sum_b partial[b][j] (fixed order)
-__global__ void k_sum_partials(const float *__restrict__ partial, int nparts, int R, float *__restrict__ grads,
-                               int dst_stride_mode) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= R) return;
+// out[j] = sum_b partial[b][j] over nparts rows of R values, one wave per j:
+// lane l adds rows l, l + 64, ... in FP64, then a fixed xor-shuffle tree
+// (the order is fixed, so the result does not depend on scheduling).
+__global__ __launch_bounds__(256) void k_sum_partials(const float *__restrict__ partial, int nparts, int R,
+                                                      float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= R) return;  // whole wave
     double acc = 0.0;
-    for (int b = 0; b < nparts; ++b) acc += (double)partial[(long)b * R + j];
-    grads[j] = (float)acc;
-    (void)dst_stride_mode;
+    for (int b = lane; b < nparts; b += 64) acc += (double)partial[(long)b * R + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[j] = (float)acc;
 }
 
 // ------------------------------------------------------ matrix cores ----
@@ -353,17 +390,21 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const uint16_t *__restrict__
     }
 }
 
-// grads[W at layer offset][co][ci][t] = sum_chunks partial[chunk][t][co][ci]
-__global__ void k_wgrad_mfma_sum(const float *__restrict__ partial, int nchunks, int CI, float *__restrict__ gw) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over co*CI*27
-    if (i >= 32 * CI * 27) return;
+// grads[W at layer offset][co][ci][t] = sum_chunks partial[chunk][t][co][ci],
+// one wave per weight as in k_sum_partials.
+__global__ __launch_bounds__(256) void k_wgrad_mfma_sum(const float *__restrict__ partial, int nchunks, int CI,
+                                                        float *__restrict__ gw) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // over co*CI*27
+    if (i >= 32 * CI * 27) return;                      // whole wave
     const int co = i / (CI * 27), ci = (i / 27) % CI, t = i % 27;
     double acc = 0.0;
-    for (int c = 0; c < nchunks; ++c) acc += (double)partial[((long)c * 27 + t) * 1024 + co * 32 + ci];
-    gw[i] = (float)acc;
+    for (int c = lane; c < nchunks; c += 64) acc += (double)partial[((long)c * 27 + t) * 1024 + co * 32 + ci];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) gw[i] = (float)acc;
 }
 
-// db[co] = sum_v G[v][co] (BF16 channels-last), partial per block then summed.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ g, int C, long n, long chunk,
                                                    float *__restrict__ partial) {
     // thread (voxel group vg, channel c), C divides 256: coalesced rows of g
@@ -421,33 +462,34 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     const unsigned vb = blocks(n), tb = (unsigned)((n / 32 + 3) / 4);
     k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
     // layer 4
-    const long vchunk = 4096;
+    // bias gradients: blocks of 512 voxels (at most 4096 blocks), then a wave per channel
+    const long vchunk = std::max(512L, (n + 4095) / 4096);
     const int nvb = (int)((n + vchunk - 1) / vchunk);
     const int rows = ny * nz;
-    const int wrpc = 16, nwb = (nx / 32) * ((rows + wrpc - 1) / wrpc);
+    const int wrpc = 4, nwb = (nx / 32) * ((rows + wrpc - 1) / wrpc);
     k_wgrad_valu<4><<<nwb, 256, 0, s>>>(nullptr, B.h3, nullptr, B.dout, B.partial, d, wrpc);
-    k_sum_partials<<<blocks(865), 256, 0, s>>>(B.partial, nwb, 865, grads + kW4, 0);
+    k_sum_partials<<<blocks(865, 4), 256, 0, s>>>(B.partial, nwb, 865, grads + kW4);
     k_conv4_bwd_input<<<vb, 256, 0, s>>>(B.dout, S.master, B.z3, B.dz3, d);
     // layer 3: weights (channels-first copies), bias, input gradient -> dz2
     const int rpc = 16, nch = (rows + rpc - 1) / rpc;
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz3, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 32), 256, 0, s>>>(B.h2, B.xT, 32, d);
     k_wgrad_mfma<32><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
-    k_wgrad_mfma_sum<<<blocks(32 * 32 * 27), 256, 0, s>>>(B.partial, nch, 32, grads + kW3);
+    k_wgrad_mfma_sum<<<blocks(32 * 32 * 27, 4), 256, 0, s>>>(B.partial, nch, 32, grads + kW3);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz3, 32, n, vchunk, B.partial);
-    k_sum_partials<<<1, 256, 0, s>>>(B.partial, nvb, 32, grads + kB3, 0);
+    k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB3);
     k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz3, S.p3d, nullptr, B.z2, nullptr, B.dz2, 32, d);
     // layer 2
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz2, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 16), 256, 0, s>>>(B.h1, B.xT, 16, d);
     k_wgrad_mfma<16><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
-    k_wgrad_mfma_sum<<<blocks(32 * 16 * 27), 256, 0, s>>>(B.partial, nch, 16, grads + kW2);
+    k_wgrad_mfma_sum<<<blocks(32 * 16 * 27, 4), 256, 0, s>>>(B.partial, nch, 16, grads + kW2);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz2, 32, n, vchunk, B.partial);
-    k_sum_partials<<<1, 256, 0, s>>>(B.partial, nvb, 32, grads + kB2, 0);
+    k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB2);
     k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz2, S.p2d, nullptr, B.z1, nullptr, B.dz1, 16, d);
     // layer 1 (input gradient not needed); dz1 holds GELU' * dh1 in BF16
     k_wgrad_valu<1><<<nwb, 256, 0, s>>>(u, nullptr, B.dz1, nullptr, B.partial, d, wrpc);
-    k_sum_partials<<<blocks(448), 256, 0, s>>>(B.partial, nwb, 448, grads + kW1, 0);
+    k_sum_partials<<<blocks(448, 4), 256, 0, s>>>(B.partial, nwb, 448, grads + kW1);
     return hipGetLastError();
 }
 
