@@ -288,44 +288,73 @@ __global__ __launch_bounds__(256) void k_sum_partials(const float *__restrict__ 
 // MODE 1 (input gradient): out channels NOUT (16 or 32), hout = BF16
 //   acc * GELU'(zprev).
 // X: [v][CI] BF16; P: [27][32][CI] BF16 (B operand, n-major).  nx % 32 == 0.
+#ifndef MGCT_CONV_ROWS
+#define MGCT_CONV_ROWS 2
+#endif
+// Output rows (y) per wave: each weight fragment is loaded once per tap and
+// channel chunk and used for all of them.
+constexpr int kConvRows = MGCT_CONV_ROWS;
+
 template <int CI, int MODE>
 __global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
                                                    const float *__restrict__ bias, const float *__restrict__ zprev,
                                                    float *__restrict__ zout, uint16_t *__restrict__ hout, int nout,
                                                    Dims d) {
+    constexpr int NT = kConvRows;
     const int lane = threadIdx.x & 63;
-    const long tile = blockIdx.x * 4L + (threadIdx.x >> 6);
-    const long n = (long)d.nx * d.ny * d.nz;
-    const long v0 = tile * 32;
-    if (v0 >= n) return;  // whole wave; no barrier below
+    const long wave = blockIdx.x * 4L + (threadIdx.x >> 6);
+    const int nxt = d.nx / 32, nyt = (d.ny + NT - 1) / NT;
+    if (wave >= (long)nxt * nyt * d.nz) return;  // whole wave; no barrier below
+    const int xt = (int)(wave % nxt), yt = (int)((wave / nxt) % nyt), z = (int)(wave / ((long)nxt * nyt));
+    const int x0 = xt * 32, y0 = yt * NT;
     const int m = lane & 31, kh = lane >> 5;
-    const int x0 = (int)(v0 % d.nx), y = (int)((v0 / d.nx) % d.ny), z = (int)(v0 / ((long)d.nx * d.ny));
-    floatx16 acc = {};
+    floatx16 acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = floatx16{};
     for (int t = 0; t < 27; ++t) {
-        long q;
-        const bool ok = tap_voxel(d, x0 + m, y, z, t, q);
+        long q[NT];
+        bool ok[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            q[i] = 0;
+            ok[i] = y0 + i < d.ny && tap_voxel(d, x0 + m, y0 + i, z, t, q[i]);
+        }
 #pragma unroll
         for (int kc = 0; kc < CI / 16; ++kc) {
-            bf16x8 a = {};
-            if (ok) a = *reinterpret_cast<const bf16x8 *>(X + q * CI + kc * 16 + kh * 8);
             const bf16x8 b = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + m) * CI + kc * 16 + kh * 8);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                bf16x8 a = {};
+                if (ok[i]) a = *reinterpret_cast<const bf16x8 *>(X + q[i] * CI + kc * 16 + kh * 8);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+            }
         }
     }
     // D[i][j]: column j = lane % 32, row i = 8 (r / 4) + 4 (lane / 32) + r % 4 for register r
     const int col = m;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
-        const long v = v0 + row;
-        if (MODE == 0) {
-            const float zv = acc[r] + bias[col];
-            if (zout) zout[v * 32 + col] = zv;
-            hout[v * 32 + col] = to_bf(gelu(zv));
-        } else if (col < nout) {
-            hout[v * nout + col] = to_bf(acc[r] * gelu_grad(zprev[v * nout + col]));
+    for (int i = 0; i < NT; ++i) {
+        if (y0 + i >= d.ny) break;  // wave-uniform
+        const long v0 = ((long)z * d.ny + y0 + i) * d.nx + x0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+            const long v = v0 + row;
+            if (MODE == 0) {
+                const float zv = acc[i][r] + bias[col];
+                if (zout) zout[v * 32 + col] = zv;
+                hout[v * 32 + col] = to_bf(gelu(zv));
+            } else if (col < nout) {
+                hout[v * nout + col] = to_bf(acc[i][r] * gelu_grad(zprev[v * nout + col]));
+            }
         }
     }
+}
+
+// waves (blocks of four) of k_conv_mfma
+static unsigned conv_blocks(int nx, int ny, int nz) {
+    const long w = (long)(nx / 32) * ((ny + kConvRows - 1) / kConvRows) * nz;
+    return (unsigned)((w + 3) / 4);
 }
 
 // channels-last BF16 [v][C] -> channels-first [C][nz+2][ny+2][nx+2] (zero border)
@@ -446,7 +475,7 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
                        bool keep, hipStream_t s) {
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
-    const unsigned vb = blocks(n), tb = (unsigned)((n / 32 + 3) / 4);
+    const unsigned vb = blocks(n), tb = conv_blocks(nx, ny, nz);
     k_conv1_fwd<<<vb, 256, 0, s>>>(u, S.master, keep ? B.z1 : nullptr, B.h1, d);
     k_conv_mfma<16, 0><<<tb, 256, 0, s>>>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d);
     k_conv_mfma<32, 0><<<tb, 256, 0, s>>>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d);
@@ -459,7 +488,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
                         hipStream_t s) {
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
-    const unsigned vb = blocks(n), tb = (unsigned)((n / 32 + 3) / 4);
+    const unsigned vb = blocks(n), tb = conv_blocks(nx, ny, nz);
     k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
     // layer 4
     // bias gradients: blocks of 512 voxels (at most 4096 blocks), then a wave per channel
