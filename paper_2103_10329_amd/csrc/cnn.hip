@@ -351,10 +351,97 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ 
     }
 }
 
-// waves (blocks of four) of k_conv_mfma
-static unsigned conv_blocks(int nx, int ny, int nz) {
-    const long w = (long)(nx / 32) * ((ny + kConvRows - 1) / kConvRows) * nz;
-    return (unsigned)((w + 3) / 4);
+// The same convolution with the input staged in LDS: a block covers one
+// 32-voxel x tile, 4 * kConvLdsRows rows (y) and one z; it loads the 3 x (rows+2)
+// x 34 voxel neighbourhood once (16-byte loads along the contiguous
+// channels-last rows, zero outside the volume) and each wave reads its A
+// fragments from there, so an input value is fetched from memory about four
+// times instead of once per tap.  Voxels are padded to CI + 8 channels
+// against LDS bank conflicts.  Same operands and order as k_conv_mfma.
+#ifndef MGCT_CONV_LDS_ROWS
+#define MGCT_CONV_LDS_ROWS 2
+#endif
+constexpr int kConvLdsRows = MGCT_CONV_LDS_ROWS;  // output rows per wave of the LDS-staged kernel
+
+template <int CI, int MODE>
+__global__ __launch_bounds__(256) void k_conv_mfma_lds(const uint16_t *__restrict__ X,
+                                                       const uint16_t *__restrict__ P,
+                                                       const float *__restrict__ bias,
+                                                       const float *__restrict__ zprev, float *__restrict__ zout,
+                                                       uint16_t *__restrict__ hout, int nout, Dims d) {
+    constexpr int NT = kConvLdsRows, YB = 4 * NT, SY = YB + 2, CP = CI + 8;
+    extern __shared__ uint16_t xs[];  // [3][SY][34][CP]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nxt = d.nx / 32, nyb = (d.ny + YB - 1) / YB;
+    const int xt = (int)(blockIdx.x % nxt), yb = (int)((blockIdx.x / nxt) % nyb), z = (int)(blockIdx.x / ((long)nxt * nyb));
+    const int x0 = xt * 32, y0 = yb * YB;
+    // stage: (zz, yy, xx) voxels of CI channels as CI / 8 chunks of 16 bytes
+    constexpr int CH = CI / 8, NV = 3 * SY * 34;
+    for (int e = threadIdx.x; e < NV * CH; e += 256) {
+        const int vox = e / CH, c8 = (e % CH) * 8;
+        const int lx = vox % 34, ly = (vox / 34) % SY, lz = vox / (34 * SY);
+        const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z + lz - 1;
+        uint4 val = {0u, 0u, 0u, 0u};
+        if (xx >= 0 && xx < d.nx && yy >= 0 && yy < d.ny && zz >= 0 && zz < d.nz)
+            val = *reinterpret_cast<const uint4 *>(X + (((long)zz * d.ny + yy) * d.nx + xx) * CI + c8);
+        *reinterpret_cast<uint4 *>(xs + vox * CP + c8) = val;
+    }
+    __syncthreads();
+    const int m = lane & 31, kh = lane >> 5;
+    const int r0 = w * NT;  // the wave's first row within the block
+    floatx16 acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = floatx16{};
+    for (int t = 0; t < 27; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + m) * CI + kc * 16 + kh * 8);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const int vox = ((1 + dz) * SY + (r0 + i + 1 + dy)) * 34 + (m + 1 + dx);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(xs + vox * CP + kc * 16 + kh * 8);
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+            }
+        }
+    }
+    const int col = m;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int y = y0 + r0 + i;
+        if (y >= d.ny) break;  // wave-uniform
+        const long v0 = ((long)z * d.ny + y) * d.nx + x0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+            const long v = v0 + row;
+            if (MODE == 0) {
+                const float zv = acc[i][r] + bias[col];
+                if (zout) zout[v * 32 + col] = zv;
+                hout[v * 32 + col] = to_bf(gelu(zv));
+            } else if (col < nout) {
+                hout[v * nout + col] = to_bf(acc[i][r] * gelu_grad(zprev[v * nout + col]));
+            }
+        }
+    }
+}
+
+#ifndef MGCT_CONV_LDS
+#define MGCT_CONV_LDS 1
+#endif
+// launch of either convolution kernel
+template <int CI, int MODE>
+static void launch_conv(const uint16_t *X, const uint16_t *P, const float *bias, const float *zprev, float *zout,
+                        uint16_t *hout, int nout, Dims d, hipStream_t s) {
+    if (MGCT_CONV_LDS) {
+        constexpr int YB = 4 * kConvLdsRows;
+        const unsigned nb = (unsigned)((long)(d.nx / 32) * ((d.ny + YB - 1) / YB) * d.nz);
+        const size_t lds = (size_t)3 * (YB + 2) * 34 * (CI + 8) * sizeof(uint16_t);
+        k_conv_mfma_lds<CI, MODE><<<nb, 256, lds, s>>>(X, P, bias, zprev, zout, hout, nout, d);
+    } else {
+        const long w = (long)(d.nx / 32) * ((d.ny + kConvRows - 1) / kConvRows) * d.nz;
+        k_conv_mfma<CI, MODE><<<(unsigned)((w + 3) / 4), 256, 0, s>>>(X, P, bias, zprev, zout, hout, nout, d);
+    }
 }
 
 // channels-last BF16 [v][C] -> channels-first [C][nz+2][ny+2][nx+2] (zero border)
@@ -475,10 +562,10 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
                        bool keep, hipStream_t s) {
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
-    const unsigned vb = blocks(n), tb = conv_blocks(nx, ny, nz);
+    const unsigned vb = blocks(n);
     k_conv1_fwd<<<vb, 256, 0, s>>>(u, S.master, keep ? B.z1 : nullptr, B.h1, d);
-    k_conv_mfma<16, 0><<<tb, 256, 0, s>>>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d);
-    k_conv_mfma<32, 0><<<tb, 256, 0, s>>>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d);
+    launch_conv<16, 0>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d, s);
+    launch_conv<32, 0>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d, s);
     k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
     return hipGetLastError();
 }
@@ -488,7 +575,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
                         hipStream_t s) {
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
-    const unsigned vb = blocks(n), tb = conv_blocks(nx, ny, nz);
+    const unsigned vb = blocks(n);
     k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
     // layer 4
     // bias gradients: blocks of 512 voxels (at most 4096 blocks), then a wave per channel
@@ -507,7 +594,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     k_wgrad_mfma_sum<<<blocks(32 * 32 * 27, 4), 256, 0, s>>>(B.partial, nch, 32, grads + kW3);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz3, 32, n, vchunk, B.partial);
     k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB3);
-    k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz3, S.p3d, nullptr, B.z2, nullptr, B.dz2, 32, d);
+    launch_conv<32, 1>(B.dz3, S.p3d, nullptr, B.z2, nullptr, B.dz2, 32, d, s);
     // layer 2
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz2, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 16), 256, 0, s>>>(B.h1, B.xT, 16, d);
@@ -515,7 +602,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     k_wgrad_mfma_sum<<<blocks(32 * 16 * 27, 4), 256, 0, s>>>(B.partial, nch, 16, grads + kW2);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz2, 32, n, vchunk, B.partial);
     k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB2);
-    k_conv_mfma<32, 1><<<tb, 256, 0, s>>>(B.dz2, S.p2d, nullptr, B.z1, nullptr, B.dz1, 16, d);
+    launch_conv<32, 1>(B.dz2, S.p2d, nullptr, B.z1, nullptr, B.dz1, 16, d, s);
     // layer 1 (input gradient not needed); dz1 holds GELU' * dh1 in BF16
     k_wgrad_valu<1><<<nwb, 256, 0, s>>>(u, nullptr, B.dz1, nullptr, B.partial, d, wrpc);
     k_sum_partials<<<blocks(448, 4), 256, 0, s>>>(B.partial, nwb, 448, grads + kW1);
