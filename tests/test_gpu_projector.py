@@ -24,9 +24,24 @@ def _ragged_geom():
     return oracle.Geom(37, 29, 70, 0.45, (0.3, -0.2, 0.1), 53, 71, views)
 
 
+def _single_view_geom(diag=False):
+    # one view (one view chunk: only the two ray-axis partial volumes of the
+    # plane-blocked transpose), grid deeper than 32; `diag` turns the view to
+    # 45 degrees so that its columns split between the x- and y-major parts
+    views = synth.trajectory(2, 2, 1.6)[:1].copy()
+    if diag:
+        c, s = np.cos(np.pi / 4), np.sin(np.pi / 4)
+        rot = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+        for k in range(4):
+            views[0, 3 * k:3 * k + 3] = rot @ views[0, 3 * k:3 * k + 3]
+    return oracle.Geom(40, 36, 44, 0.8, (0.0, 0.0, 0.0), 48, 40, views)
+
+
 CASES = {
     "c0": lambda: workload("c0"),
     "ragged": _ragged_geom,
+    "single_view": _single_view_geom,
+    "single_view_45deg": lambda: _single_view_geom(True),
     "c1_level2": lambda: workload("c1").level(2),
     "c1_level1": lambda: workload("c1").level(1),
 }
