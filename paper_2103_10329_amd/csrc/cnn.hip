@@ -467,7 +467,9 @@ __global__ void k_to_cf(const uint16_t *__restrict__ x, uint16_t *__restrict__ x
 
 // dW[t][co][ci] partial over a chunk of rows: sum_v G[co][v] X[ci][v + off_t]
 // (G channels-first [32][n], X channels-first padded [CI][nz+2][ny+2][nx+2]).
-// One wave per (tap, chunk); K = 16 voxels per MFMA along x (nx % 16 == 0).
+// One wave per (dy, dz, chunk) computes the three taps dx = -1, 0, 1: each
+// G fragment is loaded once and used for the three shifted X fragments.
+// K = 16 voxels per MFMA along x (nx % 16 == 0).
 // partial[chunk][t][co][ci] (32 x 32, ci >= CI left zero).
 template <int CI>
 __global__ __launch_bounds__(256) void k_wgrad_mfma(const uint16_t *__restrict__ G, const uint16_t *__restrict__ X,
@@ -475,34 +477,44 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const uint16_t *__restrict__
                                                     int nchunks) {
     const int lane = threadIdx.x & 63;
     const long wid = blockIdx.x * 4L + (threadIdx.x >> 6);
-    if (wid >= 27L * nchunks) return;  // whole wave; no barrier below
-    const int t = (int)(wid % 27), chunk = (int)(wid / 27);
+    if (wid >= 9L * nchunks) return;  // whole wave; no barrier below
+    const int tg = (int)(wid % 9), chunk = (int)(wid / 9);  // tg = 3 (dz + 1) + (dy + 1)
     const int m = lane & 31, kh = lane >> 5;
-    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int dy = tg % 3 - 1, dz = tg / 3 - 1;
     const long n = (long)d.nx * d.ny * d.nz;
     const long PX = d.nx + 2, PY = d.ny + 2, PZ = d.nz + 2;
     const int nrows = d.ny * d.nz;
     const int r0 = chunk * rows_per_chunk, r1 = min(nrows, r0 + rows_per_chunk);
-    floatx16 acc = {};
+    floatx16 acc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = floatx16{};
     for (int row = r0; row < r1; ++row) {
         const int y = row % d.ny, z = row / d.ny;
         const long vrow = (long)row * d.nx;
-        const long prow = (((long)m * PZ + z + 1 + dz) * PY + y + 1 + dy) * PX + 1 + dx;
+        // X row (ci = m) at x = -1 (padded index 0)
+        const long prow = (((long)m * PZ + z + 1 + dz) * PY + y + 1 + dy) * PX;
         for (int x0 = 0; x0 < d.nx; x0 += 16) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(G + (long)m * n + vrow + x0 + kh * 8);
-            bf16x8 b = {};
-            if (m < CI) {
-                const uint16_t *src = X + prow + x0 + kh * 8;
-                __builtin_memcpy(&b, __builtin_assume_aligned(src, 2), 16);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {  // dx = k - 1
+                bf16x8 b = {};
+                if (m < CI) {
+                    const uint16_t *src = X + prow + k + x0 + kh * 8;
+                    __builtin_memcpy(&b, __builtin_assume_aligned(src, 2), 16);
+                }
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k], 0, 0, 0);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
     }
-    float *dst = partial + ((long)chunk * 27 + t) * 1024;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);  // co
-        dst[row * 32 + m] = acc[r];                        // ci = m
+    for (int k = 0; k < 3; ++k) {
+        const int t = 9 * (dz + 1) + 3 * (dy + 1) + k;  // tap index: t % 3 = dx + 1
+        float *dst = partial + ((long)chunk * 27 + t) * 1024;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * kh + (r & 3);  // co
+            dst[row * 32 + m] = acc[k][r];                     // ci = m
+        }
     }
 }
 
@@ -590,7 +602,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     const int rpc = 16, nch = (rows + rpc - 1) / rpc;
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz3, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 32), 256, 0, s>>>(B.h2, B.xT, 32, d);
-    k_wgrad_mfma<32><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
+    k_wgrad_mfma<32><<<(unsigned)((9L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
     k_wgrad_mfma_sum<<<blocks(32 * 32 * 27, 4), 256, 0, s>>>(B.partial, nch, 32, grads + kW3);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz3, 32, n, vchunk, B.partial);
     k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB3);
@@ -598,7 +610,7 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     // layer 2
     k_to_cf<<<blocks(n * 32), 256, 0, s>>>(B.dz2, B.gT, 32, n);
     k_to_cf_padded<<<blocks(n * 16), 256, 0, s>>>(B.h1, B.xT, 16, d);
-    k_wgrad_mfma<16><<<(unsigned)((27L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
+    k_wgrad_mfma<16><<<(unsigned)((9L * nch + 3) / 4), 256, 0, s>>>(B.gT, B.xT, B.partial, d, rpc, nch);
     k_wgrad_mfma_sum<<<blocks(32 * 16 * 27, 4), 256, 0, s>>>(B.partial, nch, 16, grads + kW2);
     k_bias_grad<<<nvb, 256, 0, s>>>(B.dz2, 32, n, vchunk, B.partial);
     k_sum_partials<<<blocks(32, 4), 256, 0, s>>>(B.partial, nvb, 32, grads + kB2);
