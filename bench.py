@@ -51,8 +51,8 @@ def main():
                     help="only run the 640x640x2304 / 3600 x 760^2 workload (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (views would shard across "
-              "GPUs with one sum-exchange of A^T per step; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the views would shard across "
+              "GPUs, with one sum-exchange of the A^T partial volumes per step).", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
