@@ -276,11 +276,11 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
         // A^T reads, and the partial sums of its squared norm
         WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
         WS(pt, char, lvl(sd == MGCT_F32 ? "pt" : "pt16", g), L.rays() * es, false);
-        const size_t nblk = project_sep_blocks(L, L.nviews);
+        const int vtd = c.vt_dtype;
+        const size_t nblk = project_sep_blocks(L, L.nviews, vtd);
         WS(pp, double, "proj_partials", nblk * 8, false);
         WS(pp2, double, "proj_partials2", 256 * 8, false);
         WS(nrm, double, "red_scratch", 8, false);
-        const int vtd = c.vt_dtype;
         void *vtx, *vty;
         MGCHK(pair_copies(c, L, g, vol, MGCT_F32, vtd, &vtx, &vty, s));
         {
@@ -316,7 +316,7 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
 
 int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out, hipStream_t s) {
     if (L.separable) {
-        const size_t nblk = project_sep_blocks(L, L.nviews);
+        const size_t nblk = project_sep_blocks(L, L.nviews, MGCT_F32);
         WS(pp, double, "proj_partials", nblk * 8, false);
         WS(pp2, double, "proj_partials2", 256 * 8, false);
         void *vtx, *vty;

@@ -364,13 +364,15 @@ template <> __device__ __forceinline__ float round_as<_Float16>(float x) { retur
 
 // WIDE: the pair copies exceed 4 GiB, so sample addresses are formed in 64 bits.
 #ifndef MGCT_PROJ_PW2_MIN
-#define MGCT_PROJ_PW2_MIN 512  // grid width from which blocks hold 2 columns instead of 4
+#define MGCT_PROJ_PW2_MIN 512  // grid width from which blocks over BF16 copies hold 2 columns instead of 4
 #endif
 // Waves (adjacent detector columns) per block of the separable projector,
-// chosen by measurement: 4 on grids up to 256 wide (2 was 4-7 % slower at
-// 128^3 and 256^3), 2 from 512 wide (4 was 1 % slower at 512^3 in FP32 and
-// 8 % with BF16 copies).
-static int proj_pw(const Level &L) { return std::max(L.nx, L.ny) >= MGCT_PROJ_PW2_MIN ? 2 : 4; }
+// chosen by measurement: 2 for BF16 copies of grids 512 or more wide (4 was
+// 8 % slower at 512^3), 4 otherwise (2 was 4-7 % slower at 128^3 and 256^3,
+// about even at 512^3 in FP32 and 6 % slower on a 640 x 640 x 2304 FP32 grid).
+static int proj_pw(const Level &L, int vt_dtype) {
+    return vt_dtype == MGCT_BF16 && std::max(L.nx, L.ny) >= MGCT_PROJ_PW2_MIN ? 2 : 4;
+}
 
 template <typename VT, typename PT, int MODE, typename TB, bool WIDE>
 __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
@@ -488,15 +490,15 @@ hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, vo
                                    nullptr, nullptr, L, view0, view_step, nviews_sub, s);
 }
 
-size_t project_sep_blocks(const Level &L, int nviews_sub) {
-    const int pw = proj_pw(L);
+size_t project_sep_blocks(const Level &L, int nviews_sub, int vt_dtype) {
+    const int pw = proj_pw(L, vt_dtype);
     return (size_t)((L.nu + pw - 1) / pw) * ((L.nv + 63) / 64) * nviews_sub;
 }
 
 hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtype, int mode, void *out, void *out2,
                                    int out_dtype, const void *y, int y_dtype, const float *pi, double *partials,
                                    const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s) {
-    const int pw = proj_pw(L);
+    const int pw = proj_pw(L, vt_dtype);
     dim3 grid((L.nu + pw - 1) / pw, (L.nv + 63) / 64, nviews_sub);
     const int tab_len = std::max(L.nx, L.ny);
     const size_t lds = pw * (size_t)tab_len * sizeof(PlaneEntry);

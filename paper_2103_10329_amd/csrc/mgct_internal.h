@@ -155,7 +155,7 @@ hipError_t launch_project_sep(const void *vtx, const void *vty, int vt_dtype, vo
 hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtype, int mode, void *out, void *out2,
                                    int out_dtype, const void *y, int y_dtype, const float *pi, double *partials,
                                    const Level &L, int view0, int view_step, int nviews_sub, hipStream_t s);
-size_t project_sep_blocks(const Level &L, int nviews_sub);
+size_t project_sep_blocks(const Level &L, int nviews_sub, int vt_dtype);  // vt_dtype: the pair copies' type
 // OS-EMTR update that also refreshes the separable projector's pair copies
 hipError_t launch_emtr_update_pairs(float *vol, const float *num, const float *den, const unsigned *maxbits,
                                     void *vtx, void *vty, int vt_dtype, const Level &L, hipStream_t s);
