@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "2c68459871cf78b2878c3e3a5bc0eb31e4678215d3d2cc0025f7bf6e7c9e69b5", "bytes_per_launch": 382573541},
+    "k_backproject_pl": {"source_sha256": "dfa1c32a5108f20682656e19c7fb0eda5c1806fbbd1296cfa6e9fa9cf3730da2", "bytes_per_launch": 380356885},
 }
 
 
