@@ -283,7 +283,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "dfa1c32a5108f20682656e19c7fb0eda5c1806fbbd1296cfa6e9fa9cf3730da2", "bytes_per_launch": 380356885},
+    "k_backproject_pl": {"source_sha256": "bcbbda3ef936e43034855d4345d0c2370d90500b6d86f7d3039bbee4acf51345", "bytes_per_launch": 376537345},
 }
 
 

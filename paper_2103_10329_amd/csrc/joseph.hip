@@ -1104,10 +1104,19 @@ constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 constexpr int kPlRows = MGCT_BP_PLROWS;
 constexpr int kPlSlots = kPlRows + 2;
 
+// What the column loop needs of one column at the wave's plane (prepared
+// by one lane, read back by the whole wave from LDS).
+struct __align__(16) PlCol {
+    double zc, tz, rtz;  // z of detector row 0, row spacing along z, 1 / spacing
+    float whi;           // in-plane hat weight of the upper row
+    int rl;              // block row of the lower tap (-1 .. kPlRows-1)
+};
+
 template <int PART, int KZ, int NP, typename PT, bool ZS>
 __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
                                               const PT *base1, int P, int r0, int nu, int nv,
-                                              const double (&kd)[KZ], double zw0, double zw1, float *slot) {
+                                              const double (&kd)[KZ], double zw0, double zw1, float *slot,
+                                              PlCol *rec) {
     // distance of the plane from the source along the major axis
     const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
     if (ZS) {
@@ -1127,55 +1136,73 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
     int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
     alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
     ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
-    // The next column's descriptor is loaded while this one is worked on, and
-    // every field is used before the one skip test, so that its scalar loads
-    // go out together; the two rows' slots are read before the detector
-    // window so that the LDS round trip overlaps the window's loads.
-    if (alo > ahi) return;  // no column reaches the block (also keeps cv[alo] in range)
-    ColD Cn = cv[alo];
-    for (int a = alo; a <= ahi; ++a) {
-        const ColD C = Cn;
-        Cn = cv[min(a + 1, ahi)];
-        const double tau = dm * (PART == 0 ? C.rdx : C.rdy);  // ray parameter at the plane
-        const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
-        const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
-        const int rl = __builtin_amdgcn_readfirstlane((int)fl - r0);  // block row of the lower tap
-        const double tz = tau * S.vz;                                 // row spacing along z at the plane
-        const double zc = fma(tau, S.dz0, S.sz);                      // z of row 0 at the plane
-        const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;      // 1 / tz
-        if (C.axis != PART || !(tau >= 0.0 && tau <= 1.0) || rl < -1 || rl >= kPlRows) continue;
-        if (ZS) {
-            const double zend = fma(tz, (double)(nv - 1), zc);
-            if (fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0) continue;
+    const int lane = threadIdx.x & 63;
+    // The candidate columns go in batches of 64: lane l works out column
+    // a0 + l at this plane (ray parameter, in-plane position and rows, z
+    // mapping of the detector rows) and whether it reaches the block, and
+    // keeps the result in the wave's LDS records; the wave then walks the
+    // columns that do (the ballot's set bits, in increasing order), reading
+    // each record back with one broadcast load.  The per-column set-up costs
+    // one lane instead of the whole wave.  LDS operations of a wave complete
+    // in order, so a record written by one lane is seen by the next read,
+    // and the next batch's writes follow this batch's reads.
+    for (int a0 = alo; a0 <= ahi; a0 += 64) {
+        const int a = a0 + lane;
+        bool ok = false;
+        if (a <= ahi) {
+            const ColD &C = cv[a];
+            const double tau = dm * (PART == 0 ? C.rdx : C.rdy);                 // ray parameter at the plane
+            const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
+            const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
+            PlCol R;
+            R.rl = (int)fl - r0;
+            R.tz = tau * S.vz;
+            R.zc = fma(tau, S.dz0, S.sz);
+            R.rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;
+            R.whi = (float)(pos - fl);
+            ok = C.axis == PART && tau >= 0.0 && tau <= 1.0 && R.rl >= -1 && R.rl < kPlRows;
+            if (ZS && ok) {
+                const double zend = fma(R.tz, (double)(nv - 1), R.zc);
+                ok = !(fmax(R.zc, zend) <= zw0 - 1.0 || fmin(R.zc, zend) >= zw1 + 1.0);
+            }
+            if (ok) rec[lane] = R;
         }
-        float *sl = slot + (rl + 1) * KZ * 64;
-        float old[NP][2][KZ];
+        unsigned long long m = __ballot(ok);
+        __builtin_amdgcn_wave_barrier();
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const PlCol R = rec[l];
+            const long ac = a0 + l;
+            float *sl = slot + (R.rl + 1) * KZ * 64;
+            float old[NP][2][KZ];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int q = 0; q < KZ; ++q) {
-                old[p][0][q] = sl[(p * kPlSlots * KZ + q) * 64];
-                old[p][1][q] = sl[((p * kPlSlots + 1) * KZ + q) * 64];
-            }
-        const float whi = (float)(pos - fl), wlo = 1.f - whi;
-        const double hw = fabs(rtz);
-        const PT *col0 = base0 + (long)a * nv;
-        const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
-        float sums[NP][KZ];
-        bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
+                for (int q = 0; q < KZ; ++q) {
+                    old[p][0][q] = sl[(p * kPlSlots * KZ + q) * 64];
+                    old[p][1][q] = sl[((p * kPlSlots + 1) * KZ + q) * 64];
+                }
+            const float whi = R.whi, wlo = 1.f - whi;
+            const PT *col0 = base0 + ac * nv;
+            const PT *col1 = (NP > 1) ? base1 + ac * nv : nullptr;
+            float sums[NP][KZ];
+            bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.zc, R.tz, R.rtz, fabs(R.rtz), kd, sums);
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int q = 0; q < KZ; ++q) {
-                sl[(p * kPlSlots * KZ + q) * 64] = fmaf(wlo, sums[p][q], old[p][0][q]);
-                sl[((p * kPlSlots + 1) * KZ + q) * 64] = fmaf(whi, sums[p][q], old[p][1][q]);
-            }
+                for (int q = 0; q < KZ; ++q) {
+                    sl[(p * kPlSlots * KZ + q) * 64] = fmaf(wlo, sums[p][q], old[p][0][q]);
+                    sl[((p * kPlSlots + 1) * KZ + q) * 64] = fmaf(whi, sums[p][q], old[p][1][q]);
+                }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 template <int PART, int KZ, int NP, typename PT, bool ZS>
 __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
-                                              float *__restrict__ part, long np_stride, float *slot,
+                                              float *__restrict__ part, long np_stride, float *slot, PlCol *rec,
                                               const SepView *__restrict__ sep, const ColD *__restrict__ cols,
                                               int nx, int ny, int nz, int nu, int nv, int nviews_sub, int view0,
                                               int view_step, int per_chunk, int nchunks) {
@@ -1210,7 +1237,8 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
         if (!(S.flags & (PART == 0 ? 1 : 2))) continue;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, kd, zw0, zw1, slot);
+        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, kd, zw0, zw1, slot,
+                                            rec);
         // the view's sums into FP64, slots cleared (spare rows too)
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -1260,12 +1288,14 @@ __global__ __launch_bounds__(256, NP == 1 ? MGCT_BP_PL_MINW : 1) void k_backproj
                                                         int nv, int nviews_sub, int view0, int view_step,
                                                         int per_chunk, int nchunks) {
     __shared__ float lds[4 * NP * kPlSlots * KZ * 64];
+    __shared__ PlCol recs[4][64];
     float *slot = lds + (threadIdx.x >> 6) * (NP * kPlSlots * KZ * 64) + (threadIdx.x & 63);
+    PlCol *rec = recs[threadIdx.x >> 6];
     if (blockIdx.z == 0)
-        bp_plane_wave<0, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
+        bp_plane_wave<0, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, rec, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
                                          view0, view_step, per_chunk, nchunks);
     else
-        bp_plane_wave<1, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
+        bp_plane_wave<1, KZ, NP, PT, ZS>(pt0, pt1, part, np_stride, slot, rec, sep, cols, nx, ny, nz, nu, nv, nviews_sub,
                                          view0, view_step, per_chunk, nchunks);
 }
 
