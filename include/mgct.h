@@ -347,6 +347,15 @@ typedef enum {
 
 int mgct_kernel_timing(void *ctx, int enable);
 int mgct_kernel_time(void *ctx, int op, int level, double *total_ms, int *launches);
+/*
+ * Narrows what is recorded while timing is enabled: a launch of operation op
+ * on grid g is bracketed only if bit op of op_mask and bit g of level_mask are
+ * set.  A new context records everything (both masks ~0u).  Fewer records keep
+ * the events' own cost (each is a command on the stream) out of a timed
+ * region.  The masks stay until changed; existing records are kept.
+ * MGCT_ERR_INVALID_ARG for a null ctx.
+ */
+int mgct_kernel_timing_select(void *ctx, unsigned op_mask, unsigned level_mask);
 
 #ifdef __cplusplus
 }

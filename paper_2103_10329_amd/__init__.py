@@ -101,6 +101,7 @@ SIGNATURES = {
     "mgct_synth_voxelize": (_ci, [_vp, _dp, _ci, _dp, _ci, _ci, _vp, _vp]),
     "mgct_kernel_timing": (_ci, [_vp, _ci]),
     "mgct_kernel_time": (_ci, [_vp, _ci, _ci, _dp, ctypes.POINTER(_ci)]),
+    "mgct_kernel_timing_select": (_ci, [_vp, ctypes.c_uint, ctypes.c_uint]),
 }
 
 MGCT_OP_PROJECT, MGCT_OP_BACKPROJECT, MGCT_OP_PRECONDITION = 0, 1, 2
@@ -417,7 +418,13 @@ class Context:
                                   ctypes.byref(loss) if want_loss else None, _stream()), "mgct_cnn_train_step")
         return loss.value if want_loss else None
 
-    def kernel_timing(self, enable: bool):
+    def kernel_timing(self, enable: bool, ops=None, levels=None):
+        """Enable (clearing the records) or disable kernel timing.  `ops` and
+        `levels` (iterables of operation codes and grid indices, default all)
+        choose which launches are recorded from now on."""
+        om = 0xFFFFFFFF if ops is None else sum(1 << int(o) for o in ops)
+        lm = 0xFFFFFFFF if levels is None else sum(1 << int(g) for g in levels)
+        check(mgct_kernel_timing_select(self.handle, om, lm), "mgct_kernel_timing_select")  # noqa: F821
         check(mgct_kernel_timing(self.handle, 1 if enable else 0), "mgct_kernel_timing")  # noqa: F821
 
     def kernel_time(self, op: int, level: int = -1):

@@ -41,7 +41,8 @@ static hipEvent_t take_event(Ctx &c) {
 }
 
 KernelTimer::KernelTimer(Ctx &c_, int op_, int level_, hipStream_t s_) : c(c_), op(op_), level(level_), s(s_) {
-    if (!c.timing) return;
+    if (!c.timing || op < 0 || op >= 32 || level < 0 || level >= 32) return;
+    if (!((c.timing_ops >> op) & 1u) || !((c.timing_levels >> level) & 1u)) return;
     e0 = take_event(c);
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, s);
@@ -726,6 +727,14 @@ int mgct_kernel_timing(void *ctx, int enable) {
         release_events(c);
     }
     c.timing = enable != 0;
+    return MGCT_OK;
+}
+
+int mgct_kernel_timing_select(void *ctx, unsigned op_mask, unsigned level_mask) {
+    if (!ctx) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    c.timing_ops = op_mask;
+    c.timing_levels = level_mask;
     return MGCT_OK;
 }
 

@@ -116,6 +116,7 @@ struct Ctx {
     int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
     CnnState cnn;
     bool timing = false;
+    unsigned timing_ops = ~0u, timing_levels = ~0u;  // which (op, grid) pairs are recorded
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
 };
