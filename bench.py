@@ -300,7 +300,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "bcbbda3ef936e43034855d4345d0c2370d90500b6d86f7d3039bbee4acf51345", "bytes_per_launch": 376537345},
+    "k_backproject_pl": {"source_sha256": "fb6d257886743de0c9b424f33aea09f76f996ac5a0c037919b9a4f59fe563145", "bytes_per_launch": 376659201},
 }
 
 

@@ -760,6 +760,13 @@ __device__ __forceinline__ float column_coord(const SepView &S, float px, float 
     return (S.an0 + S.an1 * px + S.an2 * py) * __builtin_amdgcn_rcpf(S.ad0 + S.ad1 * px + S.ad2 * py);
 }
 
+// What the column loop of bp_part needs of one column at a half-wave's
+// plane (prepared by one lane, read back from LDS).
+struct __align__(16) SepCol {
+    double zc, tz, rtz;  // z of detector row 0, row spacing along z, 1 / spacing
+    double pos;          // in-plane position where the column's rays cross the plane
+};
+
 // One wave handles 64*KZ voxels of one (x, y) column, lane + 64*q for q < KZ.
 // For each view and each candidate detector column a (wave-uniform), the
 // rays of column a meet the voxel's plane on a line along z where row b sits
@@ -769,10 +776,19 @@ __device__ __forceinline__ float column_coord(const SepView &S, float px, float 
 // PART 1: y-major rays on plane y = j (offset along x).
 // HALF: lanes 0-31 and 32-63 hold two different j (the candidate column
 // range is the union of both halves' ranges).
+// The candidate columns go in batches of 32: lane c of each half works out
+// column a0 + c at its half's plane (ray parameter, in-plane position, z
+// mapping of the detector rows) and whether it reaches the half's row, and
+// keeps it in the wave's LDS records (rec[64]: half h at 32 h); the wave then
+// walks the columns that reach either half, in increasing order, each half
+// reading its own record.  One lane per column and half does the set-up and
+// the column descriptors arrive in one round of loads.  LDS operations of a
+// wave complete in order, so the records written are seen by the reads that
+// follow, and the next batch's writes follow this batch's reads.
 template <int PART, int KZ, int NP, typename PT, bool HALF>
 __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict__ cv,
                                         const PT *base0, const PT *base1, int i, int j, int nu, int nv,
-                                        const double (&kd)[KZ], float (&pv)[NP][KZ]) {
+                                        const double (&kd)[KZ], float (&pv)[NP][KZ], SepCol *rec) {
     const float fi = (float)i, fj = (float)j;
     float c1, c2;
     if (PART == 0) {
@@ -797,26 +813,44 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
     // distance of the plane from the source along the major axis
     const double dm = (PART == 0) ? (double)i - S.sx : (double)j - S.sy;
     const double inv_dm = 1.0 / dm;
-    for (int a = alo; a <= ahi; ++a) {
-        const ColD C = cv[a];
-        if (C.axis != PART) continue;
-        const double tau = dm * ((PART == 0) ? C.rdx : C.rdy);  // ray parameter at the plane
-        const double off = (PART == 0) ? fma(tau, C.dy, S.sy) - (double)j : fma(tau, C.dx, S.sx) - (double)i;
-        const float wp = 1.f - (float)fabs(off);
-        if (!(wp > 0.f) || tau < 0.0 || tau > 1.0) continue;
-        const double tz = tau * S.vz;                           // row spacing along z at the plane
-        const double zc = fma(tau, S.dz0, S.sz);                // z of row 0 at the plane
-        const double rtz = ((PART == 0) ? C.dxv : C.dyv) * inv_dm;  // 1 / tz
-        const double hw = fabs(rtz);
-        const PT *col0 = base0 + (long)a * nv;
-        const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
-        float sums[NP][KZ];
-        bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
-#pragma unroll
-        for (int q = 0; q < KZ; ++q) {
-            pv[0][q] = fmaf(wp, sums[0][q], pv[0][q]);
-            if (NP > 1) pv[NP - 1][q] = fmaf(wp, sums[NP - 1][q], pv[NP - 1][q]);
+    const double own = (PART == 0) ? (double)j : (double)i;  // the lane's row on the plane
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    for (int a0 = alo; a0 <= ahi; a0 += 32) {
+        const int a = a0 + (lane & 31);
+        bool ok = false;
+        if (a <= ahi) {
+            const ColD &C = cv[a];
+            const double tau = dm * ((PART == 0) ? C.rdx : C.rdy);  // ray parameter at the plane
+            SepCol R;
+            R.pos = (PART == 0) ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);
+            R.tz = tau * S.vz;                                   // row spacing along z at the plane
+            R.zc = fma(tau, S.dz0, S.sz);                        // z of row 0 at the plane
+            R.rtz = ((PART == 0) ? C.dxv : C.dyv) * inv_dm;      // 1 / tz
+            ok = C.axis == PART && 1.f - (float)fabs(R.pos - own) > 0.f && tau >= 0.0 && tau <= 1.0;
+            if (ok) rec[lane] = R;
         }
+        const unsigned long long m = __ballot(ok);
+        unsigned cm = (unsigned)m | (unsigned)(m >> 32);
+        __builtin_amdgcn_wave_barrier();
+        while (cm) {
+            const int c = __builtin_ctz(cm);
+            cm &= cm - 1;
+            if ((m >> (32 * h + c)) & 1ull) {
+                const SepCol R = rec[32 * h + c];
+                const float wp = 1.f - (float)fabs(R.pos - own);
+                const long ac = a0 + c;
+                const PT *col0 = base0 + ac * nv;
+                const PT *col1 = (NP > 1) ? base1 + ac * nv : nullptr;
+                float sums[NP][KZ];
+                bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.zc, R.tz, R.rtz, fabs(R.rtz), kd, sums);
+#pragma unroll
+                for (int q = 0; q < KZ; ++q) {
+                    pv[0][q] = fmaf(wp, sums[0][q], pv[0][q]);
+                    if (NP > 1) pv[NP - 1][q] = fmaf(wp, sums[NP - 1][q], pv[NP - 1][q]);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -991,6 +1025,8 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
                                                          const uint8_t *__restrict__ axis, int nx, int ny, int nz,
                                                          int nu, int nv, int nviews_sub, int view0, int view_step,
                                                          int per_chunk) {
+    __shared__ SepCol recs[4][64];
+    SepCol *rec = recs[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     // HALF (nz <= 32, KZ = 1): a wave covers z = lane % 32 of two rows
@@ -1025,8 +1061,8 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
         const ColD *cv = cols + (long)v * nu;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        if (S.flags & 1) bp_part<0, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
-        if (S.flags & 2) bp_part<1, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv);
+        if (S.flags & 1) bp_part<0, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv, rec);
+        if (S.flags & 2) bp_part<1, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv, rec);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
