@@ -427,9 +427,58 @@ def cpu_baseline(d, views, alphas, lam, bil):
     oracle.multigrid(g, np.zeros(g.vol_shape), d["b"], cfg.levels, 1, f, alphas, lam=lam, bilateral_on=True,
                      sigma_s=bil[0], sigma_r=bil[1])
     t = time.perf_counter() - t0
-    return {"value": n ** 3 * cfg.n_views / t / 1e9, "unit": "Gvoxel·views/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": t,
-            "sample": "one full iteration of Algorithm 1 (3 grids, same 128^3 x 360-view data) by the FP64 oracle"}
+    out = {"value": n ** 3 * cfg.n_views / t / 1e9, "unit": "Gvoxel·views/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "seconds": t,
+           "sample": "one full iteration of Algorithm 1 (3 grids, same 128^3 x 360-view data) by the FP64 oracle",
+           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    out["one_thread"] = _oracle_one_thread(views[::8], n, cfg.h, cfg.nu, cfg.nv)
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# One A and one A^T of the FP64 oracle on a view subset, on one thread (the
+# oracle reads its thread count at start-up, so this runs in a child process).
+_ONE_THREAD = """
+import sys, time
+import numpy as np
+import oracle
+views = np.load(sys.argv[1])
+n, h, nu, nv = int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])
+g = oracle.Geom(n, n, n, h, (0, 0, 0), nu, nv, views)
+x = np.random.default_rng(0).random(g.vol_shape)
+t = time.perf_counter()
+oracle.backproject(g, oracle.project(g, x))
+print(oracle.num_threads(), time.perf_counter() - t)
+"""
+
+
+def _oracle_one_thread(views, n, h, nu, nv):
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        vf = os.path.join(tmp, "views.npy")
+        np.save(vf, np.ascontiguousarray(views))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        try:
+            r = subprocess.run([sys.executable, "-c", _ONE_THREAD, vf, str(n), str(h), str(nu), str(nv)],
+                               env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+            threads, t = r.stdout.split()
+        except (subprocess.SubprocessError, ValueError) as e:
+            return {"error": str(e)[:200]}
+    t = float(t)
+    return {"value": n ** 3 * len(views) / t / 1e9, "unit": "Gvoxel·views/s", "threads": int(threads),
+            "seconds": t, "sample": "one A and one A^T on %d of the %d views (every 8th), FP64 oracle" % (
+                len(views), 8 * len(views))}
 
 
 if __name__ == "__main__":
