@@ -149,6 +149,12 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
     a_at = n ** 3 * V / ((tA + tB) * 1e-3) / 1e9
+    # combined A + A^T rate on every grid (grid g: (n / 2^g)^3 voxels, same views)
+    a_at_grid = {}
+    for g in range(levels):
+        ka, kb = kt.get("project@%d" % g), kt.get("backproject@%d" % g)
+        if ka and kb:
+            a_at_grid[str(g)] = (n >> g) ** 3 * V / ((ka["ms_avg"] + kb["ms_avg"]) * 1e-3) / 1e9
 
     out = {
         "metric": "A+A\u1d40 Gvoxel\u00b7views/s (% HBM roofline); time-to-residual vs plain SIRT",
@@ -162,6 +168,7 @@ def main():
         "a_plus_at_kernels_gvox_views_s": a_at,
         "a_plus_at_hbm_frac": 2 * bytes_per_launch / ((tA + tB) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms": kt,
+        "a_plus_at_gvox_views_s_by_grid": a_at_grid,
         "step_size_estimate_s": t_alpha,
     }
 
