@@ -307,7 +307,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # launch; valid only for the kernel source it was measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "fb6d257886743de0c9b424f33aea09f76f996ac5a0c037919b9a4f59fe563145", "bytes_per_launch": 376659201},
+    "k_backproject_pl": {"source_sha256": "cee4298d85e4e50e86329a340f9f5029e32d3fab96d9f2748a11c77766ff8334", "bytes_per_launch": 376342772},
 }
 
 
