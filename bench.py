@@ -145,8 +145,12 @@ def main():
     t_dom = kt[dom]["ms_avg"] * 1e-3
     achieved = bytes_per_launch / t_dom / 1e9
     kname = "k_backproject_pl" if dom.startswith("back") else "k_project_sep"
+    counters = measured_counters(kname)
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": counters["bytes_per_launch"] if counters else None,
+                "valu_issue": counters["valu_issue"] if counters else None,
+                "l2_hit": counters["l2_hit"] if counters else None,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
     a_at = n ** 3 * V / ((tA + tB) * 1e-3) / 1e9
     # combined A + A^T rate on every grid (grid g: (n / 2^g)^3 voxels, same views)
@@ -304,14 +308,19 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes, scaled by the same counters on a plain copy of known size, per
-# launch; valid only for the kernel source it was measured on.
+# launch, with its VALU issue fraction (SQ_INSTS_VALU per CU cycle) and L2 hit
+# rate from the counter pass; valid only for the kernel source it was
+# measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "cee4298d85e4e50e86329a340f9f5029e32d3fab96d9f2748a11c77766ff8334", "bytes_per_launch": 376342772},
+    "k_backproject_pl": {"source_sha256": "cee4298d85e4e50e86329a340f9f5029e32d3fab96d9f2748a11c77766ff8334",
+                         "bytes_per_launch": 376342772, "valu_issue": 0.80, "l2_hit": 0.959},
 }
 
 
-def measured_traffic(kernel):
+def measured_counters(kernel):
+    """The committed counter figures for `kernel`, or None when the source has
+    changed since they were taken."""
     import hashlib
     t = TRAFFIC.get(kernel)
     if not t:
@@ -320,7 +329,7 @@ def measured_traffic(kernel):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
-    return t["bytes_per_launch"]
+    return t
 
 
 def paper_shaped():
