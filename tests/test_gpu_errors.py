@@ -39,6 +39,9 @@ def test_calls_before_geometry_and_bad_arguments():
     assert mg.mgct_project(ctx.handle, 9, _ptr(vol), mg.MGCT_F32, _ptr(st), mg.MGCT_F32, None) != mg.MGCT_OK
     assert mg.mgct_landweber_step(ctx.handle, 0, _ptr(vol), _ptr(st), mg.MGCT_F32, float("nan"), None, None,
                                   None) == mg.MGCT_ERR_INVALID_ARG
+    # timing controls: a null context is rejected
+    assert mg.mgct_kernel_timing_select(None, 1, 1) == mg.MGCT_ERR_INVALID_ARG
+    assert mg.mgct_kernel_timing(None, 1) == mg.MGCT_ERR_INVALID_ARG
     # the context still works
     ctx.project(vol, out=st)
     torch.cuda.synchronize()
