@@ -694,34 +694,73 @@ template <int W> __device__ __forceinline__ void load_win(const _Float16 *p, uin
     for (int t = 0; t < W; ++t) v[t] = (float)h[t];
 }
 
-// One column's detector-row sums for the wave's KZ voxels: for voxel
-// z = kd[q], rows bs .. bs+W-1 with bs the first row above z - 1 (clamped to
-// the detector), hat weights 1 - |z_row - z| in FP32 from an FP64 anchor.
 // The hat max(0, 1 - |d|).  As 1 - |d| never exceeds 1 it equals the clamp
 // of 1 - |d| to [0, 1], which the compiler folds into the subtraction's
 // output clamp: one instruction instead of two (same value).
 __device__ __forceinline__ float hat(float d) { return fminf(fmaxf(1.f - fabsf(d), 0.f), 1.f); }
 
+// One detector column at a voxel plane, as the z windows of the transpose
+// use it.  Detector row b sits at z = zc + tz b on the plane (voxel units);
+// the voxel z = zw0 + u (u = 0, 1, ... over the wave's z values) sees the
+// row at b*(u) = (zw0 + u - zc) / tz.  With R0 the row nearest b*(0), the
+// window start b*(u) - |1/tz| is R0 + bq + u rtz and the hat argument of row
+// R0 + dl is tz dl + C - u, C = zc + tz R0 - zw0 (|C| <= |tz| / 2).  These
+// are formed in FP64 once per column; per voxel everything is FP32 (FP64
+// instructions issue at half the FP32 rate here): the products tzh dl are
+// exact inside the FMA, tz = tzh + tzl carries 48 bits, and the argument of
+// every row that can have weight errs by about 1e-7.  The window start only
+// moves a window edge, where the row it drops has a weight of order 1e-5 tz
+// at most and the row it adds has weight 0.
+struct WinCol {
+    float R0;        // reference row (an integer, |R0| <= 2^20)
+    float bq;        // window start of u = 0 relative to R0
+    float C;         // z of row R0 relative to zw0
+    float tzh, tzl;  // row spacing along z, split in two FP32 parts
+    float rtz;       // 1 / tz (|rtz| is the half-width of the window in rows)
+};
+
+__device__ __forceinline__ WinCol win_col(double zc, double tz, double rtz, double zw0) {
+    const double B = (zw0 - zc) * rtz;  // row position of z = zw0
+    const double R0 = fmin(fmax(rint(B), -1048576.0), 1048576.0);
+    WinCol w;
+    w.R0 = (float)R0;
+    w.bq = (float)((B - R0) - fabs(rtz));
+    w.C = (float)fma(tz, R0, zc - zw0);
+    w.tzh = (float)tz;
+    w.tzl = (float)(tz - (double)w.tzh);
+    w.rtz = (float)rtz;
+    return w;
+}
+
+// First row of a W-row window for the voxel at u (clamped so that the window
+// stays on the detector: R0 + dl in [0, nv - W]) and the hat argument of that
+// row.
+__device__ __forceinline__ void win_start(const WinCol &w, float u, float hi, float &dl, float &d0) {
+    dl = __builtin_amdgcn_fmed3f(ceilf(fmaf(u, w.rtz, w.bq)), -w.R0, hi);
+    d0 = fmaf(w.tzl, dl, fmaf(w.tzh, dl, -u) + w.C);
+}
+
+// One column's detector-row sums for the wave's KZ voxels (z = zw0 + u[q]):
+// rows R0 + dl .. R0 + dl + W-1, hat weights 1 - |z_row - z|.
 template <int W, int KZ, int NP, typename PT>
-__device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv, double zc, double tz, double rtz,
-                                          double hw, const double (&kd)[KZ], float (&s)[NP][KZ]) {
-    const float tzf = (float)tz;
+__device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv, const WinCol &w,
+                                          const float (&u)[KZ], float (&s)[NP][KZ]) {
+    const float hi = (float)(nv - W) - w.R0;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
-        const double zk = zc - kd[q];
-        int bs = (int)ceil(-zk * rtz - hw);
-        bs = max(0, min(bs, nv - W));
-        const float d0 = (float)fma(tz, (double)bs, zk);
+        float dl, d0;
+        win_start(w, u[q], hi, dl, d0);
+        const int bs = (int)(dl + w.R0);
         float v0[W], v1[W];
         load_win<W>(col0, (uint32_t)bs, v0);
         if (NP > 1) load_win<W>(col1, (uint32_t)bs, v1);
         float s0 = 0.f, s1 = 0.f;
 #pragma unroll
         for (int t = 0; t < W; ++t) {
-            const float d = (t == 0) ? d0 : fmaf((float)t, tzf, d0);
-            const float w = hat(d);
-            s0 = fmaf(w, v0[t], s0);
-            if (NP > 1) s1 = fmaf(w, v1[t], s1);
+            const float d = (t == 0) ? d0 : fmaf((float)t, w.tzh, d0);
+            const float h = hat(d);
+            s0 = fmaf(h, v0[t], s0);
+            if (NP > 1) s1 = fmaf(h, v1[t], s1);
         }
         s[0][q] = s0;
         if (NP > 1) s[NP - 1][q] = s1;
@@ -729,29 +768,30 @@ __device__ __forceinline__ void bp_window(const PT *col0, const PT *col1, int nv
 }
 
 // The same sums for any row spacing: the rows within one voxel of z are
-// fewer than 2 hw + 1, so a fixed window of 3 (hw < 1.5) or 4 (hw < 2)
-// consecutive rows holds them, else a window of floor(2 hw + 1) rows.
+// fewer than 2 hw + 1 (hw = |1/tz|), so a fixed window of 3 (hw < 1.5) or 4
+// (hw < 2) consecutive rows holds them, else a window of floor(2 hw + 1) + 1
+// rows (one spare row against the rounding of hw).
 template <int KZ, int NP, typename PT>
-__device__ __forceinline__ void bp_column_sums(const PT *col0, const PT *col1, int nv, double zc, double tz,
-                                               double rtz, double hw, const double (&kd)[KZ], float (&s)[NP][KZ]) {
-    if (hw < 1.5 && nv >= 3) {
-        bp_window<3, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, s);
-    } else if (hw < 2.0 && nv >= 4) {
-        bp_window<4, KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, s);
+__device__ __forceinline__ void bp_column_sums(const PT *col0, const PT *col1, int nv, const WinCol &w,
+                                               const float (&u)[KZ], float (&s)[NP][KZ]) {
+    const float hw = fabsf(w.rtz);
+    if (hw < 1.5f && nv >= 3) {
+        bp_window<3, KZ, NP, PT>(col0, col1, nv, w, u, s);
+    } else if (hw < 2.f && nv >= 4) {
+        bp_window<4, KZ, NP, PT>(col0, col1, nv, w, u, s);
     } else {
-        const int nb = (int)fmin(2.0 * hw + 1.0, (double)nv);
+        const int nb = min((int)(2.f * hw + 1.f) + 1, nv);
+        const float hi = (float)(nv - nb) - w.R0;
 #pragma unroll
         for (int q = 0; q < KZ; ++q) {
-            const double zk = zc - kd[q];
-            int bs = (int)ceil(-zk * rtz - hw);
-            bs = max(0, min(bs, nv - nb));
+            float dl, d0;
+            win_start(w, u[q], hi, dl, d0);
+            const int bs = (int)(dl + w.R0);
             float s0 = 0.f, s1 = 0.f;
             for (int t = 0; t < nb; ++t) {
-                const int b = bs + t;
-                const float d = (float)fma(tz, (double)b, zk);
-                const float w = hat(d);
-                s0 = fmaf(w, load_f(col0, b), s0);
-                if (NP > 1) s1 = fmaf(w, load_f(col1, b), s1);
+                const float h = hat(fmaf((float)t, w.tzh, d0));
+                s0 = fmaf(h, load_f(col0, bs + t), s0);
+                if (NP > 1) s1 = fmaf(h, load_f(col1, bs + t), s1);
             }
             s[0][q] = s0;
             if (NP > 1) s[NP - 1][q] = s1;
@@ -768,8 +808,8 @@ __device__ __forceinline__ float column_coord(const SepView &S, float px, float 
 // What the column loop of bp_part needs of one column at a half-wave's
 // plane (prepared by one lane, read back from LDS).
 struct __align__(16) SepCol {
-    double zc, tz, rtz;  // z of detector row 0, row spacing along z, 1 / spacing
-    double pos;          // in-plane position where the column's rays cross the plane
+    WinCol w;    // the column's z mapping at the plane
+    double pos;  // in-plane position where the column's rays cross the plane
 };
 
 // One wave handles 64*KZ voxels of one (x, y) column, lane + 64*q for q < KZ.
@@ -793,7 +833,7 @@ struct __align__(16) SepCol {
 template <int PART, int KZ, int NP, typename PT, bool HALF>
 __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict__ cv,
                                         const PT *base0, const PT *base1, int i, int j, int nu, int nv,
-                                        const double (&kd)[KZ], float (&pv)[NP][KZ], SepCol *rec) {
+                                        double zw0, const float (&u)[KZ], float (&pv)[NP][KZ], SepCol *rec) {
     const float fi = (float)i, fj = (float)j;
     float c1, c2;
     if (PART == 0) {
@@ -828,9 +868,8 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
             const double tau = dm * ((PART == 0) ? C.rdx : C.rdy);  // ray parameter at the plane
             SepCol R;
             R.pos = (PART == 0) ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);
-            R.tz = tau * S.vz;                                   // row spacing along z at the plane
-            R.zc = fma(tau, S.dz0, S.sz);                        // z of row 0 at the plane
-            R.rtz = ((PART == 0) ? C.dxv : C.dyv) * inv_dm;      // 1 / tz
+            // row spacing along z, z of row 0, 1 / spacing at the plane
+            R.w = win_col(fma(tau, S.dz0, S.sz), tau * S.vz, ((PART == 0) ? C.dxv : C.dyv) * inv_dm, zw0);
             ok = C.axis == PART && 1.f - (float)fabs(R.pos - own) > 0.f && tau >= 0.0 && tau <= 1.0;
             if (ok) rec[lane] = R;
         }
@@ -847,7 +886,7 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
                 const PT *col0 = base0 + ac * nv;
                 const PT *col1 = (NP > 1) ? base1 + ac * nv : nullptr;
                 float sums[NP][KZ];
-                bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.zc, R.tz, R.rtz, fabs(R.rtz), kd, sums);
+                bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.w, u, sums);
 #pragma unroll
                 for (int q = 0; q < KZ; ++q) {
                     pv[0][q] = fmaf(wp, sums[0][q], pv[0][q]);
@@ -870,7 +909,7 @@ __device__ __forceinline__ void bp_part(const SepView &S, const ColD *__restrict
 template <int PART, int KZ, int NP, typename PT, int BI, int BJ, bool ZS>
 __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
                                             const PT *base1, int i0, int j0, int nu, int nv,
-                                            const double (&kd)[KZ], double zw0, double zw1,
+                                            const float (&u)[KZ], double zw0, double zw1,
                                             float (&pv)[NP][BI * BJ][KZ]) {
     constexpr int NPL = PART == 0 ? BI : BJ;  // planes in the block
     constexpr int NR = PART == 0 ? BJ : BI;   // rows per plane
@@ -920,11 +959,10 @@ __device__ __forceinline__ void bp_part_blk(const SepView &S, const ColD *__rest
             const double zend = fma(tz, (double)(nv - 1), zc);
             if (ZS && (fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0)) continue;
             const double rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;     // 1 / tz
-            const double hw = fabs(rtz);
             const PT *col0 = base0 + (long)a * nv;
             const PT *col1 = (NP > 1) ? base1 + (long)a * nv : nullptr;
             float sums[NP][KZ];
-            bp_column_sums<KZ, NP, PT>(col0, col1, nv, zc, tz, rtz, hw, kd, sums);
+            bp_column_sums<KZ, NP, PT>(col0, col1, nv, win_col(zc, tz, rtz, zw0), u, sums);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!(w[r] > 0.f)) continue;
@@ -963,6 +1001,9 @@ __global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ 
 #pragma unroll
     for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
     const double zw0 = (double)(zc_id * 64 * KZ), zw1 = zw0 + (double)(64 * KZ - 1);
+    float u[KZ];  // z - zw0 of the lane's voxels
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) u[q] = (float)(q * 64 + lane);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][NB][KZ];
 #pragma unroll
@@ -987,8 +1028,8 @@ __global__ __launch_bounds__(256) void k_backproject_blk(const PT *__restrict__ 
         const ColD *cv = cols + (long)v * nu;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        if (S.flags & 1) bp_part_blk<0, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, kd, zw0, zw1, pv);
-        if (S.flags & 2) bp_part_blk<1, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, kd, zw0, zw1, pv);
+        if (S.flags & 1) bp_part_blk<0, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, u, zw0, zw1, pv);
+        if (S.flags & 2) bp_part_blk<1, KZ, NP, PT, BI, BJ, ZS>(S, cv, base0, base1, i0, j0, nu, nv, u, zw0, zw1, pv);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1046,6 +1087,11 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
     double kd[KZ];
 #pragma unroll
     for (int q = 0; q < KZ; ++q) kd[q] = HALF ? (double)(lane & 31) : (double)(zc_id * 64 * KZ + q * 64 + lane);
+    // the wave's first z and the lanes' offsets from it
+    const double zw0 = HALF ? 0.0 : (double)(zc_id * 64 * KZ);
+    float u[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) u[q] = HALF ? (float)(lane & 31) : (float)(q * 64 + lane);
     // per-view partial sums in FP32, summed over views in FP64
     double acc[NP][KZ];
 #pragma unroll
@@ -1066,8 +1112,8 @@ __global__ __launch_bounds__(256) void k_backproject_sep(const PT *__restrict__ 
         const ColD *cv = cols + (long)v * nu;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        if (S.flags & 1) bp_part<0, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv, rec);
-        if (S.flags & 2) bp_part<1, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, kd, pv, rec);
+        if (S.flags & 1) bp_part<0, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, zw0, u, pv, rec);
+        if (S.flags & 2) bp_part<1, KZ, NP, PT, HALF>(S, cv, base0, base1, i, j, nu, nv, zw0, u, pv, rec);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1148,15 +1194,15 @@ constexpr int kPlSlots = kPlRows + 2;
 // What the column loop needs of one column at the wave's plane (prepared
 // by one lane, read back by the whole wave from LDS).
 struct __align__(16) PlCol {
-    double zc, tz, rtz;  // z of detector row 0, row spacing along z, 1 / spacing
-    float whi;           // in-plane hat weight of the upper row
-    int rl;              // block row of the lower tap (-1 .. kPlRows-1)
+    WinCol w;   // the column's z mapping at the plane
+    float whi;  // in-plane hat weight of the upper row
+    int rl;     // block row of the lower tap (-1 .. kPlRows-1)
 };
 
 template <int PART, int KZ, int NP, typename PT, bool ZS>
 __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
                                               const PT *base1, int P, int r0, int nu, int nv,
-                                              const double (&kd)[KZ], double zw0, double zw1, float *slot,
+                                              const float (&u)[KZ], double zw0, double zw1, float *slot,
                                               PlCol *rec) {
     // distance of the plane from the source along the major axis
     const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
@@ -1195,16 +1241,16 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
             const double tau = dm * (PART == 0 ? C.rdx : C.rdy);                 // ray parameter at the plane
             const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
             const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
+            const double tz = tau * S.vz;             // row spacing along z at the plane
+            const double zc = fma(tau, S.dz0, S.sz);  // z of row 0 at the plane
             PlCol R;
             R.rl = (int)fl - r0;
-            R.tz = tau * S.vz;
-            R.zc = fma(tau, S.dz0, S.sz);
-            R.rtz = (PART == 0 ? C.dxv : C.dyv) * inv_dm;
+            R.w = win_col(zc, tz, (PART == 0 ? C.dxv : C.dyv) * inv_dm, zw0);
             R.whi = (float)(pos - fl);
             ok = C.axis == PART && tau >= 0.0 && tau <= 1.0 && R.rl >= -1 && R.rl < kPlRows;
             if (ZS && ok) {
-                const double zend = fma(R.tz, (double)(nv - 1), R.zc);
-                ok = !(fmax(R.zc, zend) <= zw0 - 1.0 || fmin(R.zc, zend) >= zw1 + 1.0);
+                const double zend = fma(tz, (double)(nv - 1), zc);
+                ok = !(fmax(zc, zend) <= zw0 - 1.0 || fmin(zc, zend) >= zw1 + 1.0);
             }
             if (ok) rec[lane] = R;
         }
@@ -1228,7 +1274,7 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
             const PT *col0 = base0 + ac * nv;
             const PT *col1 = (NP > 1) ? base1 + ac * nv : nullptr;
             float sums[NP][KZ];
-            bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.zc, R.tz, R.rtz, fabs(R.rtz), kd, sums);
+            bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.w, u, sums);
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1261,6 +1307,9 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
 #pragma unroll
     for (int q = 0; q < KZ; ++q) kd[q] = (double)(zc_id * 64 * KZ + q * 64 + lane);
     const double zw0 = (double)(zc_id * 64 * KZ), zw1 = zw0 + (double)(64 * KZ - 1);
+    float u[KZ];  // z - zw0 of the lane's voxels
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) u[q] = (float)(q * 64 + lane);
 #pragma unroll
     for (int t = 0; t < NP * kPlSlots * KZ; ++t) slot[t * 64] = 0.f;
     double acc[NP][kPlRows][KZ];
@@ -1278,7 +1327,7 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
         if (!(S.flags & (PART == 0 ? 1 : 2))) continue;
         const PT *base0 = pt0 + (long)vl * nu * nv;
         const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, kd, zw0, zw1, slot,
+        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, u, zw0, zw1, slot,
                                             rec);
         // the view's sums into FP64, slots cleared (spare rows too)
 #pragma unroll
