@@ -313,8 +313,8 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "d09ec58dc6e5467acf57f5f2e70b8efab2f3efad9da3d6d9e07841c848938870",
-                         "bytes_per_launch": 381950150, "valu_issue": 0.82, "l2_hit": 0.959},
+    "k_backproject_pl": {"source_sha256": "14119ad475f5b1d1e0584e4cd287dcef7b97c8827c3f9460db424ad60c49441e",
+                         "bytes_per_launch": 382923974, "valu_issue": 0.81, "l2_hit": 0.959},
 }
 
 

@@ -337,15 +337,19 @@ __global__ __launch_bounds__(256) void k_project(const VT *__restrict__ vt, PT *
 // ray parameter tau at every plane and their in-plane (x or y) sample
 // position; only the z coordinate depends on the row.  Each wave therefore
 // first tabulates, for its column, one entry per plane in LDS (the planes are
-// spread over the 64 lanes): the voxel offset of the in-plane tap pair, its
-// weight and tau.  The sampling loop then reads the entry (a broadcast LDS
-// read) and computes only z = s_z + tau * D_z(row) in FP64 and the bilinear
-// interpolation.
+// spread over the 64 lanes): the voxel offset of the in-plane tap pair and its
+// weight.  The sampling loop then reads the entry (a broadcast LDS read),
+// steps z = s_z + tau * D_z(row), which is linear in the plane, and does the
+// bilinear interpolation.
 struct PlaneEntry {
-    int off;     // offset of the (plane, in-plane tap, z = -2 pad) voxel in the padded copy
-    float wa;    // weight of the second in-plane tap
-    double tau;  // ray parameter at the plane
+    int off;   // offset of the (plane, in-plane tap, z = -2 pad) voxel in the padded copy
+    float wa;  // weight of the second in-plane tap
 };
+
+// A fraction in [0, 1) as a 0.32 fixed-point value (rounded, kept below 1).
+__device__ __forceinline__ uint32_t frac_u32(double f) {
+    return (uint32_t)fmin(rint(f * 4294967296.0), 4294967295.0);
+}
 
 // Epilogue of the separable projector, for ray (v, a, b) with value
 // l = (A mu)[ray] and ray-length factor L = h|D|/|D_m|:
@@ -363,16 +367,13 @@ template <typename T> __device__ __forceinline__ float round_as(float x) { retur
 template <> __device__ __forceinline__ float round_as<_Float16>(float x) { return (float)(_Float16)x; }
 
 // WIDE: the pair copies exceed 4 GiB, so sample addresses are formed in 64 bits.
-#ifndef MGCT_PROJ_PW2_MIN
-#define MGCT_PROJ_PW2_MIN 512  // grid width from which blocks over BF16 copies hold 2 columns instead of 4
-#endif
-// Waves (adjacent detector columns) per block of the separable projector,
-// chosen by measurement: 2 for BF16 copies of grids 512 or more wide (4 was
-// 8 % slower at 512^3), 4 otherwise (2 was 4-7 % slower at 128^3 and 256^3,
-// about even at 512^3 in FP32 and 6 % slower on a 640 x 640 x 2304 FP32 grid).
-static int proj_pw(const Level &L, int vt_dtype) {
-    return vt_dtype == MGCT_BF16 && std::max(L.nx, L.ny) >= MGCT_PROJ_PW2_MIN ? 2 : 4;
-}
+// Waves (adjacent detector columns) per block of the separable projector:
+// 4, chosen by measurement (2 was 4-7 % slower at 128^3 and 256^3 and 6 %
+// slower on a 640 x 640 x 2304 FP32 grid; for BF16 copies of grids 512 or more
+// wide 2 was faster until the z coordinate stepped in fixed point, after which
+// 4 is faster there too, 296 -> 280 ms at 512^3).  The kernel takes the count
+// from its block size.
+static int proj_pw(const Level &, int) { return 4; }
 
 template <typename VT, typename PT, int MODE, typename TB, bool WIDE>
 __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx, const VT *__restrict__ vty,
@@ -418,7 +419,6 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
             PlaneEntry e;
             e.off = (l + kVolPad) * Sm + (int)ga * Sa;  // in pairs
             e.wa = (float)(fa - ga);
-            e.tau = tau;
             T[l] = e;
         }
     }
@@ -438,17 +438,31 @@ __global__ __launch_bounds__(256) void k_project_sep(const VT *__restrict__ vtx,
         float acc = 0.f;
         if (zlo <= zhi && isfinite(Bz)) {
             const int lz0 = (int)zlo, lz1 = (int)zhi;
+            // The sample's padded z on plane l is linear in l (slope Bz), so it
+            // steps from plane lz0 in 32.32 fixed point: integer part zi (the
+            // lower z tap) and fraction zf (its weight), an integer add with
+            // carry per plane instead of FP64 arithmetic, which issues at half
+            // the FP32 rate here.  Start and slope are rounded once from FP64;
+            // the drift stays below 2^-33 per plane.  The clipped range keeps
+            // every sample at least half a voxel inside the padded copy.
+            const double z0 = fma(((double)lz0 - sm) * rDm, Dz, szp);
+            const double g0 = floor(z0), gb = floor(Bz);
+            int zi = (int)g0;
+            uint32_t zf = frac_u32(z0 - g0);
+            const int bi = (int)gb;
+            const uint32_t bf = frac_u32(Bz - gb);
 #pragma unroll 2
             for (int l = lz0; l <= lz1; ++l) {
                 const PlaneEntry e = T[l];
-                const double fz = fma(e.tau, Dz, szp);
-                const double gz = floor(fz);
-                const float wz = (float)(fz - gz);
+                const float wz = (float)zf * 0x1p-32f;
                 // taps (a0,z0) (a1,z0) (a0,z1) (a1,z1)
-                const float4 r = WIDE ? load_quad(vt + 2L * ((long)e.off + (long)gz), 0u)
-                                      : load_quad(vt, 2u * (uint32_t)(e.off + (int)gz));
+                const float4 r = WIDE ? load_quad(vt + 2L * ((long)e.off + (long)zi), 0u)
+                                      : load_quad(vt, 2u * (uint32_t)(e.off + zi));
                 const float q0 = fmaf(wz, r.z - r.x, r.x), q1 = fmaf(wz, r.w - r.y, r.y);
                 acc += fmaf(e.wa, q1 - q0, q0);
+                const uint32_t nf = zf + bf;
+                zi += bi + (nf < zf ? 1 : 0);
+                zf = nf;
             }
         }
         const float l = acc * scale;
