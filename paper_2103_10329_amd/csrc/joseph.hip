@@ -92,6 +92,11 @@ __device__ __forceinline__ double ray_setup(const ViewIdx &V, int nu, int nv, in
 }
 
 // Restrict [lo, hi] to the planes l with A + l*B inside [bmin, bmax].
+// A fraction in [0, 1) as a 0.32 fixed-point value (rounded, kept below 1).
+__device__ __forceinline__ uint32_t frac_u32(double f) {
+    return (uint32_t)fmin(rint(f * 4294967296.0), 4294967295.0);
+}
+
 __device__ __forceinline__ void clip_range(double &lo, double &hi, double A, double B, double bmin, double bmax) {
     if (B > 0.0) {
         lo = fmax(lo, ceil((bmin - A) / B));
@@ -313,20 +318,33 @@ __global__ __launch_bounds__(256) void k_project(const VT *__restrict__ vt, PT *
         const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
         const int Sm = (m == 0) ? PY * PZ : PZ;
         const int Sa = (m == 0) ? PZ : PY * PZ;
-        // Sample coordinates stay in FP64 (full-rate FMA on this GPU): their
-        // absolute error then stays far below the FP32 rounding of the weights.
-        const double Aap = Aa + kVolPad, Azp = Az + kVolPad;
+        // The sample's padded in-plane and z coordinates are linear in the
+        // plane index; both step from plane l0 in 32.32 fixed point (integer
+        // part = lower tap, fraction = its weight): integer adds with carry
+        // per plane instead of FP64 arithmetic, which issues at half the FP32
+        // rate here.  Starts and slopes are rounded once from FP64; the drift
+        // stays below 2^-33 per plane, far below the FP32 rounding of the
+        // weights.  The clipped range keeps every sample at least half a voxel
+        // inside the padded copy.
+        const double fa0 = fma((double)l0, Ba, Aa + kVolPad), fz0 = fma((double)l0, Bz, Az + kVolPad);
+        const double ga0 = floor(fa0), gz0 = floor(fz0), gba = floor(Ba), gbz = floor(Bz);
+        int ai = (int)ga0, zi = (int)gz0;
+        uint32_t af = frac_u32(fa0 - ga0), zf = frac_u32(fz0 - gz0);
+        const int bai = (int)gba, bzi = (int)gbz;
+        const uint32_t baf = frac_u32(Ba - gba), bzf = frac_u32(Bz - gbz);
         int off_m = (l0 + kVolPad) * Sm;
         for (int l = l0; l <= l1; ++l, off_m += Sm) {
-            const double lf = (double)l;
-            const double fa = fma(lf, Ba, Aap), fz = fma(lf, Bz, Azp);
-            const double ga = floor(fa), gz = floor(fz);
-            const float wa = (float)(fa - ga), wz = (float)(fz - gz);
-            const int off = off_m + (int)ga * Sa + (int)gz;
+            const float wa = (float)af * 0x1p-32f, wz = (float)zf * 0x1p-32f;
+            const int off = off_m + ai * Sa + zi;
             const float p00 = load_f(vt, off), p01 = load_f(vt, off + 1);
             const float p10 = load_f(vt, off + Sa), p11 = load_f(vt, off + Sa + 1);
             const float q0 = fmaf(wz, p01 - p00, p00), q1 = fmaf(wz, p11 - p10, p10);
             acc += fmaf(wa, q1 - q0, q0);
+            const uint32_t na = af + baf, nz2 = zf + bzf;
+            ai += bai + (na < af ? 1 : 0);
+            zi += bzi + (nz2 < zf ? 1 : 0);
+            af = na;
+            zf = nz2;
         }
     }
     store_f(proj, ((long)vl * nv + b) * nu + a, acc * scale);
@@ -346,10 +364,6 @@ struct PlaneEntry {
     float wa;  // weight of the second in-plane tap
 };
 
-// A fraction in [0, 1) as a 0.32 fixed-point value (rounded, kept below 1).
-__device__ __forceinline__ uint32_t frac_u32(double f) {
-    return (uint32_t)fmin(rint(f * 4294967296.0), 4294967295.0);
-}
 
 // Epilogue of the separable projector, for ray (v, a, b) with value
 // l = (A mu)[ray] and ray-length factor L = h|D|/|D_m|:
