@@ -1599,23 +1599,36 @@ __global__ __launch_bounds__(256) void k_geom_grad(const VT *__restrict__ vt, co
             const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
             const int Sm = (m == 0) ? PY * PZ : PZ;
             const int Sa = (m == 0) ? PZ : PY * PZ;
-            const double Aap = Aa + kVolPad, Azp = Az + kVolPad;
+            // sample coordinates stepped in 32.32 fixed point as in k_project,
+            // and the ray parameter t = (l - s_m) / D_m stepped by 1 / D_m (the
+            // sums stay FP64)
+            const double fa0 = fma((double)l0, Ba, Aa + kVolPad), fz0 = fma((double)l0, Bz, Az + kVolPad);
+            const double ga0 = floor(fa0), gz0 = floor(fz0), gba = floor(Ba), gbz = floor(Bz);
+            int ai = (int)ga0, zi = (int)gz0;
+            uint32_t af = frac_u32(fa0 - ga0), zf = frac_u32(fz0 - gz0);
+            const int bai = (int)gba, bzi = (int)gbz;
+            const uint32_t baf = frac_u32(Ba - gba), bzf = frac_u32(Bz - gbz);
+            const double rDm = 1.0 / Dm;
+            double t = ((double)l0 - sm) * rDm;
             for (int l = l0; l <= l1; ++l) {
-                const double fa = fma((double)l, Ba, Aap), fz = fma((double)l, Bz, Azp);
-                const double ga = floor(fa), gz = floor(fz);
-                const float wa = (float)(fa - ga), wz = (float)(fz - gz);
-                const uint32_t off = (uint32_t)((l + kVolPad) * Sm + (int)ga * Sa + (int)gz);
+                const float wa = (float)af * 0x1p-32f, wz = (float)zf * 0x1p-32f;
+                const uint32_t off = (uint32_t)((l + kVolPad) * Sm + ai * Sa + zi);
                 const float2 r0 = load_pair(vt, off), r1 = load_pair(vt, off + Sa);
                 const float q0 = fmaf(wz, r0.y - r0.x, r0.x), q1 = fmaf(wz, r1.y - r1.x, r1.x);
                 const float f = fmaf(wa, q1 - q0, q0);
                 const float dfa = q1 - q0;
                 const float dfz = fmaf(wa, (r1.y - r1.x) - (r0.y - r0.x), r0.y - r0.x);
-                const double t = ((double)l - sm) / Dm;
                 S += (double)f;
                 Ga += (double)dfa;
                 Gat += t * (double)dfa;
                 Gz += (double)dfz;
                 Gzt += t * (double)dfz;
+                t += rDm;
+                const uint32_t na = af + baf, nz2 = zf + bzf;
+                ai += bai + (na < af ? 1 : 0);
+                zi += bzi + (nz2 < zf ? 1 : 0);
+                af = na;
+                zf = nz2;
             }
         }
         // to physical units: positions scale by h, derivatives per index unit by 1/h
