@@ -313,8 +313,8 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "14119ad475f5b1d1e0584e4cd287dcef7b97c8827c3f9460db424ad60c49441e",
-                         "bytes_per_launch": 382923974, "valu_issue": 0.81, "l2_hit": 0.959},
+    "k_backproject_pl": {"source_sha256": "2ed9cd5085f9799f28918bafc4961bf12207772a2e80f898185d9fee36fe441b",
+                         "bytes_per_launch": 382858444, "valu_issue": 0.82, "l2_hit": 0.959},
 }
 
 
