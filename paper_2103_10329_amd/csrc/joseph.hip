@@ -1227,6 +1227,20 @@ struct __align__(16) PlCol {
     int rl;     // block row of the lower tap (-1 .. kPlRows-1)
 };
 
+// Column records per batch and the waves per SIMD the registers must allow,
+// by variant.  The single-output variant for grids of one 128-deep z chunk
+// (KZ = 2, no z-range test) runs 6 waves per SIMD: its records then go in
+// batches of 32 so that slots and records fit 6 blocks per CU in LDS (24 KB a
+// block), and its registers are held to 80 (a few spill outside the column
+// loop); at 128^3 x 360 views that is 3 % faster than 5 waves.  The others
+// keep batches of 64 and 5 waves (the deeper variant spilled inside the loop
+// at 6 and was a third slower).
+template <int KZ, int NP, bool ZS> constexpr bool bp_pl_six() { return KZ == 2 && NP == 1 && !ZS; }
+template <int KZ, int NP, bool ZS> constexpr int bp_pl_batch() { return bp_pl_six<KZ, NP, ZS>() ? 32 : 64; }
+template <int KZ, int NP, bool ZS> constexpr int bp_pl_minw() {
+    return NP > 1 ? 1 : (bp_pl_six<KZ, NP, ZS>() ? 6 : 5);
+}
+
 template <int PART, int KZ, int NP, typename PT, bool ZS>
 __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
                                               const PT *base1, int P, int r0, int nu, int nv,
@@ -1252,8 +1266,8 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
     alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
     ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
     const int lane = threadIdx.x & 63;
-    // The candidate columns go in batches of 64: lane l works out column
-    // a0 + l at this plane (ray parameter, in-plane position and rows, z
+    // The candidate columns go in batches of RB (64, or 32 in the 6-wave
+    // variant): lane l < RB works out column a0 + l at this plane (ray parameter, in-plane position and rows, z
     // mapping of the detector rows) and whether it reaches the block, and
     // keeps the result in the wave's LDS records; the wave then walks the
     // columns that do (the ballot's set bits, in increasing order), reading
@@ -1261,10 +1275,11 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
     // one lane instead of the whole wave.  LDS operations of a wave complete
     // in order, so a record written by one lane is seen by the next read,
     // and the next batch's writes follow this batch's reads.
-    for (int a0 = alo; a0 <= ahi; a0 += 64) {
+    constexpr int RB = bp_pl_batch<KZ, NP, ZS>();
+    for (int a0 = alo; a0 <= ahi; a0 += RB) {
         const int a = a0 + lane;
         bool ok = false;
-        if (a <= ahi) {
+        if (lane < RB && a <= ahi) {
             const ColD &C = cv[a];
             const double tau = dm * (PART == 0 ? C.rdx : C.rdy);                 // ray parameter at the plane
             const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
@@ -1395,18 +1410,15 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
 
 // Launch: grid (waves / 4, view chunks, 2 parts); part[] receives 2 x chunks
 // partial volumes per output (the second output np_stride floats further).
-#ifndef MGCT_BP_PL_MINW
-#define MGCT_BP_PL_MINW 5  // waves per SIMD the single-output variants' registers must allow
-#endif
 template <int KZ, int NP, typename PT, bool ZS>
-__global__ __launch_bounds__(256, NP == 1 ? MGCT_BP_PL_MINW : 1) void k_backproject_pl(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
+__global__ __launch_bounds__(256, (bp_pl_minw<KZ, NP, ZS>())) void k_backproject_pl(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
                                                         float *__restrict__ part, long np_stride,
                                                         const SepView *__restrict__ sep,
                                                         const ColD *__restrict__ cols, int nx, int ny, int nz, int nu,
                                                         int nv, int nviews_sub, int view0, int view_step,
                                                         int per_chunk, int nchunks) {
     __shared__ float lds[4 * NP * kPlSlots * KZ * 64];
-    __shared__ PlCol recs[4][64];
+    __shared__ PlCol recs[4][bp_pl_batch<KZ, NP, ZS>()];
     float *slot = lds + (threadIdx.x >> 6) * (NP * kPlSlots * KZ * 64) + (threadIdx.x & 63);
     PlCol *rec = recs[threadIdx.x >> 6];
     if (blockIdx.z == 0)
