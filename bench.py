@@ -314,9 +314,9 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
     "k_backproject_pl": {"source_sha256": "300f60c7db04fc5566f993d9337ddb2b4ff8f142899ec824e6f82025916d53fc",
-                          "bytes_per_launch": 407373088, "valu_issue": 0.85, "l2_hit": 0.958},
+                          "bytes_per_launch": 405856545, "valu_issue": 0.85, "l2_hit": 0.958},
     "k_project_sep": {"source_sha256": "300f60c7db04fc5566f993d9337ddb2b4ff8f142899ec824e6f82025916d53fc",
-                       "bytes_per_launch": 7174581862, "valu_issue": 0.71, "l2_hit": 0.494},
+                       "bytes_per_launch": 7169518308, "valu_issue": 0.72, "l2_hit": 0.495},
 }
 
 
