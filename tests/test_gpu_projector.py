@@ -37,18 +37,18 @@ def _single_view_geom(diag=False):
     return oracle.Geom(40, 36, 44, 0.8, (0.0, 0.0, 0.0), 48, 40, views)
 
 
-def _fine_detector_geom(shallow=False):
+def _fine_detector_geom(shallow=False, depth=40):
     # detector columns much finer than the voxels (magnification 2: 8 columns
     # per voxel deep, 16 shallow), so that more candidate columns reach a
     # back-projector wave than one batch of column records holds (64 for the
-    # plane-blocked kernel on grids deeper than 32, 32 per half-wave for the
-    # row-pair kernel); about 8 detector rows per voxel take the transpose's
-    # general row window
+    # plane-blocked kernel on grids deeper than 32, 32 for its 128-deep
+    # variant, 32 per half-wave for the row-pair kernel); about 8 detector
+    # rows per voxel take the transpose's general row window
     if shallow:
         views = synth.trajectory(6, 2, 0.1, z_range=(-1.5, 1.5))
         return oracle.Geom(20, 18, 16, 0.8, (0.0, 0.1, -0.2), 320, 48, views)
     views = synth.trajectory(6, 2, 0.2)
-    return oracle.Geom(24, 20, 40, 0.8, (0.1, -0.2, 0.3), 200, 48, views)
+    return oracle.Geom(24, 20, depth, 0.8, (0.1, -0.2, 0.3), 200, 48, views)
 
 
 CASES = {
@@ -58,6 +58,8 @@ CASES = {
     "single_view_45deg": lambda: _single_view_geom(True),
     "fine_detector_deep": _fine_detector_geom,
     "fine_detector_shallow": lambda: _fine_detector_geom(True),
+    # one 128-deep z chunk: the variant that walks its records in batches of 32
+    "fine_detector_128deep": lambda: _fine_detector_geom(depth=128),
     "c1_level2": lambda: workload("c1").level(2),
     "c1_level1": lambda: workload("c1").level(1),
 }
