@@ -51,6 +51,13 @@ def _fine_detector_geom(shallow=False, depth=40):
     return oracle.Geom(24, 20, depth, 0.8, (0.1, -0.2, 0.3), 200, 48, views)
 
 
+def _few_rows_geom(nv):
+    # a detector of one or two rows (fan-beam-like): every z window of the
+    # transpose is clamped to the detector, the general window with nv rows
+    views = synth.trajectory(12, 2, 1.6, z_range=(-0.5, 0.5))
+    return oracle.Geom(30, 26, 36, 0.8, (0.0, 0.0, 0.0), 44, nv, views)
+
+
 CASES = {
     "c0": lambda: workload("c0"),
     "ragged": _ragged_geom,
@@ -60,6 +67,8 @@ CASES = {
     "fine_detector_shallow": lambda: _fine_detector_geom(True),
     # one 128-deep z chunk: the variant that walks its records in batches of 32
     "fine_detector_128deep": lambda: _fine_detector_geom(depth=128),
+    "one_row": lambda: _few_rows_geom(1),
+    "two_rows": lambda: _few_rows_geom(2),
     "c1_level2": lambda: workload("c1").level(2),
     "c1_level1": lambda: workload("c1").level(1),
 }
