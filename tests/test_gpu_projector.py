@@ -51,6 +51,14 @@ def _fine_detector_geom(shallow=False, depth=40):
     return oracle.Geom(24, 20, depth, 0.8, (0.1, -0.2, 0.3), 200, 48, views)
 
 
+def _flipped_rows_geom():
+    # detector rows counted downwards (row step vector along -z): negative
+    # row spacing along z at every plane
+    views = synth.trajectory(24, 4, 1.6)
+    views[:, 9:12] *= -1.0
+    return oracle.Geom(34, 30, 48, 0.7, (0.2, -0.1, 0.0), 52, 60, views)
+
+
 def _few_rows_geom(nv):
     # a detector of one or two rows (fan-beam-like): every z window of the
     # transpose is clamped to the detector, the general window with nv rows
@@ -67,6 +75,7 @@ CASES = {
     "fine_detector_shallow": lambda: _fine_detector_geom(True),
     # one 128-deep z chunk: the variant that walks its records in batches of 32
     "fine_detector_128deep": lambda: _fine_detector_geom(depth=128),
+    "flipped_rows": _flipped_rows_geom,
     "one_row": lambda: _few_rows_geom(1),
     "two_rows": lambda: _few_rows_geom(2),
     "c1_level2": lambda: workload("c1").level(2),
