@@ -37,24 +37,68 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-LDS radix-2 Stockham FFT of B lines of length N = 2^logN.  dir = +1
-// forward (exp(-2 pi i ...)), -1 inverse (unscaled).  Returns the buffer
-// holding the result.
+// In-LDS Stockham FFT of B lines of length N = 2^logN.  A stage of radix R
+// takes the sub-transforms of length Ns to length R Ns: element j of a line
+// (j < N/R, k = j mod Ns) combines src[j + r N/R] (r < R) after the twiddles
+// exp(-+2 pi i r k/(R Ns)) by a length-R DFT and writes them to
+// dst[(j - k) R + k + r Ns].  Lines of 128 points or more use radix-4 stages
+// after one radix-2 stage when logN is odd (half the barriers and LDS round
+// trips; 128^3 filter 0.123 -> 0.112 ms), shorter ones radix 2 throughout
+// (radix 4 was slower at 64 points).  dir = +1 forward (exp(-2 pi i ...)),
+// -1 inverse (unscaled).  tw[m] = exp(-2 pi i m/N) for m < N/2 (the other half
+// is its negative).  Returns the buffer holding the result.
+__device__ __forceinline__ float2 twiddle(const float2 *__restrict__ tw, int m, int half, int dir) {
+    float2 w = m < half ? tw[m] : make_float2(-tw[m - half].x, -tw[m - half].y);
+    if (dir < 0) w.y = -w.y;
+    return w;
+}
+
 __device__ float2 *fft_lines(float2 *src, float2 *dst, int logN, int B, const float2 *__restrict__ tw, int dir) {
     const int N = 1 << logN, half = N >> 1;
-    for (int Ns = 1, ls = 0; Ns < N; Ns <<= 1, ++ls) {
+    const bool r4 = logN >= 7;
+    int lns = 0;  // log2 of the current sub-transform length Ns
+    const int n2 = r4 ? (logN & 1) : logN;  // radix-2 stages
+    for (; lns < n2; ++lns) {
+        const int Ns = 1 << lns;
         for (int q = threadIdx.x; q < B * half; q += blockDim.x) {
             const int l = q >> (logN - 1);
             const int j = q & (half - 1);
-            const float2 a = src[l * N + j];
-            float2 b = src[l * N + j + half];
             const int k = j & (Ns - 1);
-            float2 w = tw[k << (logN - 1 - ls)];
+            const float2 a = src[l * N + j];
+            float2 w = tw[k << (logN - 1 - lns)];  // index below N/2
             if (dir < 0) w.y = -w.y;
-            b = cmul(b, w);
+            const float2 b = cmul(src[l * N + j + half], w);
             const int idx = ((j - k) << 1) + k;
             dst[l * N + idx] = make_float2(a.x + b.x, a.y + b.y);
             dst[l * N + idx + Ns] = make_float2(a.x - b.x, a.y - b.y);
+        }
+        __syncthreads();
+        float2 *t = src;
+        src = dst;
+        dst = t;
+    }
+    const int quarter = N >> 2;
+    for (; lns < logN; lns += 2) {
+        const int Ns = 1 << lns;
+        for (int q = threadIdx.x; q < B * quarter; q += blockDim.x) {
+            const int l = q >> (logN - 2);
+            const int j = q & (quarter - 1);
+            const int k = j & (Ns - 1);
+            const int step = k << (logN - 2 - lns);  // twiddle index of r = 1
+            const float2 *in = src + l * N + j;
+            const float2 v0 = in[0];
+            const float2 v1 = cmul(in[quarter], twiddle(tw, step, half, dir));
+            const float2 v2 = cmul(in[2 * quarter], twiddle(tw, 2 * step, half, dir));
+            const float2 v3 = cmul(in[3 * quarter], twiddle(tw, 3 * step, half, dir));
+            const float2 t0 = make_float2(v0.x + v2.x, v0.y + v2.y), t1 = make_float2(v0.x - v2.x, v0.y - v2.y);
+            const float2 t2 = make_float2(v1.x + v3.x, v1.y + v3.y), d = make_float2(v1.x - v3.x, v1.y - v3.y);
+            // (v1 - v3) times -i (forward) or +i (inverse)
+            const float2 t3 = dir > 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+            float2 *out = dst + l * N + ((j - k) << 2) + k;
+            out[0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+            out[Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
+            out[2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
+            out[3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
         }
         __syncthreads();
         float2 *t = src;
