@@ -226,30 +226,35 @@ hipError_t launch_stencil27(const float *in, float *out, int nx, int ny, int nz,
 }
 
 // 3^3 bilateral filter, in-grid neighbours only, normalised.
-__global__ __launch_bounds__(256) void k_bilateral(const float *in, float *out, int nx, int ny, int nz, float inv2ss,
-                                                   float inv2sr) {
-    const size_t n = (size_t)nx * ny * nz;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((size_t)nx * ny));
+// 3^3 bilateral filter: neighbours inside the grid, weight
+// exp(-|offset|^2 / (2 sigma_s^2) - (v - c)^2 / (2 sigma_r^2)).  All 27 taps are
+// unrolled with the outside ones masked to weight 0 (adding exact zeros keeps
+// the sums of the branching form), 32-bit indices (grids hold fewer than
+// 2^31 voxels) and the hardware exponential (about 1e-7 relative here).
+__global__ __launch_bounds__(256) void k_bilateral(const float *__restrict__ in, float *__restrict__ out, int nx,
+                                                   int ny, int nz, float inv2ss, float inv2sr) {
+    const long n = (long)nx * ny * nz;
+    // the loop counter is 64-bit (counter + stride may pass 2^31); the voxel
+    // index itself fits 32 bits
+    for (long li = blockIdx.x * (long)blockDim.x + threadIdx.x; li < n; li += (long)gridDim.x * blockDim.x) {
+        const int idx = (int)li;
+        const int x = idx % nx, t = idx / nx, y = t % ny, z = t / ny;
         const float c = in[idx];
         float num = 0.f, den = 0.f;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int zz = z + dz;
-            if (zz < 0 || zz >= nz) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int yy = y + dy;
-                if (yy < 0 || yy >= ny) continue;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
-                    const int xx = x + dx;
-                    if (xx < 0 || xx >= nx) continue;
-                    const float v = in[((size_t)zz * ny + yy) * nx + xx];
+                    const bool ok = (unsigned)(x + dx) < (unsigned)nx && (unsigned)(y + dy) < (unsigned)ny &&
+                                    (unsigned)(z + dz) < (unsigned)nz;
+                    const float v = in[ok ? idx + (dz * ny + dy) * nx + dx : idx];
                     const float d = v - c;
-                    const float w = expf(-(float)(dx * dx + dy * dy + dz * dz) * inv2ss - d * d * inv2sr);
+                    const float w = ok ? __expf(-(float)(dx * dx + dy * dy + dz * dz) * inv2ss - d * d * inv2sr) : 0.f;
                     num = fmaf(w, v, num);
                     den += w;
                 }
-            }
-        }
         out[idx] = num / den;
     }
 }
