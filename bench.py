@@ -313,10 +313,10 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "300f60c7db04fc5566f993d9337ddb2b4ff8f142899ec824e6f82025916d53fc",
-                          "bytes_per_launch": 405856545, "valu_issue": 0.85, "l2_hit": 0.958},
-    "k_project_sep": {"source_sha256": "300f60c7db04fc5566f993d9337ddb2b4ff8f142899ec824e6f82025916d53fc",
-                       "bytes_per_launch": 7169518308, "valu_issue": 0.72, "l2_hit": 0.495},
+    "k_backproject_pl": {"source_sha256": "883b20d1f5c19920eb742a87862ab630fdb4c0c4ce2409824328862be86ccb89",
+                          "bytes_per_launch": 407852319, "valu_issue": 0.85, "l2_hit": 0.958},
+    "k_project_sep": {"source_sha256": "883b20d1f5c19920eb742a87862ab630fdb4c0c4ce2409824328862be86ccb89",
+                       "bytes_per_launch": 7171321527, "valu_issue": 0.71, "l2_hit": 0.494},
 }
 
 

@@ -78,6 +78,15 @@ template <typename T> __device__ __forceinline__ void store_f(T *p, long i, floa
 template <> __device__ __forceinline__ void store_f<float>(float *p, long i, float x) { p[i] = x; }
 template <> __device__ __forceinline__ void store_f<uint16_t>(uint16_t *p, long i, float x) { p[i] = f32_to_bf16(x); }
 template <> __device__ __forceinline__ void store_f<_Float16>(_Float16 *p, long i, float x) { p[i] = (_Float16)x; }
+// Two consecutive values at even index i in one 8-byte (float) or 4-byte
+// (bf16) store.
+template <typename T> __device__ __forceinline__ void store_pair(T *p, long i, float x0, float x1);
+template <> __device__ __forceinline__ void store_pair<float>(float *p, long i, float x0, float x1) {
+    *reinterpret_cast<float2 *>(p + i) = make_float2(x0, x1);
+}
+template <> __device__ __forceinline__ void store_pair<uint16_t>(uint16_t *p, long i, float x0, float x1) {
+    *reinterpret_cast<uint32_t *>(p + i) = (uint32_t)f32_to_bf16(x0) | ((uint32_t)f32_to_bf16(x1) << 16);
+}
 
 // ---------------------------------------------------------------- set-up --
 
@@ -159,23 +168,24 @@ hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int
 // for x-major rays (a = y) and vty[y][x][z] = (mu[x][y][z], mu[x+1][y][z])
 // for y-major rays (a = x), zero-padded by kVolPad, z fastest.  The four
 // taps of a sample are then 4 consecutive values: one 16-byte gather.
-// Grid: (x tiles of 64, z tiles of 64, y + 1 for y in [-1, ny-1]).
-template <typename TI, typename TO>
+// Grid: (x tiles of TX, z tiles of 64, y + 1 for y in [-1, ny-1]); each
+// pair leaves in one store.
+template <typename TI, typename TO, int TX>
 __global__ __launch_bounds__(256) void k_transpose_pairs(const TI *__restrict__ vol, TO *__restrict__ vtx,
                                                          TO *__restrict__ vty, int nx, int ny, int nz) {
-    __shared__ float t0[64][67];  // row y, x in [x0-1, x0+64]
-    __shared__ float t1[64][65];  // row y+1, x in [x0, x0+63]
-    const int x0 = blockIdx.x * 64, z0 = blockIdx.y * 64, y = (int)blockIdx.z - 1;
+    __shared__ float t0[64][TX + 3];  // row y, x in [x0-1, x0+TX]
+    __shared__ float t1[64][TX + 1];  // row y+1, x in [x0, x0+TX-1]
+    const int x0 = blockIdx.x * TX, z0 = blockIdx.y * 64, y = (int)blockIdx.z - 1;
     const int t = threadIdx.x;
-    for (int q = t; q < 64 * 66; q += 256) {
-        const int zl = q / 66, xl = q % 66;
+    for (int q = t; q < 64 * (TX + 2); q += 256) {
+        const int zl = q / (TX + 2), xl = q % (TX + 2);
         const int z = z0 + zl, x = x0 - 1 + xl;
         float v = 0.f;
         if (y >= 0 && z < nz && x >= 0 && x < nx) v = load_f(vol, ((long)z * ny + y) * nx + x);
         t0[zl][xl] = v;
     }
-    for (int q = t; q < 64 * 64; q += 256) {
-        const int zl = q >> 6, xl = q & 63;
+    for (int q = t; q < 64 * TX; q += 256) {
+        const int zl = q / TX, xl = q % TX;
         const int z = z0 + zl, x = x0 + xl;
         float v = 0.f;
         if (y + 1 < ny && z < nz && x < nx) v = load_f(vol, ((long)z * ny + (y + 1)) * nx + x);
@@ -183,25 +193,23 @@ __global__ __launch_bounds__(256) void k_transpose_pairs(const TI *__restrict__ 
     }
     __syncthreads();
     const long PX = nx + 2 * kVolPad, PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
-    // vtx pairs along y: x in [x0, x0+63], y in [-1, ny-1]
-    for (int q = t; q < 64 * 64; q += 256) {
+    // vtx pairs along y: x in [x0, x0+TX-1], y in [-1, ny-1]
+    for (int q = t; q < TX * 64; q += 256) {
         const int xl = q >> 6, zl = q & 63;
         const int z = z0 + zl, x = x0 + xl;
         if (z < nz && x < nx) {
             const long o = (((long)(x + kVolPad) * PY + (y + kVolPad)) * PZ + (z + kVolPad)) * 2;
-            store_f(vtx, o, t0[zl][xl + 1]);
-            store_f(vtx, o + 1, t1[zl][xl]);
+            store_pair(vtx, o, t0[zl][xl + 1], t1[zl][xl]);
         }
     }
-    // vty pairs along x: y in [0, ny-1], x in [x0, x0+63] (and x = -1 for the first tile)
+    // vty pairs along x: y in [0, ny-1], x in [x0, x0+TX-1] (and x = -1 for the first tile)
     if (y >= 0) {
-        for (int q = t; q < 65 * 64; q += 256) {
+        for (int q = t; q < (TX + 1) * 64; q += 256) {
             const int xl = (q >> 6) - 1, zl = q & 63;
             const int z = z0 + zl, x = x0 + xl;
             if (z < nz && x < nx && (xl >= 0 || x0 == 0)) {
                 const long o = (((long)(y + kVolPad) * PX + (x + kVolPad)) * PZ + (z + kVolPad)) * 2;
-                store_f(vty, o, t0[zl][xl + 1]);
-                store_f(vty, o + 1, t0[zl][xl + 2]);
+                store_pair(vty, o, t0[zl][xl + 1], t0[zl][xl + 2]);
             }
         }
     }
@@ -251,11 +259,16 @@ hipError_t launch_emtr_update_pairs(float *vol, const float *num, const float *d
     return hipGetLastError();
 }
 
+#ifndef MGCT_TP_X
+#define MGCT_TP_X 16
+#endif
+constexpr int kTpX = MGCT_TP_X;  // x tile width of the pair-copy transposition
+
 hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,
                                   hipStream_t s) {
-    dim3 grid((L.nx + 63) / 64, (L.nz + 63) / 64, L.ny + 1);
+    dim3 grid((L.nx + kTpX - 1) / kTpX, (L.nz + 63) / 64, L.ny + 1);
 #define MGCT_TP(TI, TO) \
-    k_transpose_pairs<TI, TO><<<grid, 256, 0, s>>>((const TI *)vol, (TO *)vtx, (TO *)vty, L.nx, L.ny, L.nz)
+    k_transpose_pairs<TI, TO, kTpX><<<grid, 256, 0, s>>>((const TI *)vol, (TO *)vtx, (TO *)vty, L.nx, L.ny, L.nz)
     if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_F32) MGCT_TP(float, float);
     else if (vol_dtype == MGCT_BF16 && vt_dtype == MGCT_BF16) MGCT_TP(uint16_t, uint16_t);
     else if (vol_dtype == MGCT_F32 && vt_dtype == MGCT_BF16) MGCT_TP(float, uint16_t);
