@@ -138,3 +138,41 @@ def test_paper_shaped_volume_with_wide_copies():
     e3 = abs(dot1 - dot2) / abs(dot2)
     say("  rays rel L2", e1, " voxels rel L2", e2, " adjoint", e3)
     assert e1 <= 1e-5 and e2 <= 1e-5 and e3 <= 1e-6
+
+
+def test_paper_shaped_volume_ops_sampled():
+    """Bilateral filter and soft threshold on the 640 x 640 x 2304 volume
+    (943 M voxels, more than the capped grid has threads, so the grid-stride
+    loops take several turns): sampled voxels, corners and the last voxel
+    against the oracle run on their 3^3 neighbourhoods, which hold every
+    input of the filter at that voxel (neighbours outside the grid are
+    outside the crop as well)."""
+    import torch
+    cfg = synth.PAPER_SHAPED
+    nx, nz = cfg.n, synth.PAPER_SHAPED_NZ
+    views = synth.helix_trajectory(cfg.n_views, cfg.pixel)[::100]
+    g = oracle.Geom(nx, nx, nz, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views)
+    say("paper-shaped volume ops sampled parity", g.vol_shape)
+    rng = np.random.Generator(np.random.PCG64(15))
+    ctx = context(g)
+    x = rng.random(g.vol_shape, dtype=np.float32) * 0.2
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xt)
+    ctx.bilateral(xt, out, 1.0, 0.05)
+    got = out.cpu().numpy()
+    idx = np.stack([rng.integers(0, nz, 300), rng.integers(0, nx, 300), rng.integers(0, nx, 300)], 1)
+    idx = np.concatenate([idx, [[nz - 1, nx - 1, nx - 1], [0, 0, 0], [nz - 1, 0, nx - 1], [0, nx - 1, 0]]])
+    ref, gv = np.empty(len(idx)), np.empty(len(idx))
+    for k, (z, y, xx) in enumerate(idx):
+        z0, y0, x0 = max(z - 1, 0), max(y - 1, 0), max(xx - 1, 0)
+        crop = x[z0:z + 2, y0:y + 2, x0:xx + 2].astype(np.float64)
+        ref[k] = oracle.bilateral(crop, 1.0, 0.05)[z - z0, y - y0, xx - x0]
+        gv[k] = got[z, y, xx]
+    e1 = rel_l2(gv, ref)
+    del got, out
+    ctx.soft_threshold(xt, 0.1)
+    got = xt.cpu().numpy()
+    sel = (idx[:, 0], idx[:, 1], idx[:, 2])
+    e2 = rel_l2(got[sel].astype(np.float64), oracle.soft_threshold(x[sel].astype(np.float64), 0.1))
+    say("  bilateral rel L2", e1, " soft threshold rel L2", e2)
+    assert e1 <= 1e-5 and e2 <= 1e-5
