@@ -109,11 +109,13 @@ __device__ float2 *fft_lines(float2 *src, float2 *dst, int logN, int B, const fl
 }
 
 struct LineMap {
-    long es;           // element stride
-    long inner_count;  // lines are (outer, inner); base = outer*outer_stride + inner*inner_stride
-    long inner_stride;
+    long es;         // element stride
+    int inner_log;   // lines are (outer, inner) with 2^inner_log inner lines per outer one;
+    long inner_stride;  // base = outer*outer_stride + inner*inner_stride (shifts: every edge is a power of two)
     long outer_stride;
-    __device__ long base(long L) const { return (L / inner_count) * outer_stride + (L % inner_count) * inner_stride; }
+    __device__ long base(long L) const {
+        return (L >> inner_log) * outer_stride + (L & ((1L << inner_log) - 1)) * inner_stride;
+    }
 };
 
 struct RadialH {
@@ -122,14 +124,16 @@ struct RadialH {
     float rho_max;
     int nx, ny, nz;
     const float *hk;  // when set: the transfer function itself, [ez][ey][ex]
+    int lognx, logny, lognz;
 };
 
 __device__ __forceinline__ float radial_gain(const RadialH &R, int ex, int ey, int ez) {
     if (R.hk) return R.hk[((long)ez * R.ny + ey) * R.nx + ex];
-    const int kx = ex < R.nx / 2 ? ex : ex - R.nx;
-    const int ky = ey < R.ny / 2 ? ey : ey - R.ny;
-    const int kz = ez < R.nz / 2 ? ez : ez - R.nz;
-    const float fx = (float)kx / R.nx, fy = (float)ky / R.ny, fz = (float)kz / R.nz;
+    const int kx = ex < (R.nx >> 1) ? ex : ex - R.nx;
+    const int ky = ey < (R.ny >> 1) ? ey : ey - R.ny;
+    const int kz = ez < (R.nz >> 1) ? ez : ez - R.nz;
+    // k / n as an exact scaling by 2^-log n (n is a power of two)
+    const float fx = ldexpf((float)kx, -R.lognx), fy = ldexpf((float)ky, -R.logny), fz = ldexpf((float)kz, -R.lognz);
     const float rho = 2.f * sqrtf(fx * fx + fy * fy + fz * fz);
     float t = rho / R.rho_max * (float)(R.n_table - 1);
     if (t >= (float)(R.n_table - 1)) return R.table[R.n_table - 1];
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(const float *__restrict__ in_r
         for (int q = threadIdx.x; q < total; q += blockDim.x) {
             const int l = q >> logN, e = q & (N - 1);
             const long L = L0 + l;
-            const int ex = (int)(L % R.nx), ey = (int)(L / R.nx);
+            const int ex = (int)(L & (R.nx - 1)), ey = (int)(L >> R.lognx);
             const float hgain = radial_gain(R, ex, ey, e);
             res[q] = make_float2(res[q].x * hgain, res[q].y * hgain);
         }
@@ -191,8 +195,8 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
                                 bool forward_only) {
     // tw_all holds the twiddles for nx, then ny, then nz (nx/2 + ny/2 + nz/2 entries)
     const float2 *twx = tw_all, *twy = tw_all + nx / 2, *twz = tw_all + nx / 2 + ny / 2;
-    RadialH R{table, n_table, rho_max, nx, ny, nz, hk};
-    RadialH none{nullptr, 0, 1.f, nx, ny, nz, nullptr};
+    RadialH R{table, n_table, rho_max, nx, ny, nz, hk, ilog2(nx), ilog2(ny), ilog2(nz)};
+    RadialH none{nullptr, 0, 1.f, nx, ny, nz, nullptr, ilog2(nx), ilog2(ny), ilog2(nz)};
     const long nvox = (long)nx * ny * nz;
     // lines per block: as many as fit kFftElems, fewer while that leaves
     // under 2048 blocks (down to 8 lines on strided axes, so that a block's
@@ -213,7 +217,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // pass 1: x, real -> complex
     {
         const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz, false);
-        LineMap m{1, 1L << 40, nx, 0};
+        LineMap m{1, 40, nx, 0};
         const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
         k_fft_pass<true, true, false, false>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
@@ -222,7 +226,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // pass 2: y forward
     {
         const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz, true);
-        LineMap m{nx, nx, 1, (long)nx * ny};
+        LineMap m{nx, ilog2(nx), 1, (long)nx * ny};
         const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
         k_fft_pass<false, false, false, false>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
@@ -231,7 +235,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     if (forward_only) {
         // pass 3 without the filter: the forward DFT is left in `work`
         const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny, true);
-        LineMap m{(long)nx * ny, 1L << 40, 1, 0};
+        LineMap m{(long)nx * ny, 40, 1, 0};
         const unsigned grid = (unsigned)(((long)nx * ny) >> logB);
         k_fft_pass<false, false, false, false>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
@@ -241,7 +245,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // pass 3: z forward, * H, z inverse
     {
         const int logN = ilog2(nz), logB = pick_B(nz, (long)nx * ny, true);
-        LineMap m{(long)nx * ny, 1L << 40, 1, 0};
+        LineMap m{(long)nx * ny, 40, 1, 0};
         const unsigned grid = (unsigned)(((long)nx * ny) >> logB);
         k_fft_pass<false, false, false, true>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
@@ -250,7 +254,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // pass 4: y inverse
     {
         const int logN = ilog2(ny), logB = pick_B(ny, (long)nx * nz, true);
-        LineMap m{nx, nx, 1, (long)nx * ny};
+        LineMap m{nx, ilog2(nx), 1, (long)nx * ny};
         const unsigned grid = (unsigned)(((long)nx * nz) >> logB);
         k_fft_pass<false, false, false, false>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
@@ -259,7 +263,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // pass 5: x inverse -> real, scaled
     {
         const int logN = ilog2(nx), logB = pick_B(nx, (long)ny * nz, false);
-        LineMap m{1, 1L << 40, nx, 0};
+        LineMap m{1, 40, nx, 0};
         const unsigned grid = (unsigned)(((long)ny * nz) >> logB);
         k_fft_pass<true, false, true, false>
             <<<grid, threads_of(logN, logB), lds_of(logN, logB), s>>>(
