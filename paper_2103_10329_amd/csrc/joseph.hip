@@ -234,7 +234,8 @@ __global__ void k_emtr_update_pairs(float *__restrict__ vol, const float *__rest
             m += num[i] / d;
             vol[i] = m;
         }
-        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((size_t)nx * ny));
+        int x, y, z;
+        split3(i, nx, ny, x, y, z);
         const long ox = (((long)(x + kVolPad) * PY + (y + kVolPad)) * PZ + (z + kVolPad)) * 2;
         store_f(vtx, ox, m);
         store_f(vtx, ox - 2 * PZ + 1, m);

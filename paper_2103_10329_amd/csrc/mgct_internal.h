@@ -134,6 +134,16 @@ struct KernelTimer {
 // ----- host helpers (api.cpp / geometry.cpp)
 int build_level(Ctx &c, int g, Level &out);  // fills host+device tables
 void free_level(Level &L);
+// (x, y, z) of a linear index i of an [nz][ny][nx] array in 32-bit unsigned
+// arithmetic (a 64-bit division costs several times as many instructions);
+// every array here holds fewer than 2^32 elements.
+__device__ __forceinline__ void split3(size_t i, int nx, int ny, int &x, int &y, int &z) {
+    const unsigned u = (unsigned)i, t = u / (unsigned)nx;
+    x = (int)(u - t * (unsigned)nx);
+    y = (int)(t % (unsigned)ny);
+    z = (int)(t / (unsigned)ny);
+}
+
 int check_geometry(int nx, int ny, int nz, double h, const double *origin, int nu, int nv, int nviews,
                    const double *views);
 

@@ -198,7 +198,8 @@ __global__ __launch_bounds__(256) void k_stencil27(const float *in, float *out, 
                                                    const float *__restrict__ taps) {
     const size_t n = (size_t)nx * ny * nz;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((size_t)nx * ny));
+        int x, y, z;
+        split3(idx, nx, ny, x, y, z);
         // FP64 accumulation: a zero-DC kernel applied to a smooth field is a
         // difference of nearly equal sums, so FP32 would lose digits here.
         double acc = 0.0;
@@ -238,7 +239,8 @@ __global__ __launch_bounds__(256) void k_bilateral(const float *__restrict__ in,
     // index itself fits 32 bits
     for (long li = blockIdx.x * (long)blockDim.x + threadIdx.x; li < n; li += (long)gridDim.x * blockDim.x) {
         const int idx = (int)li;
-        const int x = idx % nx, t = idx / nx, y = t % ny, z = t / ny;
+        int x, y, z;
+        split3(li, nx, ny, x, y, z);
         const float c = in[idx];
         float num = 0.f, den = 0.f;
 #pragma unroll
@@ -270,7 +272,8 @@ __global__ void k_restrict_vol(const float *f, float *c, int nx, int ny, int nz)
     const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     const size_t n = (size_t)cx * cy * cz;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(idx % cx), y = (int)((idx / cx) % cy), z = (int)(idx / ((size_t)cx * cy));
+        int x, y, z;
+        split3(idx, cx, cy, x, y, z);
         float acc = 0.f;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
@@ -292,7 +295,8 @@ __global__ void k_restrict_stack(const float *f, float *c, int nviews, int nv, i
     const int cu = nu / 2, cv = nv / 2;
     const size_t n = (size_t)nviews * cu * cv;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const int a = (int)(idx % cu), b = (int)((idx / cu) % cv), v = (int)(idx / ((size_t)cu * cv));
+        int a, b, v;
+        split3(idx, cu, cv, a, b, v);
         const float *r0 = f + ((size_t)v * nv + 2 * b) * nu + 2 * a;
         const float *r1 = r0 + nu;
         c[idx] = 0.25f * ((r0[0] + r0[1]) + (r1[0] + r1[1]));
@@ -315,7 +319,8 @@ __global__ void k_prolong_add(const float *cn, const float *co, float *f, int nx
     const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     const size_t n = (size_t)nx * ny * nz;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((size_t)nx * ny));
+        int x, y, z;
+        split3(idx, nx, ny, x, y, z);
         int x0, x1, y0, y1, z0, z1;
         float wx, wy, wz;
         prolong_taps(x, cx, x0, x1, wx);
