@@ -313,10 +313,10 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 # measured on.
 TRAFFIC = {
     # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "883b20d1f5c19920eb742a87862ab630fdb4c0c4ce2409824328862be86ccb89",
-                          "bytes_per_launch": 407852319, "valu_issue": 0.85, "l2_hit": 0.958},
-    "k_project_sep": {"source_sha256": "883b20d1f5c19920eb742a87862ab630fdb4c0c4ce2409824328862be86ccb89",
-                       "bytes_per_launch": 7171321527, "valu_issue": 0.71, "l2_hit": 0.494},
+    "k_backproject_pl": {"source_sha256": "f23a0e9827bc880d5623e26b67b0ee4243ea940c2f3dfa25edbb20a1941cb161",
+                          "bytes_per_launch": 407438624, "valu_issue": 0.86, "l2_hit": 0.958},
+    "k_project_sep": {"source_sha256": "f23a0e9827bc880d5623e26b67b0ee4243ea940c2f3dfa25edbb20a1941cb161",
+                       "bytes_per_launch": 7172105892, "valu_issue": 0.71, "l2_hit": 0.495},
 }
 
 
