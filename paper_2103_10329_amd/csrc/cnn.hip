@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ u, 
     const long n = (long)d.nx * d.ny * d.nz;
     const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+    int x, y, z;
+    split3(v, d.nx, d.ny, x, y, z);
     float in[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) {
@@ -99,7 +100,8 @@ __global__ __launch_bounds__(256) void k_conv4_fwd(const uint16_t *__restrict__ 
     const long n = (long)d.nx * d.ny * d.nz;
     const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+    int x, y, z;
+    split3(v, d.nx, d.ny, x, y, z);
     float acc = w[kB4];
     for (int t = 0; t < 27; ++t) {
         long q;
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(256) void k_conv4_bwd_input(const float *__restrict
     const long v = vb + threadIdx.x;
     float o[32];
     if (v < n) {
-        const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long)d.nx * d.ny));
+        int x, y, z;
+        split3(v, d.nx, d.ny, x, y, z);
         float g[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
@@ -305,7 +308,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ 
     const long wave = blockIdx.x * 4L + (threadIdx.x >> 6);
     const int nxt = d.nx / 32, nyt = (d.ny + NT - 1) / NT;
     if (wave >= (long)nxt * nyt * d.nz) return;  // whole wave; no barrier below
-    const int xt = (int)(wave % nxt), yt = (int)((wave / nxt) % nyt), z = (int)(wave / ((long)nxt * nyt));
+    int xt, yt, z;
+    split3(wave, nxt, nyt, xt, yt, z);
     const int x0 = xt * 32, y0 = yt * NT;
     const int m = lane & 31, kh = lane >> 5;
     floatx16 acc[NT];
@@ -373,7 +377,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma_lds(const uint16_t *__restric
     extern __shared__ uint16_t xs[];  // [3][SY][34][CP]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nxt = d.nx / 32, nyb = (d.ny + YB - 1) / YB;
-    const int xt = (int)(blockIdx.x % nxt), yb = (int)((blockIdx.x / nxt) % nyb), z = (int)(blockIdx.x / ((long)nxt * nyb));
+    int xt, yb, z;
+    split3(blockIdx.x, nxt, nyb, xt, yb, z);
     const int x0 = xt * 32, y0 = yb * YB;
     // stage: (zz, yy, xx) voxels of CI channels as CI / 8 chunks of 16 bytes
     constexpr int CH = CI / 8, NV = 3 * SY * 34;
@@ -451,7 +456,8 @@ __global__ void k_to_cf_padded(const uint16_t *__restrict__ x, uint16_t *__restr
     if (i >= n * C) return;
     const long v = i / C;
     const int c = (int)(i % C);
-    const int xx = (int)(v % d.nx), yy = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long)d.nx * d.ny));
+    int xx, yy, zz;
+    split3(v, d.nx, d.ny, xx, yy, zz);
     const long PX = d.nx + 2, PY = d.ny + 2, PZ = d.nz + 2;
     xt[(((long)c * PZ + zz + 1) * PY + yy + 1) * PX + xx + 1] = x[i];
 }
