@@ -50,7 +50,7 @@ typedef enum {
     MGCT_ERR_SIZE_NOT_DIVISIBLE = -3,   /* a size not divisible by 2^level */
     MGCT_ERR_OOM = -4,                  /* device allocation failed */
     MGCT_ERR_HIP = -5,                  /* a HIP runtime call failed */
-    MGCT_ERR_DIVERGED = -6,             /* the residual grew: step size too large */
+    MGCT_ERR_DIVERGED = -6,             /* the residual grew or is not finite: step size too large */
     MGCT_ERR_NOT_IMPLEMENTED = -7,      /* combination not provided (e.g. radial filter on non-power-of-2 grid) */
     MGCT_ERR_NO_GEOMETRY = -8           /* mgct_set_geometry has not been called */
 } mgct_status;
@@ -125,6 +125,8 @@ int mgct_destroy(void *ctx);
  * The library copies what it needs.  Rejects (UNSUPPORTED_GEOMETRY) any
  * geometry with a ray whose largest |direction component| is along z, and
  * any geometry whose source lies within one voxel of the volume box.
+ * Synchronises the device.  A new grid shape (nx, ny, nz) releases the
+ * context's device workspaces; the same shape with other views keeps them.
  */
 int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const double origin[3],
                       int nu, int nv, int n_views, const double *views);
@@ -177,10 +179,31 @@ int mgct_estimate_step(void *ctx, int level, const mgct_filter *f, int iters, ui
  * One Landweber step on grid `level`: vol += alpha * p * A^T (b - A vol)
  * (eq. 4; f NULL or IDENTITY gives SIRT, eq. 2).  vol: device F32, updated in
  * place.  b: device stack of that grid, F32 or F16.  resid_norm: host, may be
- * NULL; receives ||b - A vol|| of the input volume (FP64 reduction).
+ * NULL; receives ||b - A vol|| of the input volume (FP64 reduction) and then
+ * synchronises the stream.
+ * Divergence (Sec. 2.1, eq. 2's step alpha): p is positive semi-definite, so
+ * for alpha <= 2/lambda_max(p A^T A) the residual cannot grow from one step to
+ * the next, on consistent or inconsistent data.  With resid_norm given, the
+ * call returns MGCT_ERR_DIVERGED (after the step has been applied) when the
+ * residual is not finite, or when it exceeds the previous call's on the same
+ * grid, data pointer, alpha and filter by more than the context's ratio
+ * (mgct_set_divergence, default 1.05): alpha exceeds 2/lambda_max.
  */
 int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_dtype, double alpha,
                         const mgct_filter *f, double *resid_norm, hipStream_t stream);
+
+/*
+ * Ratio of the divergence test of mgct_landweber_step and
+ * mgct_multigrid_solve: >= 1, or 0 to report only non-finite residuals.
+ * Resets the Landweber steps' residual history.  Host only.
+ */
+int mgct_set_divergence(void *ctx, double ratio);
+
+/*
+ * The divergence rule itself (host only, no device access): 1 when cur is not
+ * finite, or when ratio > 0, prev > 0 and cur > ratio * prev; else 0.
+ */
+int mgct_residual_diverged(double prev, double cur, double ratio);
 
 /*
  * Geometry derivative for joint model estimation (paper Sec. 1: geometry
@@ -281,7 +304,12 @@ int mgct_osemtr(void *ctx, int level, float *vol, const float *b, int subsets, i
  * in place, finest grid).  b: device stack of the finest grid (F32 or F16).
  * resid_hist: host, may be NULL, n_outer x levels doubles: entry [n][g] is
  * ||b_g - A_g mu|| before grid g's Landweber step (g < L-1) and, for
- * g = L-1, before the coarse OS-EMTR solve.
+ * g = L-1, before the coarse OS-EMTR solve.  With resid_hist given the
+ * call synchronises the stream and returns MGCT_ERR_DIVERGED (after all
+ * iterations) when a recorded residual is not finite or the finest grid's
+ * grows between consecutive outer iterations by more than the divergence
+ * ratio (mgct_set_divergence).  Automatic step sizes are cached per grid
+ * and filter; a TRANSFER filter is identified by its array's contents.
  */
 int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, const mgct_mg_params *p,
                          double *resid_hist, hipStream_t stream);

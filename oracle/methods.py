@@ -374,19 +374,22 @@ def transfer_from_spectrum(T: np.ndarray, floor_rel: float) -> np.ndarray:
 
 
 def radial_profile(T: np.ndarray, n_table: int, rho_max: float):
-    """Mean of T over each shell of frequencies whose rho = 2 |k/N| (signed
-    frequencies) rounds to sample i of n_table on [0, rho_max]; rho and the
-    rounding are evaluated in FP32 as the library does, so both sides assign
-    every frequency to the same shell.  Returns (means with NaN for empty
-    shells, counts).  parity pinned: constants, rho itself."""
+    """Mean of T over each shell of frequencies: the frequency with signed
+    indices k_a in [-N_a/2, N_a/2) has rho = 2 sqrt(sum_a (k_a/N_a)^2) (the
+    radial coordinate of the Fourier filter, Sec. 3's approximate
+    deconvolution) and belongs to the shell of the nearest of n_table
+    uniform samples of [0, rho_max], i.e. floor(rho / rho_max (n_table-1)
+    + 1/2); frequencies beyond the last sample are left out.  rho and the
+    shell index are evaluated in FP64 from that definition.  Returns (means
+    with NaN for empty shells, counts).  parity pinned: shell means of
+    constants and of rho itself, counts against a brute-force enumeration."""
     nz, ny, nx = T.shape
     def signed(n):
         k = np.arange(n)
-        return np.where(k < n // 2, k, k - n).astype(np.float32) / np.float32(n)
+        return np.where(k < n // 2, k, k - n).astype(np.float64) / float(n)
     fz, fy, fx = np.meshgrid(signed(nz), signed(ny), signed(nx), indexing="ij")
-    rho = np.float32(2.0) * np.sqrt(fx * fx + fy * fy + fz * fz, dtype=np.float32)
-    t = rho / np.float32(rho_max) * np.float32(n_table - 1)
-    b = (t + np.float32(0.5)).astype(np.int64)
+    rho = 2.0 * np.sqrt(fx * fx + fy * fy + fz * fz)
+    b = np.floor(rho / float(rho_max) * (n_table - 1) + 0.5).astype(np.int64)
     keep = b < n_table
     sums = np.bincount(b[keep], weights=T[keep].astype(np.float64), minlength=n_table)
     cnt = np.bincount(b[keep], minlength=n_table)

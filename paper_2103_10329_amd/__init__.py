@@ -78,6 +78,8 @@ SIGNATURES = {
     "mgct_precondition": (_ci, [_vp, _ci, _vp, _vp, _fp, _vp]),
     "mgct_estimate_step": (_ci, [_vp, _ci, _fp, _ci, _u64, _dp, _vp]),
     "mgct_landweber_step": (_ci, [_vp, _ci, _vp, _vp, _ci, _cd, _fp, _dp, _vp]),
+    "mgct_set_divergence": (_ci, [_vp, _cd]),
+    "mgct_residual_diverged": (_ci, [_cd, _cd, _cd]),
     "mgct_psf_spectrum": (_ci, [_vp, _ci, _vp, _vp]),
     "mgct_transfer_from_spectrum": (_ci, [_vp, _ci, _vp, _cd, _vp, _vp]),
     "mgct_radial_profile": (_ci, [_vp, _ci, _vp, _ci, _cd, _dp, ctypes.POINTER(_ci), _vp]),
@@ -309,6 +311,10 @@ class Context:
                                   ctypes.byref(r) if want_norm else None, _stream()), "mgct_landweber_step")
         return r.value if want_norm else None
 
+    def set_divergence(self, ratio: float):
+        """Ratio of the divergence test (>= 1, or 0: non-finite residuals only)."""
+        check(mgct_set_divergence(self.handle, float(ratio)), "mgct_set_divergence")  # noqa: F821
+
     def restrict_volume(self, fine, coarse, level: int = 0):
         check(mgct_restrict_volume(self.handle, level, _ptr(fine), _ptr(coarse), _stream()),  # noqa: F821
               "mgct_restrict_volume")
@@ -488,6 +494,13 @@ class Context:
         check(mgct_multigrid_solve(self.handle, _ptr(vol), _ptr(b), _dtype_code(b), ctypes.byref(p), hp,  # noqa: F821
                                    _stream()), "mgct_multigrid_solve")
         return hist[: n_outer * levels].reshape(n_outer, levels) if want_hist else None
+
+
+def residual_diverged(prev: float, cur: float, ratio: float) -> bool:
+    """The library's divergence rule (host only): cur not finite, or
+    ratio > 0, prev > 0 and cur > ratio * prev."""
+    load_library()
+    return bool(mgct_residual_diverged(float(prev), float(cur), float(ratio)))  # noqa: F821
 
 
 def geometry_param_grad(views0, dviews, voxel, dx, dz, tilt_deg) -> np.ndarray:

@@ -21,6 +21,10 @@ class _ProjectFn(torch.autograd.Function):
         _sync_geometry(mctx, views)
         fctx.mctx = mctx
         fctx.level = level
+        # the geometry this node projected with: backward restores it, so that
+        # other projections between forward and backward cannot change it
+        fctx.geom = dict(mctx.geom)
+        fctx.views_np = mctx._views_np.copy()
         fctx.save_for_backward(vol)
         return mctx.project(vol.contiguous(), level=level)
 
@@ -28,6 +32,7 @@ class _ProjectFn(torch.autograd.Function):
     def backward(fctx, grad_out):
         (vol,) = fctx.saved_tensors
         mctx, level = fctx.mctx, fctx.level
+        _sync_geometry(mctx, fctx.views_np, fctx.geom)
         g = grad_out.contiguous().float()
         g_vol = g_views = None
         if fctx.needs_input_grad[0]:
@@ -38,11 +43,15 @@ class _ProjectFn(torch.autograd.Function):
         return g_vol, g_views, None, None
 
 
-def _sync_geometry(mctx: Context, views) -> None:
-    v = views.detach().cpu().double().numpy() if isinstance(views, torch.Tensor) else np.asarray(views)
+def _sync_geometry(mctx: Context, views, geom=None) -> None:
+    """Make the context hold ``views`` (and the grid ``geom``, default: the
+    context's current grid)."""
+    v = views.detach().cpu().double().numpy() if isinstance(views, torch.Tensor) else np.asarray(views, dtype=np.float64)
+    g = dict(mctx.geom) if geom is None else geom
     cur = getattr(mctx, "_views_np", None)
-    if cur is None or cur.shape != v.shape or not np.array_equal(cur, v):
-        g = mctx.geom
+    same_grid = all(mctx.geom.get(k) == g.get(k) for k in ("nx", "ny", "nz", "voxel", "nu", "nv")) and \
+        tuple(mctx.geom.get("origin", (0.0, 0.0, 0.0))) == tuple(g.get("origin", (0.0, 0.0, 0.0)))
+    if cur is None or not same_grid or cur.shape != v.shape or not np.array_equal(cur, v):
         mctx.set_geometry(g["nx"], g["ny"], g["nz"], g["voxel"], g.get("origin", (0.0, 0.0, 0.0)),
                           g["nu"], g["nv"], v)
         mctx._views_np = v.copy()

@@ -16,6 +16,7 @@
 
 using namespace mgct;
 
+
 #define HIPCHK(x)                                  \
     do {                                           \
         hipError_t e_ = (x);                       \
@@ -423,22 +424,43 @@ int do_osemtr(Ctx &c, Level &L, int g, float *vol, const float *b, int M, int pa
     return MGCT_OK;
 }
 
-std::string filter_key(const mgct_filter *f) {
+// Key of a filter for the step-size cache.  A TRANSFER filter is keyed by the
+// contents of grid g's array (an order-independent 64-bit hash computed on the
+// device), not by its address: a new H(k) at the same address, or one
+// rewritten in place, must not reuse an old step size.
+int filter_key(Ctx &c, const mgct_filter *f, int g, const Level &L, hipStream_t s, std::string *out) {
     std::ostringstream o;
-    if (!f || f->kind == MGCT_FILTER_IDENTITY) return "id";
+    if (!f || f->kind == MGCT_FILTER_IDENTITY) {
+        *out = "id";
+        return MGCT_OK;
+    }
     o << f->kind << ":";
-    if (f->kind == MGCT_FILTER_STENCIL27)
+    if (f->kind == MGCT_FILTER_STENCIL27) {
         for (int i = 0; i < 27; ++i) o << f->taps[i] << ",";
-    else if (f->kind == MGCT_FILTER_TRANSFER)
-        for (int i = 0; i < 8; ++i) o << (const void *)f->transfer[i] << ",";  // by array, not contents
-    else {
+    } else if (f->kind == MGCT_FILTER_TRANSFER) {
+        constexpr int kHashBlocks = 256;
+        WS(part, unsigned long long, "hash_partials", kHashBlocks * 8, false);
+        WS(hd, unsigned long long, "hash_out", 8, false);
+        HIPCHK(launch_hash_words(f->transfer[g], L.vox(), part, kHashBlocks, hd, s));
+        unsigned long long h = 0;
+        HIPCHK(hipMemcpyAsync(&h, hd, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        o << L.vox() << "," << h;
+    } else {
         o << f->n_table << "," << f->rho_max << ",";
         uint64_t hsh = 1469598103934665603ull;
         const unsigned char *p = (const unsigned char *)f->radial_table;
         for (size_t i = 0; i < (size_t)f->n_table * 4; ++i) hsh = (hsh ^ p[i]) * 1099511628211ull;
         o << hsh;
     }
-    return o.str();
+    *out = o.str();
+    return MGCT_OK;
+}
+
+// Divergence rule shared by the Landweber step and the multigrid solve.
+bool diverged(double prev, double cur, double ratio) {
+    if (!isfinite(cur)) return true;
+    return ratio > 0.0 && prev > 0.0 && cur > ratio * prev;
 }
 
 int do_estimate(Ctx &c, Level &L, int g, const mgct_filter *f, int iters, uint64_t seed, double *alpha,
@@ -678,7 +700,7 @@ const char *mgct_status_string(int st) {
         case MGCT_ERR_SIZE_NOT_DIVISIBLE: return "size not divisible by 2^level";
         case MGCT_ERR_OOM: return "device allocation failed";
         case MGCT_ERR_HIP: return "HIP runtime error";
-        case MGCT_ERR_DIVERGED: return "iteration diverged (non-positive or non-finite spectrum estimate)";
+        case MGCT_ERR_DIVERGED: return "iteration diverged (residual grew or is not finite, or no positive spectrum estimate)";
         case MGCT_ERR_NOT_IMPLEMENTED: return "not implemented for these arguments";
         case MGCT_ERR_NO_GEOMETRY: return "no geometry set";
         default: return "unknown status";
@@ -782,6 +804,15 @@ int mgct_set_geometry(void *ctx, int nx, int ny, int nz, double voxel, const dou
         free_level(L);
         L = Level();
     }
+    // The projector's padded volume copies rely on zero borders that are
+    // written only when a workspace is first allocated; another grid shape
+    // would place earlier interior voxels in the new borders.  A change of
+    // shape therefore releases every workspace (the same shape keeps them).
+    if (!c.has_geom || c.nx != nx || c.ny != ny || c.nz != nz) {
+        for (auto &w : c.ws) (void)hipFree(w.second.first);
+        c.ws.clear();
+    }
+    for (auto &ch : c.lw_chain) ch = Ctx::LwChain();
     c.alpha_cache.clear();
     for (bool &v : c.pi_valid) v = false;
     c.nx = nx; c.ny = ny; c.nz = nz; c.nu = nu; c.nv = nv; c.nviews = n_views;
@@ -857,9 +888,32 @@ int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_d
         HIPCHK(hipMemcpyAsync(&v, d, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         *resid_norm = sqrt(v);
+        // eq. 2 / eq. 4 with p positive semi-definite: for alpha <= 2/lambda_max
+        // the residual cannot grow from one step to the next
+        std::string fk;
+        MGCHK(filter_key(c, f, level, *L, s, &fk));
+        Ctx::LwChain &ch = c.lw_chain[level];
+        const bool same = ch.valid && ch.b == b && ch.alpha == alpha && ch.filter == fk;
+        const bool bad = diverged(same ? ch.prev : 0.0, *resid_norm, c.diverge_ratio);
+        ch.valid = true;
+        ch.b = b;
+        ch.alpha = alpha;
+        ch.filter = fk;
+        ch.prev = *resid_norm;
+        if (bad) return MGCT_ERR_DIVERGED;
     }
     return MGCT_OK;
 }
+
+int mgct_set_divergence(void *ctx, double ratio) {
+    if (!ctx || !(ratio == 0.0 || ratio >= 1.0) || !isfinite(ratio)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    c.diverge_ratio = ratio;
+    for (auto &ch : c.lw_chain) ch = Ctx::LwChain();
+    return MGCT_OK;
+}
+
+int mgct_residual_diverged(double prev, double cur, double ratio) { return diverged(prev, cur, ratio) ? 1 : 0; }
 
 int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *cot, double *dviews, hipStream_t s) {
     if (!ctx || !vol || !cot || !dviews) return MGCT_ERR_INVALID_ARG;
@@ -1051,8 +1105,10 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
             alpha[g] = p->alpha[g];
             continue;
         }
-        std::string key = std::to_string(g) + "|" + filter_key(&p->filter) + "|" + std::to_string(p->power_iters) +
-                          "|" + std::to_string(p->power_seed);
+        std::string fk;
+        MGCHK(filter_key(c, &p->filter, g, *Ls[g], s, &fk));
+        std::string key = std::to_string(g) + "|" + fk + "|" + std::to_string(p->power_iters) + "|" +
+                          std::to_string(p->power_seed);
         auto it = c.alpha_cache.find(key);
         if (it != c.alpha_cache.end()) {
             alpha[g] = it->second;
@@ -1142,8 +1198,15 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
         HIPCHK(hipMemcpyAsync(h.data(), dh, nh * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int i = 0; i < nh; ++i) resid_hist[i] = sqrt(h[i]);
+        // the fine grid's residual between outer iterations, and every
+        // recorded residual's finiteness
+        for (int i = 0; i < nh; ++i)
+            if (!isfinite(resid_hist[i])) return MGCT_ERR_DIVERGED;
+        for (int n = 1; n < p->n_outer; ++n)
+            if (diverged(resid_hist[(n - 1) * NL], resid_hist[n * NL], c.diverge_ratio)) return MGCT_ERR_DIVERGED;
     }
     return MGCT_OK;
 }
 
 }  // extern "C"
+

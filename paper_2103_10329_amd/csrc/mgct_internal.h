@@ -114,6 +114,17 @@ struct Ctx {
     // storage of the Landweber steps' internal copies: the projector's
     // volume copy (F32 or BF16) and the data/residual stacks (F32 or F16)
     int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
+    // divergence status: a Landweber step whose input residual exceeds the
+    // previous step's (same grid, data, step size and filter) by more than
+    // this factor, or a multigrid solve whose fine-grid residual grows by it
+    // between outer iterations, reports MGCT_ERR_DIVERGED; 0 disables
+    double diverge_ratio = 1.05;
+    struct LwChain {
+        bool valid = false;
+        const void *b = nullptr;
+        double alpha = 0.0, prev = 0.0;
+        std::string filter;
+    } lw_chain[kMaxLevels];
     CnnState cnn;
     bool timing = false;
     unsigned timing_ops = ~0u, timing_levels = ~0u;  // which (op, grid) pairs are recorded
@@ -220,6 +231,10 @@ hipError_t launch_emtr_terms_t(const float *l, const float *y, const float *pi, 
 hipError_t launch_emtr_reduce(const float *part_num, const float *part_den, float *num, float *den, size_t n,
                               int nchunks, unsigned *maxbits, hipStream_t s);
 hipError_t launch_splitmix_uniform(float *x, size_t n, uint64_t seed, hipStream_t s);
+// order-independent 64-bit content key of n_words 32-bit words (partials:
+// nblocks values of scratch); out: one device value
+hipError_t launch_hash_words(const void *x, size_t n_words, unsigned long long *partials, int nblocks,
+                             unsigned long long *out, hipStream_t s);
 
 hipError_t launch_scale(const float *x, float *y, float a, size_t n, hipStream_t s);
 hipError_t launch_add(const float *x, const float *y, float *out, size_t n, hipStream_t s);

@@ -416,3 +416,48 @@ hipError_t launch_splitmix_uniform(float *x, size_t n, uint64_t seed, hipStream_
 }
 
 }  // namespace mgct
+
+namespace mgct {
+
+// Content key of an array of 32-bit words: the sum, modulo 2^64, of the
+// SplitMix64 finaliser applied to (word + (i+1) * golden ratio) over all
+// words i.  The sum is order-independent, so the blocks' partial sums may
+// be combined in any order; used to tell apart filter arrays that sit at the
+// same address.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_hash_words(const uint32_t *__restrict__ x, size_t n,
+                                                    unsigned long long *__restrict__ partials) {
+    unsigned long long acc = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        acc += mix64((unsigned long long)x[i] + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull);
+    __shared__ unsigned long long s[256];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+__global__ void k_hash_finish(const unsigned long long *__restrict__ partials, int n, unsigned long long *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < n; ++i) t += partials[i];
+        out[0] = t;
+    }
+}
+
+hipError_t launch_hash_words(const void *x, size_t n_words, unsigned long long *partials, int nblocks,
+                             unsigned long long *out, hipStream_t s) {
+    k_hash_words<<<nblocks, 256, 0, s>>>((const uint32_t *)x, n_words, partials);
+    k_hash_finish<<<1, 64, 0, s>>>(partials, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace mgct

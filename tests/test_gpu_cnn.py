@@ -1,17 +1,39 @@
 """Learned preconditioner network on the matrix cores against the FP64
-oracle.  The GPU keeps BF16 weights for the two 32-output layers and BF16
-activations between layers (FP32 accumulation), so results are compared at
-the level those roundings allow: 2^-9 relative per stored value, compounded
-over four layers."""
+oracle.
+
+Two references: the plain FP64 network (what the method computes), and the
+same oracle layer functions with the library's documented BF16 storage
+roundings applied between them (``cnn_storage``).  The second differs from
+the GPU only by FP32 accumulation order and rare BF16 rounding flips, so the
+forward output, every layer's weight and bias gradient and three Adam steps
+are compared with it at bars a localized kernel error cannot hide under."""
 
 import numpy as np
 import pytest
 
+import cnn_storage
 import paper_2103_10329_amd as mg
 from gpu_common import rel_l2, say, to_dev, to_host
 from oracle import cnn
 
 pytestmark = pytest.mark.gpu
+
+# Bars against the storage-model reference.  What is left after the storage
+# roundings is the BF16 rounding flips that FP32 accumulation order triggers
+# (a value within FP32 error of a BF16 rounding boundary rounds the other way,
+# one BF16 ulp, and the flip propagates through later layers): measured on
+# MI355X forward 1.9e-4 (max 1.2e-3), and the same floor is reproduced on the
+# CPU by evaluating the storage model's convolutions in FP32 (2.2e-4, max
+# 1.1e-3).  The bars sit about 5x above that floor and at least 10x below the
+# deviation of any localized kernel error planted in the storage model on the
+# CPU (one tap of one 8-channel block: >= 4e-2; tests/test_cnn_storage.py).
+FWD_L2, FWD_MAX = 1e-3, 6e-3
+GRAD_L2 = 1e-3
+# Adam: its first steps are about lr * sign(g), so a component whose gradient
+# sits at the flip floor may take the opposite step (|dw| up to 2 lr per step).
+# Measured on MI355X: 14 of 42849 components differ by more than 0.1 lr, the
+# rest agree to 1.1e-3 of the update (L2).  Bars about 5x those.
+ADAM_FLIPS, ADAM_REST_L2 = 64, 5e-3
 
 
 def _setup(shape=(16, 24, 32), seed=5):
@@ -28,30 +50,39 @@ def _setup(shape=(16, 24, 32), seed=5):
     return ctx, params, u, target
 
 
+def _max_rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
 def test_forward_matches_oracle():
     ctx, params, u, _ = _setup()
     out = to_host(ctx.cnn_forward(to_dev(u)))
     ref, _ = cnn.forward(u, params)
-    e = rel_l2(out - u, ref - u)
-    say("cnn forward: rel L2 of f(u)", e)
-    assert e <= 2e-2
+    e_plain = rel_l2(out - u, ref - u)
+    sref, _ = cnn_storage.forward(u, params)
+    u32 = cnn_storage.f32(u)
+    e = rel_l2(out - u32, sref - u32)
+    emax = _max_rel(out - u32, sref - u32)
+    say("cnn forward f(u): rel L2 vs storage model %.3e (max %.3e), vs plain FP64 network %.3e" % (e, emax, e_plain))
+    assert e <= FWD_L2 and emax <= FWD_MAX
+    assert e_plain <= 2e-2
 
 
 def test_gradients_match_oracle():
     ctx, params, u, target = _setup()
     g, loss = ctx.cnn_gradients(to_dev(u), to_dev(target))
-    out, cache = cnn.forward(u, params)
-    lref, dout = cnn.mse(out, target)
-    grads, _ = cnn.backward(cache, dout, params)
-    gref = mg.cnn_unflatten(mg.cnn_flatten(grads))
     gg = mg.cnn_unflatten(g)
+    out, cache = cnn_storage.forward(u, params)
+    lref, dout = cnn.mse(out, target)
+    gref = cnn_storage.backward(cache, dout, params)
     say("cnn loss", loss, lref)
-    assert abs(loss - lref) / lref <= 1e-2
+    assert abs(loss - lref) / lref <= 1e-5
     for li in range(4):
         for pi in range(2):
             e = rel_l2(gg[li][pi], gref[li][pi])
-            say("  layer", li + 1, "W" if pi == 0 else "b", "rel L2", e)
-            assert e <= 5e-2
+            emax = _max_rel(gg[li][pi], gref[li][pi])
+            say("  layer %d %s rel L2 %.3e max %.3e" % (li + 1, "W" if pi == 0 else "b", e, emax))
+            assert e <= GRAD_L2, (li, pi, e)
 
 
 def test_adam_training_reduces_loss():
@@ -60,22 +91,23 @@ def test_adam_training_reduces_loss():
     losses = [ctx.cnn_train_step(ut, tt, 3e-3) for _ in range(40)]
     say("cnn training loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.7 * losses[0]
-    # the same 3 steps on the oracle, from the same start
+    # the same 3 Adam steps under the storage model, from the same start
     ctx2, params2, u2, t2 = _setup(shape=(16, 16, 32), seed=9)
     w0 = mg.cnn_flatten(params2).astype(np.float64)
     st = {}
     for _ in range(3):
-        out, cache = cnn.forward(u2, params2)
+        out, cache = cnn_storage.forward(u2, params2)
         _, dout = cnn.mse(out, t2)
-        gr, _ = cnn.backward(cache, dout, params2)
+        gr = cnn_storage.backward(cache, dout, params2)
         cnn.adam_step(params2, gr, st, lr=3e-3)
     for _ in range(3):
         ctx2.cnn_train_step(to_dev(u2), to_dev(t2), 3e-3, want_loss=False)
-    # Adam's first steps are close to lr * sign(g): compare the updates, whose
-    # error reflects the BF16-level gradient differences (~2e-3 relative) on
-    # components with small gradients
-    dw = ctx2.cnn_get_weights().astype(np.float64) - w0
-    dref = mg.cnn_flatten(params2).astype(np.float64) - w0
-    e = rel_l2(dw, dref)
-    say("Adam update after 3 steps vs oracle", e)
-    assert e <= 5e-2
+    w = ctx2.cnn_get_weights().astype(np.float64)
+    wref = mg.cnn_flatten(params2).astype(np.float64)
+    du, duref = w - w0, wref - w0
+    d = np.abs(du - duref)
+    big = d > 0.1 * 3e-3
+    e_rest = float(np.linalg.norm((du - duref)[~big]) / np.linalg.norm(duref[~big]))
+    say("Adam after 3 steps vs storage model: weights rel L2 %.3e, updates %.3e; %d components beyond 0.1 lr, "
+        "the rest %.3e" % (rel_l2(w, wref), rel_l2(du, duref), int(big.sum()), e_rest))
+    assert int(big.sum()) <= ADAM_FLIPS and e_rest <= ADAM_REST_L2

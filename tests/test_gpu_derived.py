@@ -16,6 +16,17 @@ from gpu_common import context, rel_l2, say, to_dev, to_host, workload
 pytestmark = pytest.mark.gpu
 
 
+def _ambiguous_shells(shape, n_table, rho_max, rel=4e-7):
+    """Lower shell index of every frequency whose shell coordinate
+    t = rho/rho_max (n_table - 1) lies within rel*(t+1) of a half-way point
+    t = i + 1/2 (FP32 evaluation of rho may round it to either side)."""
+    k = [np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n) / n for n in shape]
+    kz, ky, kx = np.meshgrid(*k, indexing="ij")
+    t = 2 * np.sqrt(kx ** 2 + ky ** 2 + kz ** 2) / rho_max * (n_table - 1)
+    near = np.abs((t - 0.5) - np.round(t - 0.5)) <= rel * (t + 1.0)
+    return np.round(t[near] - 0.5).astype(np.int64)
+
+
 def test_transfer_function_and_filter_match_oracle():
     g = workload("c1").level(1)   # 64^3, 360 views of 96^2
     ctx = context(g)
@@ -25,8 +36,22 @@ def test_transfer_function_and_filter_match_oracle():
     n_table, rho_max = 257, math.sqrt(3.0)
     prof, cnt = ctx.radial_profile(T_gpu, n_table=n_table, rho_max=rho_max)
     prof_or, cnt_or = oracle.radial_profile(T_or, n_table, rho_max)
-    assert np.array_equal(cnt, cnt_or)
-    m = cnt > 0
+    # The library places rho in FP32, the oracle in FP64: a frequency whose
+    # shell coordinate lies within FP32 rounding of a half-way point may fall
+    # in either neighbouring shell.  Enumerate those frequencies; counts may
+    # differ only by them, and shell means are compared on the other shells.
+    amb_lo = _ambiguous_shells(g.vol_shape, n_table, rho_max)
+    d = cnt.astype(np.int64) - cnt_or.astype(np.int64)
+    allowed = np.zeros(n_table, dtype=np.int64)
+    np.add.at(allowed, amb_lo, 1)
+    np.add.at(allowed, np.minimum(amb_lo + 1, n_table - 1), 1)
+    assert np.all(np.abs(d) <= allowed), np.nonzero(np.abs(d) > allowed)
+    assert cnt.sum() == cnt_or.sum() or len(amb_lo) > 0
+    touched = np.zeros(n_table, dtype=bool)
+    touched[amb_lo] = True
+    touched[np.minimum(amb_lo + 1, n_table - 1)] = True
+    m = (cnt > 0) & (cnt_or > 0) & ~touched
+    say("shell ambiguity: %d frequencies within FP32 rounding of a shell boundary" % len(amb_lo))
     e_p = rel_l2(prof[m], prof_or[m])
     H_gpu = to_host(ctx.transfer_from_spectrum(T_gpu, 1e-2))
     H_or = oracle.transfer_from_spectrum(T_or, 1e-2)

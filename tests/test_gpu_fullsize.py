@@ -63,7 +63,8 @@ def test_full_size_512_mixed_precision_sampled():
     say("  rays rel L2", e1, "worst ray", worst, " voxels rel L2", e2, " adjoint", e3)
     assert worst <= 2.0 ** -11 + 1e-5
     assert e2 <= 1e-5
-    assert e3 <= 1e-4
+    # measured 1.5e-7 on MI355X (the FP16 roundings of A x average out)
+    assert e3 <= 1e-6
 
 
 def test_full_size_256_tilted_sampled_and_geometry_gradient():
@@ -97,9 +98,11 @@ def test_full_size_256_tilted_sampled_and_geometry_gradient():
     ref = oracle.project_geom_grad(g.subset(idx), x, cot[idx].astype(np.float64))
     e4 = rel_l2(got[idx], ref)
     say("  geometry gradient (6 views) rel L2", e4)
-    # FP32 sums of a few hundred samples per ray with cancellation between
-    # the two sides of each bilinear cell
-    assert e4 <= 1e-4
+    # FP32 samples (tap differences of the bilinear derivative) summed over a
+    # few hundred planes per ray, then over 147456 rays weighted by a random
+    # cotangent, which cancels most of the sum: measured 5.0e-5 on MI355X
+    # (5.5e-8 on the 32^3 crop, tests/test_gpu_geometry.py, bar 1e-5)
+    assert e4 <= 2.5e-4
 
 
 def test_paper_shaped_volume_with_wide_copies():

@@ -86,7 +86,8 @@ def test_mixed_sirt_c0():
         rg = ctx.landweber_step(vol, b, alpha)
     e = rel_l2(to_host(vol), mu)
     say("mixed SIRT x10 vs FP64 oracle", e, "residual", abs(rg - r) / r)
-    assert e <= 5e-3 and abs(rg - r) / r <= 5e-3
+    # measured on MI355X: 1.0e-4 (volume); bars about 5x that
+    assert e <= 5e-4 and abs(rg - r) / r <= 5e-4
 
 
 def test_crop_resolve_mixed_vs_fp64_oracle():
@@ -115,4 +116,5 @@ def test_crop_resolve_mixed_vs_fp64_oracle():
     say("crop re-solve rel L2 vs FP64 oracle: fp32 %.3e (hist %.3e), mixed %.3e (hist %.3e)"
         % (res["fp32"] + res["mixed"]))
     assert res["fp32"][0] <= 1e-5 and res["fp32"][1] <= 1e-5
-    assert res["mixed"][0] <= 1e-2 and res["mixed"][1] <= 1e-2
+    # measured on MI355X: mixed 1.0e-4 (volume); bars about 5x that
+    assert res["mixed"][0] <= 5e-4 and res["mixed"][1] <= 5e-4

@@ -16,8 +16,10 @@ TOL = 1e-5
 
 
 def _geom(nx, ny, nz):
+    """c0's views around a grid of the given shape, voxel at most 0.5 and the
+    box at most 32 units long (the source stays outside)."""
     g = workload("c0")
-    return oracle.Geom(nx, ny, nz, 0.5, (0, 0, 0), g.nu, g.nv, g.views)
+    return oracle.Geom(nx, ny, nz, min(0.5, 32.0 / max(nx, ny, nz)), (0, 0, 0), g.nu, g.nv, g.views)
 
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (70, 29, 37), (8, 8, 8), (3, 4, 5)])
@@ -45,7 +47,13 @@ def test_stencil27_arbitrary_taps():
     assert rel_l2(out, oracle.stencil27(x, taps)) <= TOL
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (64, 64, 64), (128, 128, 128), (16, 32, 64), (64, 8, 2)])
+# Line lengths per stage path of the in-LDS FFT: radix 2 only (<= 64 points),
+# one radix-2 stage then radix 4 (128, 512), radix 4 only (256, 1024); each
+# length appears on every axis somewhere, 256^3 and 512^3 are the filtered
+# grids of the 256^3 and 512^3 workloads.
+@pytest.mark.parametrize("shape", [(32, 32, 32), (64, 64, 64), (128, 128, 128), (16, 32, 64), (64, 8, 2),
+                                   (256, 256, 256), (512, 16, 32), (16, 512, 32), (16, 32, 512),
+                                   (4, 8, 1024), (8, 1024, 4), (1024, 4, 8), (256, 32, 128)])
 def test_radial_filter(shape):
     nz, ny, nx = shape
     g = _geom(nx, ny, nz)
@@ -111,3 +119,19 @@ def test_soft_threshold_and_bilateral():
     assert rel_l2(to_host(out), oracle.bilateral(y, 1.0, 0.05)) <= TOL
     with pytest.raises(mg.MgctError):
         ctx.bilateral(out, out, 1.0, 0.05)
+
+
+def test_transfer_filter_radix4_only_lines():
+    """TRANSFER kind (a per-frequency H(k)) on 256^3: every axis takes the
+    radix-4-only stage path."""
+    shape = (256, 256, 256)
+    g = _geom(256, 256, 256)
+    ctx = context(g)
+    rng = np.random.Generator(np.random.PCG64(7))
+    x = rng.normal(size=shape)
+    H = 0.2 + rng.random(shape)
+    say("transfer", shape)
+    y = to_host(ctx.precondition(to_dev(x), mg.filter_transfer([to_dev(H)])))
+    err = rel_l2(y, oracle.transfer_filter(x, H))
+    say("  rel L2", err)
+    assert err <= TOL

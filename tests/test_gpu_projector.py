@@ -112,15 +112,26 @@ def test_backproject_matches_oracle(case):
 
 
 def test_phantom_projection_c0_close_to_analytic():
+    """Parity on the voxelised phantom, then its distance to the exact chords
+    (a property of the discretisation, not parity): the GPU's distance equals
+    the oracle's, and halving voxel and pixel (64^3, 96^2) shrinks it by at
+    least 1.4x.  Measured with the oracle: 0.0574 at 32^3 and 0.0363 at 64^3
+    (1.58x; the smallest ellipsoids are 2 voxels across at 32^3)."""
     d = synth.make_dataset("c0")
     g = workload("c0")
     ctx = context(g)
     p = to_host(ctx.project(to_dev(d["mu"])))
     ref = oracle.project(g, d["mu"])
     assert rel_l2(p, ref) <= TOL
-    # discretisation error against the exact chords of the phantom (not
-    # parity; the smallest ellipsoids are 2 voxels across)
-    assert rel_l2(p, d["b_true"]) < 0.08
+    e32 = rel_l2(p, d["b_true"])
+    e32_or = rel_l2(ref, d["b_true"])
+    g64 = workload("c0", n=64, nu=96, nv=96)
+    mu64 = synth.voxelize(d["phantom"], 64, g64.h)
+    p64 = to_host(context(g64).project(to_dev(mu64)))
+    e64 = rel_l2(p64, synth.line_integrals(d["phantom"], g64.views, 96, 96))
+    say("distance to exact chords: 32^3 %.4f (oracle %.4f), 64^3 %.4f, ratio %.2f" % (e32, e32_or, e64, e32 / e64))
+    assert abs(e32 - e32_or) <= 0.01 * e32_or
+    assert e64 * 1.4 <= e32
 
 
 def test_full_size_c1_sampled_rays_and_voxels():

@@ -57,3 +57,21 @@ def test_radial_profile_constants_and_rho():
     step = rho_max / (n_table - 1)
     centres = np.arange(n_table) * step
     assert np.all(np.abs(prof[cnt > 0] - centres[cnt > 0]) <= 0.5 * step + 1e-6)
+
+
+def test_radial_profile_counts_by_enumeration():
+    """Shell counts against a plain loop over every frequency with exact
+    rational k/N: shell = nearest sample of [0, rho_max] to rho."""
+    shape = (4, 8, 6)
+    n_table, rho_max = 9, math.sqrt(3.0)
+    prof, cnt = oracle.radial_profile(np.zeros(shape), n_table, rho_max)
+    ref = np.zeros(n_table, dtype=int)
+    for kz in range(shape[0]):
+        for ky in range(shape[1]):
+            for kx in range(shape[2]):
+                f = [(k if k < n // 2 else k - n) / n for k, n in zip((kz, ky, kx), shape)]
+                rho = 2 * math.sqrt(sum(q * q for q in f))
+                best = min(range(n_table), key=lambda i: abs(i * rho_max / (n_table - 1) - rho))
+                if abs(best * rho_max / (n_table - 1) - rho) <= 0.5 * rho_max / (n_table - 1):
+                    ref[best] += 1
+    assert np.array_equal(cnt, ref)

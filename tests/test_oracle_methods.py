@@ -273,3 +273,121 @@ def test_multigrid_single_level_is_one_landweber_step(rng):
     m1, hist = oracle.multigrid(g, mu0, b, levels=1, n_outer=1, filt=f, alphas=[0.003])
     m2, r = oracle.landweber_step(g, mu0, b, 0.003, f)
     assert np.array_equal(m1, m2) and hist[0, 0] == r
+
+
+def test_bilateral_hand_value():
+    """1 x 1 x 3 volume (0, 0.1, 0.3), sigma_s = 0.8, sigma_r = 0.2.  Every
+    neighbour is one voxel away, so its spatial weight is exp(-1/1.28) and its
+    range weight exp(-delta^2/0.08):
+      left end   (0 + 0.1 w1) / (1 + w1),             w1 = exp(-0.78125 - 0.125)
+      middle     (0.1 + 0.3 w2) / (1 + w1 + w2),      w2 = exp(-0.78125 - 0.5)
+      right end  (0.3 + 0.1 w2) / (1 + w2)
+    evaluated by hand to 0.028776781576, 0.108999288453, 0.256532495791.
+    A range term without its factor 2 would give 0.0987 in the middle, |delta|
+    in place of delta^2 0.0952."""
+    x = np.array([0.0, 0.1, 0.3]).reshape(1, 1, 3)
+    out = oracle.bilateral(x, 0.8, 0.2).reshape(-1)
+    assert out == pytest.approx([0.028776781576, 0.108999288453, 0.256532495791], abs=1e-11)
+    # the same line along y and along z gives the same values (isotropic weights)
+    assert np.allclose(oracle.bilateral(x.reshape(1, 3, 1), 0.8, 0.2).reshape(-1), out, atol=1e-15)
+    assert np.allclose(oracle.bilateral(x.reshape(3, 1, 1), 0.8, 0.2).reshape(-1), out, atol=1e-15)
+
+
+# ------------------------------------------------------------- Algorithm 1
+
+def _mg_problem(rng, n=8, n_views=12, nu=8, nv=8):
+    return _tiny_problem(rng, n=n, n_views=n_views, nu=nu, nv=nv)
+
+
+def test_coarse_grid_centres_are_child_means(rng):
+    """The coarse grid of Algorithm 1 keeps s and d and doubles h and the pixel
+    steps: every coarse voxel centre is the mean of its 8 fine children and
+    every coarse pixel centre the mean of its 2 x 2 fine pixels."""
+    g = _mg_problem(rng)
+    c = g.level(1)
+
+    def vox(gg):
+        i = (np.arange(gg.nx) - (gg.nx - 1) / 2) * gg.h + gg.origin[0]
+        j = (np.arange(gg.ny) - (gg.ny - 1) / 2) * gg.h + gg.origin[1]
+        k = (np.arange(gg.nz) - (gg.nz - 1) / 2) * gg.h + gg.origin[2]
+        return i, j, k
+
+    (fi, fj, fk), (ci, cj, ck) = vox(g), vox(c)
+    assert np.allclose(ci, fi.reshape(-1, 2).mean(1), atol=1e-14)
+    assert np.allclose(cj, fj.reshape(-1, 2).mean(1), atol=1e-14)
+    assert np.allclose(ck, fk.reshape(-1, 2).mean(1), atol=1e-14)
+
+    def pix(gg, v):
+        s, d, u, w = gg.views[v, 0:3], gg.views[v, 3:6], gg.views[v, 6:9], gg.views[v, 9:12]
+        a = np.arange(gg.nu) - (gg.nu - 1) / 2
+        b = np.arange(gg.nv) - (gg.nv - 1) / 2
+        return d + a[None, :, None] * u + b[:, None, None] * w, s
+
+    for v in range(g.n_views):
+        pf, sf = pix(g, v)
+        pc, sc = pix(c, v)
+        assert np.array_equal(sf, sc)
+        mean = pf.reshape(g.nv // 2, 2, g.nu // 2, 2, 3).mean(axis=(1, 3))
+        assert np.allclose(pc, mean, atol=1e-12)
+
+
+def test_multigrid_without_coarse_change_is_one_fine_step(rng):
+    """When the coarse grids leave the restricted volume unchanged (no OS-EMTR
+    pass, and a zero step on the intermediate grid), Algorithm 1's correction
+    mu += P(mu_c1 - mu_c0) adds exactly zero, so one iteration is exactly one
+    grid-0 Landweber step followed by the regularisers.  Prolongating mu_c1
+    instead of the coarse change, or restricting the wrong level's data,
+    breaks it."""
+    g = _mg_problem(rng)
+    mu0 = rng.random(g.vol_shape)
+    b = rng.random(g.stack_shape)
+    f = oracle.filter_stencil27()
+    # two grids, with both regularisers on
+    m, hist = oracle.multigrid(g, mu0, b, levels=2, n_outer=1, filt=f, alphas=[0.004, 1.0], lam=0.01,
+                               bilateral_on=True, sigma_s=0.9, sigma_r=0.3, coarse_passes=0)
+    ref, r = oracle.landweber_step(g, mu0, b, 0.004, f)
+    ref = oracle.bilateral(oracle.soft_threshold(ref, 0.01), 0.9, 0.3)
+    assert np.array_equal(m, ref) and hist[0, 0] == r
+    # the coarse residual is the restricted data against the restricted volume
+    gc = g.level(1)
+    assert hist[0, 1] == pytest.approx(np.linalg.norm(oracle.restrict_stack(b) - oracle.project(gc, oracle.restrict_volume(mu0))), rel=1e-14)
+    # three grids, zero step on grid 1
+    m3, hist3 = oracle.multigrid(g, mu0, b, levels=3, n_outer=1, filt=f, alphas=[0.004, 0.0, 1.0],
+                                 coarse_passes=0)
+    ref3, r3 = oracle.landweber_step(g, mu0, b, 0.004, f)
+    assert np.array_equal(m3, ref3) and hist3[0, 0] == r3
+    # the same with a non-zero coarse step does change the result
+    m3b, _ = oracle.multigrid(g, mu0, b, levels=3, n_outer=1, filt=f, alphas=[0.004, 0.002, 1.0],
+                              coarse_passes=0)
+    assert np.linalg.norm(m3b - ref3) > 1e-6 * np.linalg.norm(ref3)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_multigrid_injection_fixed_point(rng, levels):
+    """mu = piecewise-constant injection of a coarsest-grid volume x_c, data
+    b_0 = A_{L-1} x_c repeated over the 2^(L-1) x 2^(L-1) fine pixels of each
+    coarsest pixel.  The restricted data on the coarsest grid are then
+    exactly A_{L-1} x_c, the restricted volume exactly x_c, so the coarse
+    OS-EMTR solve starts at its fixed point (eq. 3: e^{-A x} = I/I0) and, with
+    a zero step on the finer grids, one iteration of Algorithm 1 returns mu
+    unchanged.  The coarse residual it records is zero."""
+    f = 2 ** (levels - 1)
+    g = _mg_problem(rng, n=8, n_views=10, nu=8, nv=8)
+    gc = g.level(levels - 1)
+    xc = rng.random(gc.vol_shape) * 0.05
+    mu = xc
+    for _ in range(levels - 1):
+        mu = np.repeat(np.repeat(np.repeat(mu, 2, 0), 2, 1), 2, 2)
+    bc = oracle.project(gc, xc)
+    b0 = np.repeat(np.repeat(bc, f, 1), f, 2)
+    assert b0.shape == g.stack_shape
+    out, hist = oracle.multigrid(g, mu, b0, levels=levels, n_outer=1, filt=oracle.filter_identity(),
+                                 alphas=[0.0] * levels, coarse_M=2, coarse_passes=3)
+    assert np.allclose(out, mu, rtol=0, atol=1e-13)
+    assert hist[0, levels - 1] < 1e-13 * np.linalg.norm(bc)
+    # a wrong coarse datum (the data not restricted, only subsampled) is not a fixed point
+    b_bad = b0.copy()
+    b_bad[:, 0::f, 0::f] += 0.01
+    out_bad, _ = oracle.multigrid(g, mu, b_bad, levels=levels, n_outer=1, filt=oracle.filter_identity(),
+                                  alphas=[0.0] * levels, coarse_M=2, coarse_passes=3)
+    assert np.abs(out_bad - mu).max() > 1e-6
