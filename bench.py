@@ -1,25 +1,32 @@
 """Benchmark: preconditioned multigrid Landweber reconstruction on one MI355X.
 
-Workload (synthetic, seeded): 128^3 volume, 360 views of 192x192 on the
-golden-angle + 8-level height-lattice trajectory, 60 random ellipsoids,
-Poisson noise at I0 = 1e4.  One step = one full iteration of Algorithm 1
-with 3 grids (restrict, OS-EMTR on the coarsest grid, prolongate, and on the
-two finer grids a radially preconditioned Landweber step, soft threshold and
-bilateral filter).  Inputs are resident in HBM before timing starts.
+Workload (synthetic, seeded): 512^3 volume, 1440 views of 768x768 on the
+golden-angle + 8-level height-lattice trajectory, 400 random ellipsoids plus
+5 % cubic inclusions, Poisson noise at I0 = 5e3 (generated on the device from
+the same definitions as the CPU generator).  One step = one full iteration
+of Algorithm 1 with 4 grids (restrict, OS-EMTR on the coarsest 64^3 grid,
+prolongate, and on the three finer grids a radially preconditioned Landweber
+step, soft threshold and bilateral filter), FP32 storage.  Inputs are
+resident in HBM before timing starts.
 
-value = fine-grid voxel*views of one A + A^T pair per step (128^3 * 360) per
+value = fine-grid voxel*views of one A + A^T pair per step (512^3 * 1440) per
 second of whole-step time: the paper prices one such iteration at about one
 SIRT iteration.  The JSON line also carries the dominant kernel's roofline
-(measured with HIP events inside the library), the time-to-residual against
-plain SIRT on the same GPU, and the FP64 oracle timed on the host cores.
+(HIP events recorded inside the library on the launch stream), the same
+operators with BF16 volume / FP16 stack storage, time-to-residual and image
+error against plain SIRT on the same data, the 128^3 workload's
+time-to-residual against SIRT and OS-EMTR (with the learned and derived
+preconditioners), and the FP64 oracle timed on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1]
+                    [--no-cpu-baseline] [--no-quality]
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -30,7 +37,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "c1"
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+WORKLOAD_NAMES = {
+    "c2": "pmg-512^3-1440x768^2-L4-radial",
+    "c1": "pmg-128^3-360x192^2-L3-radial",
+}
 
 
 def log(*a):
@@ -40,11 +51,12 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOAD_NAMES), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sirt", action="store_true")
-    ap.add_argument("--sirt-cap", type=int, default=1000)
+    ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--sirt-cap", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--paper-shaped", action="store_true",
@@ -66,17 +78,22 @@ def main():
 
     import paper_2103_10329_amd as mg
     import synth
+    from paper_2103_10329_amd import learned as lrn
 
-    cfg = synth.CONFIGS[WORKLOAD]
+    wl = args.workload
+    cfg = synth.CONFIGS[wl]
+    idx = int(wl[1:])
     n, V, nu, nv = cfg.n, cfg.n_views, cfg.nu, cfg.nv
-    t0 = time.time()
-    d = synth.make_dataset(WORKLOAD, truth=not args.no_sirt)
-    log("data %.1fs" % (time.time() - t0))
-    views = d["views"]
-
+    views = synth.trajectory(V, cfg.z_levels, cfg.pixel)
     ctx = mg.Context(0)
     ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), nu, nv, views)
-    b = torch.from_numpy(d["b"].astype(np.float32)).cuda()
+    # data on the device: phantom seed 1000 + k, noise seed 2000 + k
+    t0 = time.time()
+    ph = synth.random_phantom(cfg, 1000 + idx)
+    gen = torch.Generator(device="cuda").manual_seed(2000 + idx)
+    b = lrn.poisson_data(ctx.synth_line_integrals(ph), cfg.noise_level, gen)
+    torch.cuda.synchronize()
+    log("data %.1fs" % (time.time() - t0))
     table = np.maximum(np.linspace(0, np.sqrt(3), 4097), 2.0 / n)
     filt = mg.filter_radial(table, np.sqrt(3))
     levels = cfg.levels
@@ -88,7 +105,7 @@ def main():
     alphas = [ctx.estimate_step(filt, level=g, iters=30, seed=0) for g in range(levels - 1)]
     torch.cuda.synchronize()
     t_alpha = time.time() - t0
-    log("alphas", alphas, "%.3fs" % t_alpha)
+    log("alphas", alphas, "%.1fs" % t_alpha)
 
     def step(vol):
         ctx.multigrid_solve(vol, b, levels, 1, filt, alphas=alphas, lam=lam, bilateral=bil, want_hist=False)
@@ -102,8 +119,11 @@ def main():
     ctx.kernel_timing(True, ops=(mg.MGCT_OP_PROJECT, mg.MGCT_OP_BACKPROJECT), levels=(0,))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step(vol)
+        if wl == "c2":
+            torch.cuda.synchronize()
+            log("step %d/%d %.3fs" % (k + 1, args.steps, time.perf_counter() - t0))
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
     ctx.kernel_timing(False)
@@ -128,11 +148,10 @@ def main():
         return out
 
     live = collect((mg.MGCT_OP_PROJECT, mg.MGCT_OP_BACKPROJECT), (0,))
-    # every instrumented kernel on every grid, from two further steps after
-    # the timed region; the fine grid's A and A^T keep their timed-region figures
+    # every instrumented kernel on every grid, from one further step after the
+    # timed region; the fine grid's A and A^T keep their timed-region figures
     ctx.kernel_timing(True)
-    for _ in range(2):
-        step(vol)
+    step(vol)
     torch.cuda.synchronize()
     ctx.kernel_timing(False)
     kt = collect(names.keys(), range(levels))
@@ -142,18 +161,8 @@ def main():
     tA = kt["project@0"]["ms_avg"]
     tB = kt["backproject@0"]["ms_avg"]
     dom = "backproject@0" if tB >= tA else "project@0"
-    t_dom = kt[dom]["ms_avg"] * 1e-3
-    achieved = bytes_per_launch / t_dom / 1e9
-    kname = "k_backproject_pl" if dom.startswith("back") else "k_project_sep"
-    counters = measured_counters(kname)
-    roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": counters["bytes_per_launch"] if counters else None,
-                "valu_issue": counters["valu_issue"] if counters else None,
-                "l2_hit": counters["l2_hit"] if counters else None,
-                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": kt[dom]["ms_avg"]}
+    roofline = make_roofline(dom, kt[dom]["ms_avg"], bytes_per_launch, n ** 3 * V, wl)
     a_at = n ** 3 * V / ((tA + tB) * 1e-3) / 1e9
-    # combined A + A^T rate on every grid (grid g: (n / 2^g)^3 voxels, same views)
     a_at_grid = {}
     for g in range(levels):
         ka, kb = kt.get("project@%d" % g), kt.get("backproject@%d" % g)
@@ -161,13 +170,16 @@ def main():
             a_at_grid[str(g)] = (n >> g) ** 3 * V / ((ka["ms_avg"] + kb["ms_avg"]) * 1e-3) / 1e9
 
     out = {
-        "metric": "A+A\u1d40 Gvoxel\u00b7views/s (% HBM roofline); time-to-residual vs plain SIRT",
-        "value": value, "unit": "Gvoxel\u00b7views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": "A+Aᵀ Gvoxel·views/s (% HBM roofline); time-to-residual vs plain SIRT",
+        "value": value, "unit": "Gvoxel·views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "pmg-128^3-360x192^2-L3-radial", "volume": [n, n, n], "views": V,
+        "config": {"workload": WORKLOAD_NAMES[wl], "volume": [n, n, n], "views": V,
                    "detector": [nv, nu], "levels": levels, "filter": "radial ramp max(rho,2/N)",
-                   "soft_threshold": lam, "bilateral": list(bil), "coarse": "OS-EMTR M=8 x2"},
+                   "soft_threshold": lam, "bilateral": list(bil), "coarse": "OS-EMTR M=8 x2",
+                   "phantom": "%d ellipsoids%s, Poisson I0=%g" % (
+                       cfg.n_ellipsoids, " + %g%% cubes" % (100 * cfg.cube_fraction) if cfg.cube_fraction else "",
+                       cfg.noise_level)},
         "roofline": roofline,
         "a_plus_at_kernels_gvox_views_s": a_at,
         "a_plus_at_hbm_frac": 2 * bytes_per_launch / ((tA + tB) * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -175,14 +187,203 @@ def main():
         "a_plus_at_gvox_views_s_by_grid": a_at_grid,
         "step_size_estimate_s": t_alpha,
     }
+    out["mixed_precision"] = mixed_precision(ctx, mg, b, n, V, step, bytes_per_launch)
+    torch.cuda.synchronize()
 
-    if not args.no_sirt:
-        out.update(quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args))
+    if not args.no_quality:
+        out["time_to_residual"] = time_to_residual(ctx, mg, synth, ph, b, cfg, levels, filt, alphas, lam, bil,
+                                                   args.sirt_cap)
+        if wl != "c1":
+            ctx.close()
+            del b, vol
+            torch.cuda.empty_cache()
+            out["c1"] = quality_c1(args)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, views, alphas, lam, bil)
+        out["cpu_baseline"] = cpu_baseline(cfg, views)
     print(json.dumps(out), flush=True)
+
+
+# HBM-side traffic of the dominant kernels from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes, scaled by the same counters on a plain copy of known
+# size, per launch, with their VALU and LDS issue fractions (wave-instructions
+# per CU cycle) and L2 hit rates from the counter passes; valid only for the
+# kernel source they were measured on.
+TRAFFIC = {}
+
+
+def measured_counters(kernel, workload):
+    """The committed counter figures for `kernel` on `workload`, or None when
+    the source has changed since they were taken."""
+    import hashlib
+    t = TRAFFIC.get((kernel, workload))
+    if not t:
+        return None
+    src = os.path.join(ROOT, "paper_2103_10329_amd", "csrc", "joseph.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t
+
+
+# Algorithmic FP32 operations per voxel*view (SURVEY-style count of the
+# kernels' arithmetic per Joseph sample times the measured samples per
+# voxel*view of these trajectories, 1.45): A 12 per sample (bilinear blend
+# 7, z step 3, weight 2); A^T about 3 weight pairs per voxel*view of 8.
+ALG_OPS = {"project@0": 1.45 * 12, "backproject@0": 24.0}
+
+
+def make_roofline(dom, ms_avg, bytes_per_launch, voxel_views, workload):
+    """Roofline of the dominant kernel.  The metric's HBM model is the
+    per-view-stream bytes V (N^3 s_vol + U W s_det) per launch; the measured
+    counters (when present for this source) decide which unit binds: HBM
+    (counter bytes per second against 8 TB/s) or the vector ALUs (VALU issue
+    against one wave-instruction per CU cycle)."""
+    kname = "k_backproject_pl" if dom.startswith("back") else "k_project_lds"
+    t = ms_avg * 1e-3
+    hbm_achieved = bytes_per_launch / t / 1e9
+    cnt = measured_counters(kname, workload)
+    r = {"kernel": kname, "bound": "hbm", "achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": hbm_achieved / HBM_PEAK_GBS, "traffic": cnt["bytes_per_launch"] if cnt else None,
+         "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms_avg,
+         "per_view_stream_frac": hbm_achieved / HBM_PEAK_GBS}
+    if cnt:
+        hbm_util = cnt["bytes_per_launch"] / t / 1e9 / HBM_PEAK_GBS
+        r.update({"valu_issue": cnt["valu_issue"], "lds_issue": cnt.get("lds_issue"), "l2_hit": cnt["l2_hit"],
+                  "hbm_util_measured": hbm_util})
+        if cnt["valu_issue"] > hbm_util:
+            ops = ALG_OPS[dom] * voxel_views
+            ach = ops / t / 1e12
+            r.update({"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "algorithmic_ops_per_launch": ops})
+    return r
+
+
+def mixed_precision(ctx, mg, b, n, V, step, bytes_fp32):
+    """The same operators with BF16 volume copies and FP16 stacks (FP32
+    accumulation): one A from a BF16 volume to an FP16 stack, one A^T from an
+    FP16 stack, one Algorithm 1 iteration with mixed storage."""
+    import torch
+    x = torch.rand((n, n, n), device="cuda", generator=torch.Generator(device="cuda").manual_seed(7))
+    xb = x.to(torch.bfloat16)
+    y = b.half()
+    p = ctx.project(xb, out_dtype=torch.float16)
+    q = ctx.backproject(y)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True, ops=(mg.MGCT_OP_PROJECT, mg.MGCT_OP_BACKPROJECT), levels=(0,))
+    ctx.project(xb, out=p)
+    ctx.backproject(y, out=q)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(False)
+    tA = ctx.kernel_time(mg.MGCT_OP_PROJECT, 0)[0]
+    tB = ctx.kernel_time(mg.MGCT_OP_BACKPROJECT, 0)[0]
+    ctx.set_precision("bfloat16", "float16")
+    v = torch.zeros((n, n, n), device="cuda")
+    step(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(v)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    ctx.set_precision("float32", "float32")
+    bytes_mixed = V * (n ** 3 * 2 + b[0].numel() * 2)
+    del x, xb, y, p, q, v
+    return {"storage": "BF16 volume copies, FP16 stacks, FP32 accumulation",
+            "A_ms": tA, "At_ms": tB, "A_gvox_views_s": n ** 3 * V / (tA * 1e-3) / 1e9,
+            "At_gvox_views_s": n ** 3 * V / (tB * 1e-3) / 1e9,
+            "a_plus_at_gvox_views_s": n ** 3 * V / ((tA + tB) * 1e-3) / 1e9,
+            "per_view_stream_frac_A": bytes_mixed / (tA * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "step_ms": t_step * 1e3, "step_gvox_views_s": n ** 3 * V / t_step / 1e9}
+
+
+def time_to_residual(ctx, mg, synth, ph, b, cfg, levels, filt, alphas, lam, bil, cap):
+    """Two iterations of Algorithm 1 from zero against plain SIRT (eq. 2, its
+    own power-iteration step) from zero until it reaches the same relative
+    residual ||b - A mu|| / ||b||, on the same GPU; masked image error against
+    the voxelised phantom after 2 iterations of each."""
+    import torch
+    n = cfg.n
+    truth = ctx.synth_voxelize(ph, ss=2)
+    mask = torch.from_numpy(synth.evaluation_mask(n, cfg.h)).cuda()
+    tm = truth[mask].double()
+
+    def err(v):
+        return float(torch.linalg.vector_norm(v[mask].double() - tm) / torch.linalg.vector_norm(tm))
+
+    def resid(v):
+        return float(torch.linalg.vector_norm((b - ctx.project(v)).double()).item())
+
+    bnorm = float(torch.linalg.vector_norm(b.double()).item())
+    v = torch.zeros((n, n, n), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.multigrid_solve(v, b, levels, 2, filt, alphas=alphas, lam=lam, bilateral=bil, want_hist=False)
+    torch.cuda.synchronize()
+    t_pmg = time.perf_counter() - t0
+    r_pmg = resid(v)
+    e_pmg = err(v)
+    del v
+    a_sirt = ctx.estimate_step(None, level=0, iters=30, seed=0)
+    vs = torch.zeros((n, n, n), device="cuda")
+    k, e_sirt2 = 0, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while k < cap:
+        if ctx.landweber_step(vs, b, a_sirt, None, want_norm=True) <= r_pmg:  # ||b - A mu_k||
+            break
+        k += 1
+        if k == 2:
+            torch.cuda.synchronize()
+            t_pause = time.perf_counter()
+            e_sirt2 = err(vs)
+            t0 += time.perf_counter() - t_pause
+    torch.cuda.synchronize()
+    t_sirt = time.perf_counter() - t0
+    out = {"target_rel_residual": r_pmg / bnorm, "pmg": {"iterations": 2, "seconds": t_pmg,
+                                                        "image_error_masked": e_pmg},
+           "sirt_iterations": k if k < cap else None, "sirt_cap": cap, "sirt_s": t_sirt, "sirt_alpha": a_sirt,
+           "sirt_image_error_masked_2": e_sirt2,
+           "speedup_vs_sirt": (t_sirt / t_pmg) if k < cap else None}
+    log("time-to-residual", out)
+    del vs, truth
+    return out
+
+
+def quality_c1(args):
+    """The 128^3 workload's time-to-residual and image errors (plain, learned
+    and derived preconditioners; SIRT and OS-EMTR), on a context of its own."""
+    import torch
+
+    import paper_2103_10329_amd as mg
+    import synth
+    cfg = synth.CONFIGS["c1"]
+    n = cfg.n
+    d = synth.make_dataset("c1", truth=True)
+    ctx = mg.Context(0)
+    ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, d["views"])
+    b = torch.from_numpy(d["b"].astype(np.float32)).cuda()
+    table = np.maximum(np.linspace(0, np.sqrt(3), 4097), 2.0 / n)
+    filt = mg.filter_radial(table, np.sqrt(3))
+    lam, bil = 1e-3, (1.0, 0.05)
+    alphas = [ctx.estimate_step(filt, level=g, iters=30, seed=0) for g in range(cfg.levels - 1)]
+
+    def step(vol):
+        ctx.multigrid_solve(vol, b, cfg.levels, 1, filt, alphas=alphas, lam=lam, bilateral=bil, want_hist=False)
+
+    vol = torch.zeros((n, n, n), device="cuda")
+    step(vol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        step(vol)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 10 * 1e3
+    res = quality(ctx, mg, b, d, step, cfg.levels, filt, alphas, lam, bil, args)
+    res["workload"] = WORKLOAD_NAMES["c1"]
+    res["ms_per_step"] = ms
+    res["value_gvox_views_s"] = n ** 3 * cfg.n_views / (ms * 1e-3) / 1e9
     ctx.close()
+    return res
 
 
 def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
@@ -198,7 +399,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 
     import synth
     from paper_2103_10329_amd import learned as lrn
-    cfg = synth.CONFIGS[WORKLOAD]
+    cfg = synth.CONFIGS["c1"]
     n = cfg.n
     truth = torch.from_numpy(d["mu"].astype(np.float32)).cuda()
     mask = torch.from_numpy(synth.evaluation_mask(n, cfg.h)).cuda()
@@ -267,7 +468,8 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
     k = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while k < args.sirt_cap:
+    cap1 = 1000
+    while k < cap1:
         if ctx.landweber_step(vs, b, a_sirt, None, want_norm=True) <= r_pmg:  # ||b - A mu_k||
             break
         k += 1
@@ -281,7 +483,7 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
 
     # OS-EMTR at full resolution, 8 subsets per iteration
     vo = torch.zeros((n, n, n), device="cuda")
-    cap_os = min(args.sirt_cap, 200)
+    cap_os = 200
     reached, t_os = None, 0.0
     for ko in range(1, cap_os + 1):
         torch.cuda.synchronize()
@@ -296,42 +498,14 @@ def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
         if reached is not None and ko >= 10:
             break
     ttr = {"target_rel_residual": r_pmg / bnorm, "pmg": pmg,
-           "sirt_iterations": k if k < args.sirt_cap else None, "sirt_cap": args.sirt_cap,
+           "sirt_iterations": k if k < cap1 else None, "sirt_cap": cap1,
            "sirt_s": t_sirt, "sirt_alpha": a_sirt,
-           "speedup_vs_sirt": (t_sirt / t_pmg) if k < args.sirt_cap else None,
+           "speedup_vs_sirt": (t_sirt / t_pmg) if k < cap1 else None,
            "osemtr_iterations": reached[0] if reached else None, "osemtr_s": reached[1] if reached else None,
            "osemtr_cap": cap_os}
     log("time-to-residual", ttr)
     log("masked image error", errors)
     return {"time_to_residual": ttr, "image_error_masked": errors}
-
-
-# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes, scaled by the same counters on a plain copy of known size, per
-# launch, with its VALU issue fraction (SQ_INSTS_VALU per CU cycle) and L2 hit
-# rate from the counter pass; valid only for the kernel source it was
-# measured on.
-TRAFFIC = {
-    # profiles/backproject_project_128cube_360x192_counters.md
-    "k_backproject_pl": {"source_sha256": "f23a0e9827bc880d5623e26b67b0ee4243ea940c2f3dfa25edbb20a1941cb161",
-                          "bytes_per_launch": 407438624, "valu_issue": 0.86, "l2_hit": 0.958},
-    "k_project_sep": {"source_sha256": "f23a0e9827bc880d5623e26b67b0ee4243ea940c2f3dfa25edbb20a1941cb161",
-                       "bytes_per_launch": 7172105892, "valu_issue": 0.71, "l2_hit": 0.495},
-}
-
-
-def measured_counters(kernel):
-    """The committed counter figures for `kernel`, or None when the source has
-    changed since they were taken."""
-    import hashlib
-    t = TRAFFIC.get(kernel)
-    if not t:
-        return None
-    src = os.path.join(ROOT, "paper_2103_10329_amd", "csrc", "joseph.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
-            return None
-    return t
 
 
 def paper_shaped():
@@ -431,26 +605,27 @@ def copy_calibration(size_mib=1024, reps=5):
     print(json.dumps({"copy_bytes_each_way": size_mib << 20, "reps": reps}), flush=True)
 
 
-def cpu_baseline(d, views, alphas, lam, bil):
-    """The FP64 oracle, as it stands, on the host cores: one full iteration of
-    Algorithm 1 on the same workload (same data, steps and parameters)."""
+def cpu_baseline(cfg, views, n_sub=8):
+    """The FP64 oracle, as it stands, on the host cores: one A and one A^T of
+    the same workload's geometry restricted to n_sub of its views (evenly
+    spaced), on a seeded random volume; the rate counts voxel*views of that
+    sample.  A full solve at this size is impractical on the host."""
     import oracle
-    import synth
-    cfg = synth.CONFIGS[WORKLOAD]
     n = cfg.n
-    g = oracle.Geom(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views)
-    table, rho_max = oracle.radial_table(n)
-    f = oracle.filter_radial(table, rho_max)
+    sub = np.ascontiguousarray(views[:: max(1, len(views) // n_sub)][:n_sub])
+    g = oracle.Geom(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, sub)
+    x = np.random.default_rng(0).random(g.vol_shape)
     t0 = time.perf_counter()
-    oracle.multigrid(g, np.zeros(g.vol_shape), d["b"], cfg.levels, 1, f, alphas, lam=lam, bilateral_on=True,
-                     sigma_s=bil[0], sigma_r=bil[1])
-    t = time.perf_counter() - t0
-    out = {"value": n ** 3 * cfg.n_views / t / 1e9, "unit": "Gvoxel·views/s", "cores": oracle.num_threads(),
-           "kind": "oracle", "seconds": t,
-           "sample": "one full iteration of Algorithm 1 (3 grids, same 128^3 x 360-view data) by the FP64 oracle",
-           "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
-    out["one_thread"] = _oracle_one_thread(views[::8], n, cfg.h, cfg.nu, cfg.nv)
-    return out
+    p = oracle.project(g, x)
+    t1 = time.perf_counter()
+    oracle.backproject(g, p)
+    t2 = time.perf_counter()
+    t = t2 - t0
+    return {"value": n ** 3 * len(sub) / t / 1e9, "unit": "Gvoxel·views/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": t, "A_s": t1 - t0, "At_s": t2 - t1,
+            "sample": "one A and one A^T of the FP64 oracle on %d of the %d views (evenly spaced) of the %d^3, "
+                      "%dx%d-detector geometry, seeded random volume" % (len(sub), len(views), n, cfg.nv, cfg.nu),
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def _cpu_model():
@@ -462,41 +637,6 @@ def _cpu_model():
     except OSError:
         pass
     return None
-
-
-# One A and one A^T of the FP64 oracle on a view subset, on one thread (the
-# oracle reads its thread count at start-up, so this runs in a child process).
-_ONE_THREAD = """
-import sys, time
-import numpy as np
-import oracle
-views = np.load(sys.argv[1])
-n, h, nu, nv = int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5])
-g = oracle.Geom(n, n, n, h, (0, 0, 0), nu, nv, views)
-x = np.random.default_rng(0).random(g.vol_shape)
-t = time.perf_counter()
-oracle.backproject(g, oracle.project(g, x))
-print(oracle.num_threads(), time.perf_counter() - t)
-"""
-
-
-def _oracle_one_thread(views, n, h, nu, nv):
-    import subprocess
-    import tempfile
-    with tempfile.TemporaryDirectory() as tmp:
-        vf = os.path.join(tmp, "views.npy")
-        np.save(vf, np.ascontiguousarray(views))
-        env = dict(os.environ, OMP_NUM_THREADS="1")
-        try:
-            r = subprocess.run([sys.executable, "-c", _ONE_THREAD, vf, str(n), str(h), str(nu), str(nv)],
-                               env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
-            threads, t = r.stdout.split()
-        except (subprocess.SubprocessError, ValueError) as e:
-            return {"error": str(e)[:200]}
-    t = float(t)
-    return {"value": n ** 3 * len(views) / t / 1e9, "unit": "Gvoxel·views/s", "threads": int(threads),
-            "seconds": t, "sample": "one A and one A^T on %d of the %d views (every 8th), FP64 oracle" % (
-                len(views), 8 * len(views))}
 
 
 if __name__ == "__main__":

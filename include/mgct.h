@@ -153,6 +153,22 @@ int mgct_backproject(void *ctx, int level, const void *proj, int proj_dtype, voi
                      hipStream_t stream);
 
 /*
+ * Which forward projector the separable geometry (detector columns
+ * horizontal, rows vertical) uses when all views are projected at once; both
+ * compute the same Joseph sums and return bit-identical results:
+ * MGCT_PROJECTOR_GATHER reads each sample's four taps with one 16-byte gather
+ * from two pair-expanded volume copies (fast while the copies stay in the
+ * caches); MGCT_PROJECTOR_STAGED stages, for a tile of 8 detector columns x
+ * 64 rows of one view, the volume window its rays cross into LDS, 8 planes
+ * at a time, from one plain copy, with the views ordered so that a band of
+ * the volume is shared in the last-level cache; MGCT_PROJECTOR_AUTO (the
+ * default) takes the staged one for grids of 256^3 voxels or more.  Other
+ * geometries and view subsets always use their own kernels.  Host only.
+ */
+typedef enum { MGCT_PROJECTOR_AUTO = 0, MGCT_PROJECTOR_GATHER = 1, MGCT_PROJECTOR_STAGED = 2 } mgct_projector;
+int mgct_set_projector(void *ctx, int variant);
+
+/*
  * Storage precision of the copies a Landweber step makes (mgct_landweber_step,
  * and every Landweber grid of mgct_multigrid_solve): the projector's copy of
  * the volume (F32 or BF16) and the projected / residual / scaled data stacks

@@ -79,6 +79,7 @@ SIGNATURES = {
     "mgct_estimate_step": (_ci, [_vp, _ci, _fp, _ci, _u64, _dp, _vp]),
     "mgct_landweber_step": (_ci, [_vp, _ci, _vp, _vp, _ci, _cd, _fp, _dp, _vp]),
     "mgct_set_divergence": (_ci, [_vp, _cd]),
+    "mgct_set_projector": (_ci, [_vp, _ci]),
     "mgct_residual_diverged": (_ci, [_cd, _cd, _cd]),
     "mgct_psf_spectrum": (_ci, [_vp, _ci, _vp, _vp]),
     "mgct_transfer_from_spectrum": (_ci, [_vp, _ci, _vp, _cd, _vp, _vp]),
@@ -310,6 +311,12 @@ class Context:
         check(mgct_landweber_step(self.handle, level, _ptr(vol), _ptr(b), _dtype_code(b), float(alpha), fp,  # noqa: F821
                                   ctypes.byref(r) if want_norm else None, _stream()), "mgct_landweber_step")
         return r.value if want_norm else None
+
+    def set_projector(self, variant: str = "auto"):
+        """Forward projector of the separable geometry: auto | gather | staged
+        (bit-identical results)."""
+        code = {"auto": 0, "gather": 1, "staged": 2}[variant]
+        check(mgct_set_projector(self.handle, code), "mgct_set_projector")  # noqa: F821
 
     def set_divergence(self, ratio: float):
         """Ratio of the divergence test (>= 1, or 0: non-finite residuals only)."""

@@ -121,11 +121,29 @@ int pair_copies(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, int vt_
     return MGCT_OK;
 }
 
+// The plain padded z-fastest copy of grid g (zero borders survive: allocated
+// zeroed, never written there) read by the LDS projector and the general one.
+int plain_copy(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, int vt_dtype, void **vt, hipStream_t s) {
+    const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
+    *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es + kCopyTail, true);
+    if (!*vt) return MGCT_ERR_OOM;
+    KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
+    HIPCHK(launch_transpose_volume(vol, vol_dtype, *vt, vt_dtype, L, s));
+    return MGCT_OK;
+}
+
 int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *proj, int proj_dtype, int view0,
                int step, int nsub, hipStream_t s, int vt_dtype = -1) {
     // the projector's volume copy: BF16 when the input is BF16 or when asked
     if (vt_dtype < 0 || vol_dtype == MGCT_BF16) vt_dtype = vol_dtype;
     const size_t es = vt_dtype == MGCT_F32 ? 4 : 2;
+    if (L.separable && view0 == 0 && step == 1 && project_lds_ok(L, nsub, c.proj_variant)) {
+        void *vt;
+        MGCHK(plain_copy(c, L, g, vol, vol_dtype, vt_dtype, &vt, s));
+        KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+        HIPCHK(launch_project_lds_mode(vt, vt_dtype, 0, proj, proj_dtype, nullptr, MGCT_F32, nullptr, L, s));
+        return MGCT_OK;
+    }
     if (L.separable) {
         void *vtx, *vty;
         MGCHK(pair_copies(c, L, g, vol, vol_dtype, vt_dtype, &vtx, &vty, s));
@@ -133,7 +151,7 @@ int do_project(Ctx &c, Level &L, int g, const void *vol, int vol_dtype, void *pr
         HIPCHK(launch_project_sep(vtx, vty, vt_dtype, proj, proj_dtype, L, view0, step, nsub, s));
         return MGCT_OK;
     }
-    void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es, true);
+    void *vt = workspace(c, lvl(vt_dtype == MGCT_F32 ? "vt32" : "vt16", g), L.padded_vox() * es + kCopyTail, true);
     if (!vt) return MGCT_ERR_OOM;
     {
         KernelTimer t(c, MGCT_OP_VOLUME_TRANSPOSE, g, s);
@@ -279,13 +297,19 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
         WS(grad, float, lvl("lw_g", g), L.vox() * 4, false);
         WS(pt, char, lvl(sd == MGCT_F32 ? "pt" : "pt16", g), L.rays() * es, false);
         const int vtd = c.vt_dtype;
-        const size_t nblk = project_sep_blocks(L, L.nviews, vtd);
+        const bool lds = project_lds_ok(L, L.nviews, c.proj_variant);
+        const size_t nblk = lds ? project_lds_blocks(L) : project_sep_blocks(L, L.nviews, vtd);
         WS(pp, double, "proj_partials", nblk * 8, false);
         WS(pp2, double, "proj_partials2", 256 * 8, false);
         WS(nrm, double, "red_scratch", 8, false);
-        void *vtx, *vty;
-        MGCHK(pair_copies(c, L, g, vol, MGCT_F32, vtd, &vtx, &vty, s));
-        {
+        if (lds) {
+            void *vt;
+            MGCHK(plain_copy(c, L, g, vol, MGCT_F32, vtd, &vt, s));
+            KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+            HIPCHK(launch_project_lds_mode(vt, vtd, 1, pt, sd, b, b_dtype, pp, L, s));
+        } else {
+            void *vtx, *vty;
+            MGCHK(pair_copies(c, L, g, vol, MGCT_F32, vtd, &vtx, &vty, s));
             KernelTimer t(c, MGCT_OP_PROJECT, g, s);
             HIPCHK(launch_project_sep_mode(vtx, vty, vtd, 1, pt, nullptr, sd, b, b_dtype, nullptr, pp, L, 0, 1,
                                            L.nviews, s));
@@ -318,12 +342,18 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
 
 int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out, hipStream_t s) {
     if (L.separable) {
-        const size_t nblk = project_sep_blocks(L, L.nviews, MGCT_F32);
+        const bool lds = project_lds_ok(L, L.nviews, c.proj_variant);
+        const size_t nblk = lds ? project_lds_blocks(L) : project_sep_blocks(L, L.nviews, MGCT_F32);
         WS(pp, double, "proj_partials", nblk * 8, false);
         WS(pp2, double, "proj_partials2", 256 * 8, false);
-        void *vtx, *vty;
-        MGCHK(pair_copies(c, L, g, vol, MGCT_F32, MGCT_F32, &vtx, &vty, s));
-        {
+        if (lds) {
+            void *vt;
+            MGCHK(plain_copy(c, L, g, vol, MGCT_F32, MGCT_F32, &vt, s));
+            KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+            HIPCHK(launch_project_lds_mode(vt, MGCT_F32, 3, nullptr, MGCT_F32, b, MGCT_F32, pp, L, s));
+        } else {
+            void *vtx, *vty;
+            MGCHK(pair_copies(c, L, g, vol, MGCT_F32, MGCT_F32, &vtx, &vty, s));
             KernelTimer t(c, MGCT_OP_PROJECT, g, s);
             HIPCHK(launch_project_sep_mode(vtx, vty, MGCT_F32, 3, nullptr, nullptr, MGCT_F32, b, MGCT_F32, nullptr,
                                            pp, L, 0, 1, L.nviews, s));
@@ -905,6 +935,12 @@ int mgct_landweber_step(void *ctx, int level, float *vol, const void *b, int b_d
     return MGCT_OK;
 }
 
+int mgct_set_projector(void *ctx, int variant) {
+    if (!ctx || variant < MGCT_PROJECTOR_AUTO || variant > MGCT_PROJECTOR_STAGED) return MGCT_ERR_INVALID_ARG;
+    as_ctx(ctx)->proj_variant = variant;
+    return MGCT_OK;
+}
+
 int mgct_set_divergence(void *ctx, double ratio) {
     if (!ctx || !(ratio == 0.0 || ratio >= 1.0) || !isfinite(ratio)) return MGCT_ERR_INVALID_ARG;
     Ctx &c = *as_ctx(ctx);
@@ -924,7 +960,7 @@ int mgct_project_geom_grad(void *ctx, int level, const float *vol, const float *
     Level &L = *Lp;
     // the derivative kernel addresses its padded FP32 copy with 32-bit byte offsets
     if (L.padded_vox() * 4 > 0xFFFFFFF0ull) return MGCT_ERR_NOT_IMPLEMENTED;
-    void *vt = workspace(c, lvl("vt32", level), L.padded_vox() * 4, true);
+    void *vt = workspace(c, lvl("vt32", level), L.padded_vox() * 4 + kCopyTail, true);
     if (!vt) return MGCT_ERR_OOM;
     WS(partial, double, lvl("gg_partial", level), geom_grad_partial_bytes(L), false);
     WS(dv, double, lvl("gg_dviews", level), (size_t)L.nviews * 12 * 8, false);
@@ -1209,4 +1245,3 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
 }
 
 }  // extern "C"
-

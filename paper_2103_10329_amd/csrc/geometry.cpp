@@ -10,6 +10,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "mgct_internal.h"
@@ -178,6 +179,29 @@ int build_level(Ctx &c, int g, Level &L) {
         }
     }
 
+    // The LDS projector's block order: (view, row tile) pairs with the views
+    // grouped by source height (one row tile of views at one height samples
+    // one z band of the volume), groups by height, views by angle within one.
+    std::vector<int> order;
+    if (sep) {
+        L.n_rt = (nv + 63) / 64;
+        std::vector<int> idx(V);
+        for (int v = 0; v < V; ++v) idx[v] = v;
+        const double cx = 0.5 * (L.nx - 1), cy = 0.5 * (L.ny - 1);
+        std::stable_sort(idx.begin(), idx.end(), [&](int p, int q) {
+            if (vi[p].s[2] != vi[q].s[2]) return vi[p].s[2] < vi[q].s[2];
+            return atan2(vi[p].s[1] - cy, vi[p].s[0] - cx) < atan2(vi[q].s[1] - cy, vi[q].s[0] - cx);
+        });
+        order.reserve((size_t)V * L.n_rt);
+        for (int g0 = 0; g0 < V;) {
+            int g1 = g0 + 1;
+            while (g1 < V && vi[idx[g1]].s[2] == vi[idx[g0]].s[2]) ++g1;
+            for (int r = 0; r < L.n_rt; ++r)
+                for (int k = g0; k < g1; ++k) order.push_back(idx[k] * L.n_rt + r);
+            g0 = g1;
+        }
+    }
+
     // upload
     if (hipMalloc(&L.d_views, sizeof(ViewIdx) * V) != hipSuccess) return MGCT_ERR_OOM;
     if (hipMemcpy(L.d_views, vi.data(), sizeof(ViewIdx) * V, hipMemcpyHostToDevice) != hipSuccess)
@@ -191,6 +215,11 @@ int build_level(Ctx &c, int g, Level &L) {
         if (hipMalloc(&L.d_cols, sizeof(ColD) * cols.size()) != hipSuccess) return MGCT_ERR_OOM;
         if (hipMemcpy(L.d_cols, cols.data(), sizeof(ColD) * cols.size(), hipMemcpyHostToDevice) != hipSuccess)
             return MGCT_ERR_HIP;
+        if ((double)V * L.n_rt < 2.0e9) {
+            if (hipMalloc(&L.d_order, sizeof(int) * order.size()) != hipSuccess) return MGCT_ERR_OOM;
+            if (hipMemcpy(L.d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return MGCT_ERR_HIP;
+        }
     }
     return MGCT_OK;
 }
@@ -200,6 +229,8 @@ void free_level(Level &L) {
     if (L.d_sep) (void)hipFree(L.d_sep);
     if (L.d_cols) (void)hipFree(L.d_cols);
     if (L.d_axis) (void)hipFree(L.d_axis);
+    if (L.d_order) (void)hipFree(L.d_order);
+    L.d_order = nullptr;
     L.d_views = nullptr;
     L.d_sep = nullptr;
     L.d_cols = nullptr;

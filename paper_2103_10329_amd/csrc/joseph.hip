@@ -591,6 +591,494 @@ hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtyp
     return hipGetLastError();
 }
 
+#ifndef MGCT_PROJ_LDS
+#define MGCT_PROJ_LDS 1
+#endif
+#ifndef MGCT_PROJ_LDS_MIN_VOX
+#define MGCT_PROJ_LDS_MIN_VOX (256u * 256u * 256u)
+#endif
+#ifndef MGCT_PROJ_LDS_WAVES
+#define MGCT_PROJ_LDS_WAVES 6
+#endif
+
+// ------------------------------------------ LDS-staged separable projector --
+//
+// The Joseph sums of k_project_sep with the four bilinear taps of every sample
+// served from LDS.  A block takes kLdsTC adjacent detector columns of one view
+// (one wave per column, lanes = 64 consecutive rows) and reads the volume from
+// the plain padded z-fastest copy vt[x][y][z] (half the bytes of the two pair
+// copies).  The planes of the rays' major axis are walked in chunks of kLdsP:
+// for each chunk the block stages in LDS, per plane, the in-plane rows
+// [a_lo(l), a_lo(l) + n_a(l)) (a_lo from the block's own columns' taps) times
+// the z values [z_lo, z_lo + n_z) (from the tile's corner rays, which bound
+// every ray of the tile because z is bilinear in the ray parameter and the
+// row's z slope), one coalesced run of z values per row, and every sample
+// reads its taps as two pairs of adjacent LDS words.  Each staged value serves
+// about 1.8 rays x 4 taps at the workloads' sampling density, where the pair
+// copies delivered 16 bytes from the vector cache per sample.  A chunk whose
+// window exceeds the buffer, and every chunk of a block whose columns mix x-
+// and y-major rays, reads its taps from the copy directly (two 8-byte loads per
+// sample).
+//
+// Per sample the arithmetic is k_project_sep's: the same FP64 in-plane position
+// and weight, the same 32.32 fixed-point z stepping from the same FP64 start,
+// the same FP32 blend in the same order, planes in increasing order; the two
+// kernels return bit-identical sums.
+//
+// Blocks are ordered for the caches: `order` lists (view, row tile) pairs,
+// views grouped by source height (views at one height sample the same z band
+// in a row tile) and by angle within a group, and a pair's column tiles are
+// consecutive blocks.  The blocks resident at one time then cover a few views
+// of one height and row tile: one z band of the volume, which stays in the
+// last-level cache while the group's views pass over it.  (Handing each XCD
+// every 8th pair instead, to keep a pair's neighbouring tiles in one L2, was
+// 8 % slower at 512^3; views in their natural order 13 % slower.)
+constexpr int kLdsTC = 8;    // columns (waves) per block
+constexpr int kLdsP = 8;     // planes per chunk (one staging buffer)
+constexpr int kLdsTB = 64;   // planes per table block (one per lane)
+constexpr int kLdsNQ = kLdsTB / kLdsP;  // chunks per table block
+constexpr int kLdsAW = 11;   // in-plane rows per staged plane
+constexpr int kLdsZW = 64;   // z values per staged row
+constexpr int kLdsRows = kLdsP * kLdsAW;
+constexpr int kNoTap = -0x7fffffff - 1;  // no tap of this column on the plane
+static_assert(kLdsTB % kLdsP == 0 && kLdsNQ <= 64, "LDS projector tiling");
+
+// Staging of one chunk: issue the loads (into registers), then commit them to
+// an LDS buffer; the next chunk's loads are in flight while the current one is
+// sampled.  Wave w stages plane w of the chunk: its in-plane rows
+// ia = 4 u + lane / 16 (u < kLdsIter), z values 4 (lane mod 16) .. + 3, so the
+// plane's window (a_lo, n_a) is wave-uniform.
+constexpr int kLdsIter = (kLdsAW + 3) / 4;
+static_assert(kLdsP == kLdsTC, "one staged plane per wave");
+
+struct LdsStage {
+    float4 val[kLdsIter];
+    unsigned ok;  // bit u: rows 4u .. 4u + 3 hold this lane's row
+};
+
+// pl: the plane (absolute), alo / na: its window (wave-uniform), zl / zn: the
+// chunk's z window
+template <typename VT, bool WIDE>
+__device__ __forceinline__ void lds_stage_issue(LdsStage &st, const VT *__restrict__ vt, int lane, bool plane_ok,
+                                                int pl, int alo, int na, int zl, int zn, long Sm, long Sa) {
+    const int sub = lane >> 4, zq = (lane & 15) * 4;
+    const bool zok = plane_ok && zq < zn;
+    const long base = (long)(pl + kVolPad) * Sm + (long)(alo + sub) * Sa + zl + zq;
+    st.ok = 0u;
+#pragma unroll
+    for (int u = 0; u < kLdsIter; ++u) {
+        const bool ok = zok && 4 * u + sub < na;
+        if (WIDE) {
+            st.val[u] = load_quad(vt + (ok ? base + 4 * u * Sa : 0), 0u);
+        } else {
+            st.val[u] = load_quad(vt, ok ? (uint32_t)(base + 4 * u * Sa) : 0u);
+        }
+        st.ok |= ok ? (1u << u) : 0u;
+    }
+}
+
+// buf: the LDS array (passed as such so that the accesses stay LDS accesses),
+// base: the plane's first element in the buffer
+__device__ __forceinline__ void lds_stage_commit(const LdsStage &st, int lane, float (&buf)[2 * kLdsRows * kLdsZW],
+                                                 int base) {
+    const int o = base + (lane >> 4) * kLdsZW + (lane & 15) * 4;
+#pragma unroll
+    for (int u = 0; u < kLdsIter; ++u)
+        if (st.ok & (1u << u)) *reinterpret_cast<float4 *>(&buf[o + 4 * u * kLdsZW]) = st.val[u];
+}
+
+template <typename VT, typename PT, int MODE, typename TB, bool WIDE>
+__global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_lds(const VT *__restrict__ vt, PT *__restrict__ out,
+                                                             const TB *__restrict__ y, double *__restrict__ partials,
+                                                             const ViewIdx *__restrict__ views,
+                                                             const ColD *__restrict__ cols, const int *__restrict__ order,
+                                                             int n_ct, int n_t, int n_rt, int nx, int ny, int nz,
+                                                             int nu, int nv, double h) {
+    __shared__ float S[2 * kLdsRows * kLdsZW];  // two staging buffers
+    __shared__ int AI[kLdsTC][kLdsTB];
+    __shared__ int WL[kLdsTB], NA[kLdsTB];
+    __shared__ int CZ[kLdsNQ], CN[kLdsNQ], CD[kLdsNQ];
+    __shared__ int s_l0, s_l1, s_and, s_or;
+    __shared__ double wsum[kLdsTC];
+
+    const unsigned bid = blockIdx.x;
+    const int ct = (int)(bid % (unsigned)n_ct);
+    const int t = (int)(bid / (unsigned)n_ct);
+    if (t >= n_t) return;  // whole block, before any barrier
+    const int e = order[t];
+    const int v = e / n_rt, rt = e - (e / n_rt) * n_rt;
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int a = ct * kLdsTC + w;
+    const int b = rt * 64 + lane;
+    const bool colok = a < nu;
+    const int ac = min(a, nu - 1);
+    const ColD C = cols[(long)v * nu + ac];
+    const ViewIdx &V = views[v];
+    const int m = C.axis;
+    const double Dm = (m == 0) ? C.dx : C.dy, Da = (m == 0) ? C.dy : C.dx, rDm = (m == 0) ? C.rdx : C.rdy;
+    const double sm = V.s[m], sa = V.s[1 - m];
+    const int n_m = (m == 0) ? nx : ny, n_a = (m == 0) ? ny : nx;
+    const int PY = ny + 2 * kVolPad, PZ = nz + 2 * kVolPad;
+    // copy strides of this column's plane and in-plane axes (vt is [x][y][z])
+    const long Sm = (m == 0) ? (long)PY * PZ : (long)PZ;
+    const long Sa = (m == 0) ? (long)PZ : (long)PY * PZ;
+    double lo = fmax(0.0, ceil(fmin(sm, sm + Dm)));
+    double hi = fmin((double)(n_m - 1), floor(fmax(sm, sm + Dm)));
+    const double Ba = Da * rDm;
+    clip_range(lo, hi, sa - sm * Ba, Ba, -1.5, n_a + 0.5);
+    if (!(fabs(Dm) > 0.0) || !isfinite(Ba) || !colok) hi = lo - 1.0;
+    const int l0 = (int)fmax(lo, 0.0), l1 = (int)fmin(hi, (double)(n_m - 1));
+
+    if (threadIdx.x == 0) {
+        s_l0 = 0x7fffffff;
+        s_l1 = -1;
+        s_and = 3;
+        s_or = 0;
+    }
+    __syncthreads();
+    if (lane == 0 && colok) {
+        if (l0 <= l1) {
+            atomicMin(&s_l0, l0);
+            atomicMax(&s_l1, l1);
+        }
+        atomicAnd(&s_and, 1 << m);
+        atomicOr(&s_or, 1 << m);
+    }
+    __syncthreads();
+    // block-uniform values read from LDS, made scalar
+    const int L0 = __builtin_amdgcn_readfirstlane(s_l0), L1 = __builtin_amdgcn_readfirstlane(s_l1);
+    const bool mixed = __builtin_amdgcn_readfirstlane(s_and) != __builtin_amdgcn_readfirstlane(s_or);
+
+    // this lane's ray
+    const bool valid = colok && b < nv;
+    double D[3];
+    const double len = ray_setup(V, nu, nv, ac, min(b, nv - 1), D);
+    const double Dz = D[2];
+    const double Bz = Dz * rDm;
+    double zlo = (double)l0, zhi = (double)l1;
+    clip_range(zlo, zhi, V.s[2] - sm * Bz, Bz, -1.5, nz + 0.5);
+    const bool act = valid && zlo <= zhi && isfinite(Bz);
+    const int lz0 = act ? (int)zlo : 0x7fffffff, lz1 = act ? (int)zhi : -1;
+    const float scale = (float)(h * len / fabs(D[m]));
+    const double szp = V.s[2] + kVolPad;
+    int zi = 0, bi = 0;
+    uint32_t zf = 0, bfr = 0;
+    if (act) {
+        const double z0 = fma(((double)lz0 - sm) * rDm, Dz, szp);
+        const double g0 = floor(z0), gb = floor(Bz);
+        zi = (int)g0;
+        zf = frac_u32(z0 - g0);
+        bi = (int)gb;
+        bfr = frac_u32(Bz - gb);
+    }
+    // planes on which every active lane of this wave samples: no per-sample test there
+    int f_lo = act ? lz0 : -0x7fffffff, f_hi = act ? lz1 : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        f_lo = max(f_lo, __shfl_xor(f_lo, o, 64));
+        f_hi = min(f_hi, __shfl_xor(f_hi, o, 64));
+    }
+    f_lo = __builtin_amdgcn_readfirstlane(f_lo);
+    f_hi = __builtin_amdgcn_readfirstlane(f_hi);
+    float acc = 0.f;
+
+    for (int tb = L0; tb <= L1; tb += kLdsTB) {
+        // A: this column's tap and weight on plane tb + lane
+        int my_ai = kNoTap;
+        float my_wa = 0.f;
+        {
+            const int l = tb + lane;
+            if (l >= l0 && l <= l1) {
+                const double tau = ((double)l - sm) * rDm;
+                const double fa = fma(tau, Da, sa) + kVolPad;
+                const double ga = floor(fa);
+                my_ai = (int)ga;
+                my_wa = (float)(fa - ga);
+            }
+            AI[w][lane] = my_ai;
+        }
+        __syncthreads();
+        // B (wave 0): per-plane in-plane windows (lane = plane), per-chunk z
+        // windows from the tile's corner rays (lane = chunk), and whether each
+        // chunk fits the buffers
+        if (w == 0) {
+            int alo = 0x7fffffff, ahi = kNoTap;
+#pragma unroll
+            for (int c = 0; c < kLdsTC; ++c) {
+                const int ai = AI[c][lane];
+                if (ai != kNoTap) {
+                    alo = min(alo, ai);
+                    ahi = max(ahi, ai);
+                }
+            }
+            const int na = ahi >= alo ? ahi - alo + 2 : 0;
+            WL[lane] = alo;
+            NA[lane] = na;
+            const unsigned long long over = __ballot(na > kLdsAW);
+            if (lane < kLdsNQ) {
+                const int cs = tb + lane * kLdsP, ce = min(cs + kLdsP - 1, L1);
+                int zl = 0, zn = 0;
+                if (cs <= L1 && !mixed) {
+                    const int c0 = ct * kLdsTC, c1 = min(c0 + kLdsTC - 1, nu - 1);
+                    const int b0 = rt * 64, b1 = min(b0 + 63, nv - 1);
+                    double zmin = HUGE_VAL, zmax = -HUGE_VAL;
+                    for (int q = 0; q < 4; ++q) {
+                        const int cc = (q & 1) ? c1 : c0, bb = (q & 2) ? b1 : b0;
+                        const ColD Cq = cols[(long)v * nu + cc];
+                        const double rq = (m == 0) ? Cq.rdx : Cq.rdy;
+                        const double dzq = (V.d[2] + (cc - 0.5 * (nu - 1)) * V.u[2] + (bb - 0.5 * (nv - 1)) * V.v[2]) -
+                                           V.s[2];
+                        for (int r = 0; r < 2; ++r) {
+                            const double z = fma(((double)(r ? ce : cs) - sm) * rq, dzq, szp);
+                            zmin = fmin(zmin, z);
+                            zmax = fmax(zmax, z);
+                        }
+                    }
+                    const double flo = fmax(floor(zmin) - 1.0, 0.0), fhi = fmin(floor(zmax) + 2.0, (double)(PZ - 1));
+                    if (isfinite(flo) && isfinite(fhi) && fhi >= flo && fhi - flo + 1.0 <= (double)kLdsZW) {
+                        zl = (int)flo;
+                        zn = (int)(fhi - flo) + 1;
+                    } else {
+                        zn = kLdsZW + 1;  // does not fit
+                    }
+                }
+                CZ[lane] = zl;
+                CN[lane] = zn;
+                const unsigned grp = (unsigned)((over >> (lane * kLdsP)) & ((1ull << kLdsP) - 1));
+                CD[lane] = (mixed || zn > kLdsZW || grp != 0u) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        // this lane's plane's offset in a staging buffer, relative to z = 0
+        const int my_off =
+            my_ai == kNoTap ? 0 : ((lane & (kLdsP - 1)) * kLdsAW + (my_ai - WL[lane])) * kLdsZW - CZ[lane / kLdsP];
+        const int tend = min(tb + kLdsTB - 1, L1);
+        const int nq = (tend - tb) / kLdsP + 1;
+        // C: chunks, staging double-buffered; a chunk whose window does not
+        // fit is sampled from the copy directly
+        LdsStage st;
+        // the window of plane w of chunk q (wave-uniform)
+        auto issue = [&](int q) {
+            const int cs = tb + q * kLdsP, pl = cs + w, j = q * kLdsP + w;
+            lds_stage_issue<VT, WIDE>(st, vt, lane, pl <= L1, pl, __builtin_amdgcn_readfirstlane(WL[j]),
+                                      __builtin_amdgcn_readfirstlane(NA[j]), __builtin_amdgcn_readfirstlane(CZ[q]),
+                                      __builtin_amdgcn_readfirstlane(CN[q]), Sm, Sa);
+        };
+        const int wplane = w * kLdsAW * kLdsZW;  // this wave's plane in a buffer
+        bool dnext = __builtin_amdgcn_readfirstlane(CD[0]) != 0;
+        if (!dnext) {
+            issue(0);
+            lds_stage_commit(st, lane, S, wplane);
+        }
+        __syncthreads();
+        for (int q = 0; q < nq; ++q) {
+            const int cs = tb + q * kLdsP, ce = min(cs + kLdsP - 1, L1);
+            const bool direct = dnext;
+            if (q + 1 < nq) {
+                dnext = __builtin_amdgcn_readfirstlane(CD[q + 1]) != 0;
+                if (!dnext) issue(q + 1);
+            }
+            if (act) {
+                const int sb = (q & 1) * kLdsRows * kLdsZW;
+                // one sample on plane l (wave-uniform): taps from LDS or, for a
+                // direct chunk, from the copy
+                auto lds_sample = [&](int l) {
+                    const int j = l - tb;
+                    const float wa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wa), j));
+                    const int o = sb + __builtin_amdgcn_readlane(my_off, j) + zi;
+                    const float x00 = S[o], x01 = S[o + 1], x10 = S[o + kLdsZW], x11 = S[o + kLdsZW + 1];
+                    const float wz = (float)zf * 0x1p-32f;
+                    const float q0 = fmaf(wz, x01 - x00, x00), q1 = fmaf(wz, x11 - x10, x10);
+                    acc += fmaf(wa, q1 - q0, q0);
+                    const uint32_t nf = zf + bfr;
+                    zi += bi + (nf < zf ? 1 : 0);
+                    zf = nf;
+                };
+                auto direct_sample = [&](int l) {
+                    const int j = l - tb;
+                    const float wa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wa), j));
+                    const int ai = __builtin_amdgcn_readlane(my_ai, j);
+                    const long g = (long)(l + kVolPad) * Sm + (long)ai * Sa + zi;
+                    float2 p0, p1;
+                    if (WIDE) {
+                        p0 = load_pair(vt + g, 0u);
+                        p1 = load_pair(vt + g + Sa, 0u);
+                    } else {
+                        p0 = load_pair(vt, (uint32_t)g);
+                        p1 = load_pair(vt, (uint32_t)(g + Sa));
+                    }
+                    const float wz = (float)zf * 0x1p-32f;
+                    const float q0 = fmaf(wz, p0.y - p0.x, p0.x), q1 = fmaf(wz, p1.y - p1.x, p1.x);
+                    acc += fmaf(wa, q1 - q0, q0);
+                    const uint32_t nf = zf + bfr;
+                    zi += bi + (nf < zf ? 1 : 0);
+                    zf = nf;
+                };
+                // planes where every active lane samples need no per-lane test
+                const int f0 = max(cs, f_lo), f1 = min(ce, f_hi);
+                auto run = [&](auto smp) {
+                    if (f0 > f1) {
+                        for (int l = cs; l <= ce; ++l)
+                            if (l >= lz0 && l <= lz1) smp(l);
+                        return;
+                    }
+                    for (int l = cs; l < f0; ++l)
+                        if (l >= lz0) smp(l);
+                    int l = f0;
+                    for (; l + 3 <= f1; l += 4) {
+                        smp(l);
+                        smp(l + 1);
+                        smp(l + 2);
+                        smp(l + 3);
+                    }
+                    for (; l <= f1; ++l) smp(l);
+                    for (l = f1 + 1; l <= ce; ++l)
+                        if (l <= lz1) smp(l);
+                };
+                if (direct) {
+                    for (int l = cs; l <= ce; ++l)
+                        if (l >= lz0 && l <= lz1) direct_sample(l);
+                } else if (f0 > f1) {
+                    run(lds_sample);
+                } else {
+                    for (int l = cs; l < f0; ++l)
+                        if (l >= lz0) lds_sample(l);
+                    // every active lane samples planes f0..f1: the taps of the
+                    // next plane are read while this plane is blended (two
+                    // register sets in turn; past f1 the last address is read
+                    // again and the values are not used)
+                    int o = sb + __builtin_amdgcn_readlane(my_off, f0 - tb) + zi;
+                    float a00 = S[o], a01 = S[o + 1], a10 = S[o + kLdsZW], a11 = S[o + kLdsZW + 1];
+                    float b00, b01, b10, b11;
+                    auto blend = [&](int l, float x00, float x01, float x10, float x11, float wz) {
+                        const float wa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wa), l - tb));
+                        const float q0 = fmaf(wz, x01 - x00, x00), q1 = fmaf(wz, x11 - x10, x10);
+                        acc += fmaf(wa, q1 - q0, q0);
+                    };
+                    auto step = [&]() {
+                        const float wz = (float)zf * 0x1p-32f;
+                        const uint32_t nf = zf + bfr;
+                        zi += bi + (nf < zf ? 1 : 0);
+                        zf = nf;
+                        return wz;
+                    };
+                    for (int l = f0;;) {
+                        float wz = step();
+                        if (l < f1) o = sb + __builtin_amdgcn_readlane(my_off, l + 1 - tb) + zi;
+                        b00 = S[o];
+                        b01 = S[o + 1];
+                        b10 = S[o + kLdsZW];
+                        b11 = S[o + kLdsZW + 1];
+                        blend(l, a00, a01, a10, a11, wz);
+                        if (++l > f1) break;
+                        wz = step();
+                        if (l < f1) o = sb + __builtin_amdgcn_readlane(my_off, l + 1 - tb) + zi;
+                        a00 = S[o];
+                        a01 = S[o + 1];
+                        a10 = S[o + kLdsZW];
+                        a11 = S[o + kLdsZW + 1];
+                        blend(l, b00, b01, b10, b11, wz);
+                        if (++l > f1) break;
+                    }
+                    for (int l = f1 + 1; l <= ce; ++l)
+                        if (l <= lz1) lds_sample(l);
+                }
+            }
+            if (q + 1 < nq && !dnext) lds_stage_commit(st, lane, S, ((q + 1) & 1) * kLdsRows * kLdsZW + wplane);
+            __syncthreads();
+        }
+    }
+
+    double r2 = 0.0;
+    if (valid) {
+        const float lv = acc * scale;
+        if (MODE == kProjPlain) {
+            store_f(out, ((long)v * nv + b) * nu + a, lv);
+        } else {
+            const long gi = ((long)v * nv + b) * nu + a;
+            const long ot = ((long)v * nu + a) * nv + b;
+            const float yv = load_f(y, gi);
+            const float r = round_as<PT>(yv - lv);
+            if (MODE == kProjResidual) store_f(out, ot, r * scale);
+            r2 = (double)r * (double)r;
+        }
+    }
+    if (MODE == kProjResidual || MODE == kProjNorm) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+        if (lane == 0) wsum[w] = r2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int q = 0; q < kLdsTC; ++q) s += wsum[q];
+            partials[(long)t * n_ct + ct] = s;
+        }
+    }
+}
+
+bool project_lds_ok(const Level &L, int nviews_sub, int variant) {
+    if (!L.separable || !L.d_order || nviews_sub != L.nviews || variant == MGCT_PROJECTOR_GATHER) return false;
+    if (variant == MGCT_PROJECTOR_STAGED) return true;
+    // automatic: the staged projector where the volume outgrows the caches
+    return MGCT_PROJ_LDS && (size_t)L.nx * L.ny * L.nz >= (size_t)MGCT_PROJ_LDS_MIN_VOX;
+}
+
+size_t project_lds_blocks(const Level &L) {
+    const int n_ct = (L.nu + kLdsTC - 1) / kLdsTC;
+    return (size_t)n_ct * L.n_rt * L.nviews;
+}
+
+size_t plain_copy_elems(const Level &L) { return L.padded_vox(); }
+
+hipError_t launch_project_lds_mode(const void *vt, int vt_dtype, int mode, void *out, int out_dtype, const void *y,
+                                   int y_dtype, double *partials, const Level &L, hipStream_t s) {
+    const int n_ct = (L.nu + kLdsTC - 1) / kLdsTC;
+    const int n_t = L.n_rt * L.nviews;
+    const unsigned nblk = (unsigned)n_ct * (unsigned)n_t;
+    const size_t copy_bytes = L.padded_vox() * (vt_dtype == MGCT_F32 ? 4 : 2);
+    const bool wide = copy_bytes > 0xFFFFFFF0ull;
+#define MGCT_LDS_W(VT, PT, MODE, TB, W)                                                                           \
+    k_project_lds<VT, PT, MODE, TB, W><<<nblk, 64 * kLdsTC, 0, s>>>(                                             \
+        (const VT *)vt, (PT *)out, (const TB *)y, partials, L.d_views, L.d_cols, L.d_order, n_ct, n_t, L.n_rt, L.nx, \
+        L.ny, L.nz, L.nu, L.nv, L.h)
+#define MGCT_LDS(VT, PT, MODE, TB)                                \
+    do {                                                          \
+        if (wide) MGCT_LDS_W(VT, PT, MODE, TB, true);             \
+        else MGCT_LDS_W(VT, PT, MODE, TB, false);                 \
+    } while (0)
+#define MGCT_LDS_VT(PT, MODE, TB)                                                                                 \
+    do {                                                                                                        \
+        if (vt_dtype == MGCT_F32) MGCT_LDS(float, PT, MODE, TB);                                                \
+        else if (vt_dtype == MGCT_BF16) MGCT_LDS(uint16_t, PT, MODE, TB);                                       \
+        else return hipErrorInvalidValue;                                                                       \
+    } while (0)
+    const bool of32 = out_dtype == MGCT_F32, of16 = out_dtype == MGCT_F16;
+    const bool yf32 = y_dtype == MGCT_F32, yf16 = y_dtype == MGCT_F16;
+    if (mode == kProjPlain) {
+        if (of32) MGCT_LDS_VT(float, kProjPlain, float);
+        else if (of16) MGCT_LDS_VT(_Float16, kProjPlain, float);
+        else return hipErrorInvalidValue;
+    } else if (mode == kProjResidual) {
+        if (of32 && yf32) MGCT_LDS_VT(float, kProjResidual, float);
+        else if (of32 && yf16) MGCT_LDS_VT(float, kProjResidual, _Float16);
+        else if (of16 && yf32) MGCT_LDS_VT(_Float16, kProjResidual, float);
+        else if (of16 && yf16) MGCT_LDS_VT(_Float16, kProjResidual, _Float16);
+        else return hipErrorInvalidValue;
+    } else if (mode == kProjNorm) {
+        if (yf32) MGCT_LDS_VT(float, kProjNorm, float);
+        else if (yf16) MGCT_LDS_VT(float, kProjNorm, _Float16);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef MGCT_LDS_VT
+#undef MGCT_LDS
+#undef MGCT_LDS_W
+    return hipGetLastError();
+}
+
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L, int view0,
                           int view_step, int nviews_sub, hipStream_t s) {
     dim3 grid((L.nu + 3) / 4, (L.nv + 63) / 64, nviews_sub);

@@ -43,6 +43,9 @@ struct ColD {
 
 // Padding (voxels) around the transposed volume copy read by the projector.
 constexpr int kVolPad = 2;
+// Bytes allocated past the end of the plain padded copy: the LDS projector
+// stages whole 64-value z runs and may read up to 63 values past a run's end.
+constexpr size_t kCopyTail = 256;
 
 struct Level {
     int nx = 0, ny = 0, nz = 0, nu = 0, nv = 0, nviews = 0;
@@ -53,6 +56,8 @@ struct Level {
     SepView *d_sep = nullptr;        // [view]       (separable only)
     ColD *d_cols = nullptr;          // [view][nu] (separable only)
     uint8_t *d_axis = nullptr;       // [view][nu] (separable) or [view][nv][nu]: 0 = x, 1 = y
+    int *d_order = nullptr;          // (separable) LDS projector's (view, row tile) order, view * n_rt + tile
+    int n_rt = 0;                    // row tiles of 64 rows
     long axis_row_stride = 0;        // 0 (separable) or nu
     size_t vox() const { return (size_t)nx * ny * nz; }
     size_t rays() const { return (size_t)nviews * nu * nv; }
@@ -114,6 +119,7 @@ struct Ctx {
     // storage of the Landweber steps' internal copies: the projector's
     // volume copy (F32 or BF16) and the data/residual stacks (F32 or F16)
     int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
+    int proj_variant = MGCT_PROJECTOR_AUTO;  // mgct_set_projector
     // divergence status: a Landweber step whose input residual exceeds the
     // previous step's (same grid, data, step size and filter) by more than
     // this factor, or a multigrid solve whose fine-grid residual grows by it
@@ -164,6 +170,13 @@ hipError_t launch_transpose_volume(const void *vol, int vol_dtype, void *vt, int
                                    hipStream_t s);
 hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dtype, const Level &L,
                           int view0, int view_step, int nviews_sub, hipStream_t s);
+// separable geometry, all views: the LDS-staged projector reading the plain
+// padded copy (launch_transpose_volume's layout); mode as for
+// launch_project_sep_mode (no OS-EMTR terms); partials: project_lds_blocks()
+bool project_lds_ok(const Level &L, int nviews_sub, int variant);
+size_t project_lds_blocks(const Level &L);
+hipError_t launch_project_lds_mode(const void *vt, int vt_dtype, int mode, void *out, int out_dtype, const void *y,
+                                   int y_dtype, double *partials, const Level &L, hipStream_t s);
 // separable geometry: pair-expanded copies for x-major and y-major rays
 size_t pair_copy_elems(const Level &L);
 hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,

@@ -38,6 +38,51 @@ def test_autograd_volume_and_geometry_gradients():
     assert e_vol <= 1e-5 and e_geo <= 1e-5
 
 
+def _identifiability(ctx, views0, n, h, nu, mu, p0, iters=25, step=0.05):
+    """How much of each geometry parameter's effect on the data survives when
+    the volume is re-solved: J_i = d(A(p) mu)/dp_i by central differences, R_i
+    = J_i minus its least-squares fit by A x (CGLS, `iters` iterations).
+    Returns diag(R^T R) / diag(J^T J) and the eigenvalues of R^T R scaled by
+    diag(J^T J) (the reduced Gauss-Newton matrix of the joint problem)."""
+    import torch
+    from synth import perturb_geometry
+    J = []
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = step
+        ctx.set_geometry(n, n, n, h, (0, 0, 0), nu, nu, perturb_geometry(views0, h, *(p0 + e)))
+        jp = ctx.project(mu).double()
+        ctx.set_geometry(n, n, n, h, (0, 0, 0), nu, nu, perturb_geometry(views0, h, *(p0 - e)))
+        jm = ctx.project(mu).double()
+        J.append(((jp - jm) / (2 * step)).reshape(-1))
+    ctx.set_geometry(n, n, n, h, (0, 0, 0), nu, nu, perturb_geometry(views0, h, *p0))
+    shp = ctx.shapes(0)[1]
+    R = []
+    for i in range(3):
+        bvec = J[i]
+        x = torch.zeros((n, n, n), device="cuda", dtype=torch.float64)
+        r = bvec.clone()
+        sv = ctx.backproject(r.float().reshape(shp)).double()
+        pd = sv.clone()
+        gam = float((sv * sv).sum())
+        for _ in range(iters):
+            q = ctx.project(pd.float()).double().reshape(-1)
+            al = gam / float((q * q).sum())
+            x += al * pd
+            r -= al * q
+            sv = ctx.backproject(r.float().reshape(shp)).double()
+            gn = float((sv * sv).sum())
+            pd = sv + (gn / gam) * pd
+            gam = gn
+        R.append(r)
+    Jm = torch.stack(J, 1)
+    Rm = torch.stack(R, 1)
+    Hf = (Jm.T @ Jm).cpu().numpy()
+    Hr = (Rm.T @ Rm).cpu().numpy()
+    d = np.sqrt(np.diag(Hf))
+    return np.diag(Hr) / np.diag(Hf), np.linalg.eigvalsh(Hr / np.outer(d, d))
+
+
 def test_joint_estimation_recovers_misalignment():
     import torch
     cfg = synth.CONFIGS["c3"]
@@ -69,11 +114,22 @@ def test_joint_estimation_recovers_misalignment():
         p = p - lr * (m1 / (1 - beta1 ** it)) / (np.sqrt(m2 / (1 - beta2 ** it)) + 1e-12)
     err = np.abs(p - p_true)
     say("joint estimation: hidden", p_true, "estimated", p, "error", err, "initial", err0)
-    # dx (source along the detector columns) and the detector tilt are
-    # identifiable; dz moves the source along z with the detector fixed, which
-    # for this trajectory is nearly equivalent to a z-translation of the object
-    # (absorbed by the reconstruction), so it is reported, not required
+    # dx (source along the detector columns) and the detector tilt converge
     assert err[0] <= 0.5 * err0[0] + 0.05 and err[2] <= 0.5 * err0[2] + 0.02
+    # dz moves the source along z with the detector fixed: apart from the
+    # depth-dependent magnification that is a z-translation of the object,
+    # which the re-solved volume absorbs.  The reduced Gauss-Newton matrix
+    # shows it: the fraction of each parameter's data signature that no
+    # volume change can reproduce (measured with the oracle at 32^3: dx 0.93,
+    # dz 0.085, tilt 0.90; smallest normalised eigenvalue 0.085, eigenvector
+    # along dz).  dz is required to be at least 4x less identifiable than dx
+    # and the tilt, and its estimate to stay inside the prior range widened
+    # by one voxel (Adam's normalised steps random-walk a flat direction).
+    mu_t = to_dev(synth.voxelize(ph, n, g0.h, ss=2))
+    ratio, eig = _identifiability(ctx, g0.views, n, g0.h, nu, mu_t, p_true)
+    say("identifiability with the volume re-solved (dx, dz, tilt):", ratio, "eigenvalues", eig)
+    assert ratio[1] <= 0.25 * min(ratio[0], ratio[2])
+    assert abs(p[1]) <= 2.0
 
 
 def test_joint_estimation_full_size():
@@ -125,3 +181,8 @@ def test_joint_estimation_full_size():
     err = np.abs(p - p_true)
     say("joint estimation 256^3: hidden", p_true, "estimated", p, "error", err, "initial", err0)
     assert err[0] <= 0.5 * err0[0] + 0.05 and err[2] <= 0.5 * err0[2] + 0.02
+    # dz: weakly identifiable, as at 64^3 (see the test above)
+    ratio, eig = _identifiability(ctx, views0, n, cfg.h, nu, ctx.synth_voxelize(ph, ss=2), p_true)
+    say("identifiability at 256^3 (dx, dz, tilt):", ratio, "eigenvalues", eig)
+    assert ratio[1] <= 0.25 * min(ratio[0], ratio[2])
+    assert abs(p[1]) <= 2.0
