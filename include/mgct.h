@@ -52,7 +52,8 @@ typedef enum {
     MGCT_ERR_HIP = -5,                  /* a HIP runtime call failed */
     MGCT_ERR_DIVERGED = -6,             /* the residual grew or is not finite: step size too large */
     MGCT_ERR_NOT_IMPLEMENTED = -7,      /* combination not provided (e.g. radial filter on non-power-of-2 grid) */
-    MGCT_ERR_NO_GEOMETRY = -8           /* mgct_set_geometry has not been called */
+    MGCT_ERR_NO_GEOMETRY = -8,          /* mgct_set_geometry has not been called */
+    MGCT_ERR_TOO_LARGE = -9             /* the grid exceeds mgct_project_noalloc's fixed scratch */
 } mgct_status;
 
 typedef enum { MGCT_F32 = 0, MGCT_F16 = 1, MGCT_BF16 = 2 } mgct_dtype;
@@ -220,6 +221,23 @@ int mgct_set_divergence(void *ctx, double ratio);
  * finite, or when ratio > 0, prev > 0 and cur > ratio * prev; else 0.
  */
 int mgct_residual_diverged(double prev, double cur, double ratio);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * projection as mgct_project on grid `level`, with the projector's padded
+ * volume copies in a fixed scratch of 40 MiB per GPU (FP32 grids up to about
+ * 128^3, BF16 up to about 160^3) instead of context workspaces.  Calls no
+ * allocating routine.  The grid's tables must exist: level 0 always does
+ * after mgct_set_geometry, another level after any earlier call on it (else
+ * MGCT_ERR_INVALID_ARG).  A grid whose copies exceed the scratch returns
+ * MGCT_ERR_TOO_LARGE before any launch.  vol, proj, dtypes and the stream as
+ * in mgct_project.  Every call on one GPU shares that GPU's scratch (it is
+ * cleared where it must start at zero on every call): calls that overlap on
+ * one GPU, from any context or stream, race.  No kernel timing is recorded.
+ */
+int mgct_project_noalloc(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype,
+                         hipStream_t stream);
 
 /*
  * Geometry derivative for joint model estimation (paper Sec. 1: geometry

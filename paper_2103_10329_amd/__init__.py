@@ -27,6 +27,7 @@ MGCT_ERR_HIP = -5
 MGCT_ERR_DIVERGED = -6
 MGCT_ERR_NOT_IMPLEMENTED = -7
 MGCT_ERR_NO_GEOMETRY = -8
+MGCT_ERR_TOO_LARGE = -9
 
 MGCT_F32, MGCT_F16, MGCT_BF16 = 0, 1, 2
 MGCT_FILTER_IDENTITY, MGCT_FILTER_STENCIL27, MGCT_FILTER_RADIAL, MGCT_FILTER_TRANSFER = 0, 1, 2, 3
@@ -75,6 +76,7 @@ SIGNATURES = {
     "mgct_set_geometry": (_ci, [_vp, _ci, _ci, _ci, _cd, _dp, _ci, _ci, _ci, _dp]),
     "mgct_project": (_ci, [_vp, _ci, _vp, _ci, _vp, _ci, _vp]),
     "mgct_backproject": (_ci, [_vp, _ci, _vp, _ci, _vp, _ci, _vp]),
+    "mgct_project_noalloc": (_ci, [_vp, _ci, _vp, _ci, _vp, _ci, _vp]),
     "mgct_precondition": (_ci, [_vp, _ci, _vp, _vp, _fp, _vp]),
     "mgct_estimate_step": (_ci, [_vp, _ci, _fp, _ci, _u64, _dp, _vp]),
     "mgct_landweber_step": (_ci, [_vp, _ci, _vp, _vp, _ci, _cd, _fp, _dp, _vp]),
@@ -304,6 +306,13 @@ class Context:
         check(mgct_estimate_step(self.handle, level, fp, iters, seed, ctypes.byref(a), _stream()),  # noqa: F821
               "mgct_estimate_step")
         return a.value
+
+    def project_noalloc(self, vol, out, level: int = 0):
+        """A vol into ``out`` with no device allocation (fixed per-GPU scratch;
+        concurrent calls on one GPU race)."""
+        check(mgct_project_noalloc(self.handle, level, _ptr(vol), _dtype_code(vol), _ptr(out),  # noqa: F821
+                                   _dtype_code(out), _stream()), "mgct_project_noalloc")
+        return out
 
     def landweber_step(self, vol, b, alpha, filt=None, level: int = 0, want_norm: bool = True):
         r = ctypes.c_double()

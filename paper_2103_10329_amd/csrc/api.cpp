@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -16,6 +17,8 @@
 
 using namespace mgct;
 
+// the fixed scratch of mgct_project_noalloc (end of this file)
+static int static_scratch_setup(int device);
 
 #define HIPCHK(x)                                  \
     do {                                           \
@@ -731,6 +734,7 @@ const char *mgct_status_string(int st) {
         case MGCT_ERR_OOM: return "device allocation failed";
         case MGCT_ERR_HIP: return "HIP runtime error";
         case MGCT_ERR_DIVERGED: return "iteration diverged (residual grew or is not finite, or no positive spectrum estimate)";
+        case MGCT_ERR_TOO_LARGE: return "grid exceeds the fixed scratch of the allocation-free entry point";
         case MGCT_ERR_NOT_IMPLEMENTED: return "not implemented for these arguments";
         case MGCT_ERR_NO_GEOMETRY: return "no geometry set";
         default: return "unknown status";
@@ -756,6 +760,7 @@ int mgct_create(int device, void **ctx_out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MGCT_ERR_INVALID_ARG;
     HIPCHK(hipSetDevice(device));
+    MGCHK(static_scratch_setup(device));
     Ctx *c = new Ctx();
     c->device = device;
     *ctx_out = c;
@@ -1241,6 +1246,75 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
         for (int n = 1; n < p->n_outer; ++n)
             if (diverged(resid_hist[(n - 1) * NL], resid_hist[n * NL], c.diverge_ratio)) return MGCT_ERR_DIVERGED;
     }
+    return MGCT_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Allocation-free projection: the fixed scratch and its entry point.
+//
+// One array per GPU, in the code object's device memory, holds the
+// projector's padded volume copies for mgct_project_noalloc.  Its device
+// address is looked up once per device (with that device current) when a
+// context is created there, and only that address is used from the host: the
+// array's name in host code is a host-side stand-in, not a device address.
+namespace {
+constexpr size_t kStaticScratchBytes = 40ull << 20;  // 40 MiB: FP32 pair copies of grids up to 128^3
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+void *static_scratch(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+static int static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return MGCT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return MGCT_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MGCT_ERR_HIP;
+    g_scratch_ptr[device] = ptr;
+    return MGCT_OK;
+}
+
+extern "C" {
+
+int mgct_project_noalloc(void *ctx, int level, const void *vol, int vol_dtype, void *proj, int proj_dtype,
+                         hipStream_t s) {
+    if (!ctx || !vol || !proj || !vol_dtype_ok(vol_dtype) || !stack_dtype_ok(proj_dtype)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    if (!c.has_geom) return MGCT_ERR_NO_GEOMETRY;
+    if (level < 0 || level >= Ctx::kMaxLevels) return MGCT_ERR_INVALID_ARG;
+    Level &L = c.levels[level];
+    if (L.nx == 0) return MGCT_ERR_INVALID_ARG;  // the grid's tables are built by an earlier call
+    char *base = static_cast<char *>(static_scratch(c.device));
+    if (!base) return MGCT_ERR_HIP;
+    // the projector's copy has the input's type, as in mgct_project
+    const int vt = vol_dtype;
+    const size_t es = vt == MGCT_F32 ? 4 : 2;
+    if (L.separable) {
+        const size_t one = align256(pair_copy_elems(L) * es);
+        if (2 * one > kStaticScratchBytes) return MGCT_ERR_TOO_LARGE;
+        // the copies' zero borders: the scratch keeps the previous call's contents
+        HIPCHK(launch_fill(reinterpret_cast<float *>(base), 2 * one / 4, 0.f, s));
+        HIPCHK(launch_transpose_pairs(vol, vol_dtype, base, base + one, vt, L, s));
+        HIPCHK(launch_project_sep(base, base + one, vt, proj, proj_dtype, L, 0, 1, L.nviews, s));
+        return MGCT_OK;
+    }
+    const size_t one = align256(L.padded_vox() * es);
+    if (one > kStaticScratchBytes) return MGCT_ERR_TOO_LARGE;
+    HIPCHK(launch_fill(reinterpret_cast<float *>(base), one / 4, 0.f, s));
+    HIPCHK(launch_transpose_volume(vol, vol_dtype, base, vt, L, s));
+    HIPCHK(launch_project(base, vt, proj, proj_dtype, L, 0, 1, L.nviews, s));
     return MGCT_OK;
 }
 

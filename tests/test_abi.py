@@ -43,7 +43,7 @@ def test_binding_has_no_undeclared_entry_points(lib):
 
 
 def test_status_strings(lib):
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         s = mg.mgct_status_string(code).decode()
         assert s and s != "unknown status"
     assert mg.mgct_status_string(-99).decode() == "unknown status"
