@@ -1706,92 +1706,241 @@ constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 // wave-uniform, so the column's detector-row sums for the wave's z values
 // (bp_column_sums) are formed once and added, with the in-plane hat weights
 // 1 - f and f (f = pos - floor(pos)), to those two rows.  The rows are picked
-// by a runtime index, so the per-view sums live in LDS slots private to each
-// lane (no other lane touches them: no barriers), with two spare rows for the
-// taps that fall just outside the block; after each view they are added to
-// FP64 registers and cleared.  The slot updates are plain LDS read-add-writes
-// (exact, as the slots are lane-private; the LDS atomic add measured about
-// five times slower here).  The parts write separate partial volumes,
-// summed with the view chunks afterwards.  Per voxel and view this forms
-// about 1.6 column sums against 2.5 for the 2 x 2 row blocks
+// by a runtime index, so the sums live in LDS slots private to each lane (no
+// other lane touches them: no barriers), with two spare rows for the taps
+// that fall just outside the block.  The slot updates are plain LDS
+// read-add-writes (exact, as the slots are lane-private; the LDS atomic add
+// measured about five times slower here).  The parts write separate partial
+// volumes, summed with the view chunks afterwards.  Per voxel and view this
+// forms about 1.6 column sums against 2.5 for the 2 x 2 row blocks
 // (k_backproject_blk, kept for comparison builds).
+//
+// The views go in groups of kBpGroup: the candidate columns of all the
+// group's views at the wave's plane form one list, and the per-column set-up
+// (ray parameter, in-plane position, z mapping, in FP64) runs one column per
+// lane over that list, so a batch of 64 lanes serves several views instead of
+// the dozen or so columns one view has at one plane.  The slots collect the
+// whole group's sums in FP32 and are added to FP64 registers (and cleared)
+// once per group.
 #ifndef MGCT_BP_PLROWS
 #define MGCT_BP_PLROWS 8
 #endif
+#ifndef MGCT_BP_GROUP
+#define MGCT_BP_GROUP 8
+#endif
 constexpr int kPlRows = MGCT_BP_PLROWS;
 constexpr int kPlSlots = kPlRows + 2;
+constexpr int kBpGroup = MGCT_BP_GROUP;
 
 // What the column loop needs of one column at the wave's plane (prepared
 // by one lane, read back by the whole wave from LDS).
 struct __align__(16) PlCol {
-    WinCol w;   // the column's z mapping at the plane
-    float whi;  // in-plane hat weight of the upper row
-    int rl;     // block row of the lower tap (-1 .. kPlRows-1)
+    WinCol w;      // the column's z mapping at the plane
+    float whi;     // in-plane hat weight of the upper row
+    int rl;        // block row of the lower tap (-1 .. kPlRows-1)
+    uint32_t off;  // element offset of the column's first detector row in the stack
 };
 
 // Column records per batch and the waves per SIMD the registers must allow,
 // by variant.  The single-output variant for grids of one 128-deep z chunk
 // (KZ = 2, no z-range test) runs 6 waves per SIMD: its records then go in
-// batches of 32 so that slots and records fit 6 blocks per CU in LDS (24 KB a
-// block), and its registers are held to 80 (a few spill outside the column
-// loop); at 128^3 x 360 views that is 3 % faster than 5 waves.  The others
-// keep batches of 64 and 5 waves (the deeper variant spilled inside the loop
-// at 6 and was a third slower).
+// batches of 32 so that slots and records fit 6 blocks per CU in LDS, and its
+// registers are held to 80.  The others keep batches of 64 and 5 waves.
 template <int KZ, int NP, bool ZS> constexpr bool bp_pl_six() { return KZ == 2 && NP == 1 && !ZS; }
 template <int KZ, int NP, bool ZS> constexpr int bp_pl_batch() { return bp_pl_six<KZ, NP, ZS>() ? 32 : 64; }
 template <int KZ, int NP, bool ZS> constexpr int bp_pl_minw() {
     return NP > 1 ? 1 : (bp_pl_six<KZ, NP, ZS>() ? 6 : 5);
 }
 
-template <int PART, int KZ, int NP, typename PT, bool ZS>
-__device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__restrict__ cv, const PT *base0,
-                                              const PT *base1, int P, int r0, int nu, int nv,
-                                              const float (&u)[KZ], double zw0, double zw1, float *slot,
-                                              PlCol *rec) {
-    // distance of the plane from the source along the major axis
-    const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
+__device__ __forceinline__ float uniform_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
+// The candidate columns of one view at plane P (those whose rays can cross
+// the in-plane rows r0-1 .. r0+kPlRows), as a range [lo, lo + n); n = 0 when
+// the view has no columns of this axis or (ZS) its extreme rows stay a voxel
+// away from the wave's z range [zw0, zw1] at this plane.
+template <int PART, bool ZS>
+__device__ __forceinline__ void bp_view_range(const SepView &S, int P, int r0, int nu, int nv, double zw0,
+                                              double zw1, int &lo, int &n) {
+    lo = 0;
+    n = 0;
+    if (!(S.flags & (PART == 0 ? 1 : 2))) return;
+    const double dm = (double)P - (PART == 0 ? S.sx : S.sy);  // plane's distance from the source
     if (ZS) {
-        // the view's extreme rows at this plane stay a voxel away from the
-        // wave's z range: nothing to add
         const double ta = dm * (PART == 0 ? S.r0lo : S.r1lo), tb = dm * (PART == 0 ? S.r0hi : S.r1hi);
         const double dzn = fma(S.vz, (double)(nv - 1), S.dz0);
         const double z1 = fma(ta, S.dz0, S.sz), z2 = fma(tb, S.dz0, S.sz);
         const double z3 = fma(ta, dzn, S.sz), z4 = fma(tb, dzn, S.sz);
         if (fmax(fmax(z1, z2), fmax(z3, z4)) <= zw0 - 1.0 || fmin(fmin(z1, z2), fmin(z3, z4)) >= zw1 + 1.0) return;
     }
-    const double inv_dm = 1.0 / dm;
     const float fp = (float)P, flo = (float)(r0 - 1), fhi = (float)(r0 + kPlRows);
     const float c1 = PART == 0 ? column_coord(S, fp, flo) : column_coord(S, flo, fp);
     const float c2 = PART == 0 ? column_coord(S, fp, fhi) : column_coord(S, fhi, fp);
-    int alo = (int)floorf(fminf(c1, c2) - 0.01f);
-    int ahi = (int)ceilf(fmaxf(c1, c2) + 0.01f);
-    alo = __builtin_amdgcn_readfirstlane(max(alo, 0));
-    ahi = __builtin_amdgcn_readfirstlane(min(ahi, nu - 1));
+    const int alo = max((int)floorf(fminf(c1, c2) - 0.01f), 0);
+    const int ahi = min((int)ceilf(fmaxf(c1, c2) + 0.01f), nu - 1);
+    lo = alo;
+    n = max(ahi - alo + 1, 0);
+}
+
+// The column walk, software-pipelined: the next column's record is read and
+// its detector-row loads issued before the current column's sums are formed,
+// so each wave keeps two columns' loads in flight.  Columns whose rows lie at
+// least half a voxel apart along z (|1/tz| < 2, the usual case) take a fixed
+// window of 4 rows (it holds every row within one voxel of z; the hat weights
+// of the others are 0); the others re-read their record and take the
+// variable window of bp_column_sums.  Needs nv >= 4.
+template <int KZ, int NP> struct BpFetch {
+    float v[NP][KZ][4];  // the window's rows
+    float d0[KZ];        // hat argument of the window's first row
+    float tzh, whi;
+    int rl, l;           // slot row, record index (wave-uniform)
+    bool w4;             // the 4-row window applies (wave-uniform)
+};
+
+template <int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_fetch(BpFetch<KZ, NP> &F, const PlCol *rec, int l, const PT *pt0,
+                                         const PT *pt1, int nv, const float (&u)[KZ]) {
+    PlCol R = rec[l];
+    const uint32_t off = __builtin_amdgcn_readfirstlane(R.off);
+    F.rl = __builtin_amdgcn_readfirstlane(R.rl);
+    F.l = l;
+    R.w.rtz = uniform_f(R.w.rtz);
+    F.w4 = fabsf(R.w.rtz) < 2.f;
+    F.tzh = R.w.tzh;
+    F.whi = R.whi;
+    const float hi = (float)(nv - 4) - R.w.R0;
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        float dl;
+        win_start(R.w, u[q], hi, dl, F.d0[q]);
+        const uint32_t bs = (uint32_t)(int)(dl + R.w.R0);
+        load_win<4>(pt0 + off, bs, F.v[0][q]);
+        if (NP > 1) load_win<4>(pt1 + off, bs, F.v[NP - 1][q]);
+    }
+}
+
+template <int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_finish(const BpFetch<KZ, NP> &F, const PlCol *rec, const PT *pt0,
+                                          const PT *pt1, int nv, const float (&u)[KZ], float *slot) {
+    float sums[NP][KZ];
+    if (F.w4) {
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) {
+            float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float h = hat(t == 0 ? F.d0[q] : fmaf((float)t, F.tzh, F.d0[q]));
+                s0 = fmaf(h, F.v[0][q][t], s0);
+                if (NP > 1) s1 = fmaf(h, F.v[NP - 1][q][t], s1);
+            }
+            sums[0][q] = s0;
+            if (NP > 1) sums[NP - 1][q] = s1;
+        }
+    } else {
+        PlCol R = rec[F.l];
+        const uint32_t off = __builtin_amdgcn_readfirstlane(R.off);
+        R.w.rtz = uniform_f(R.w.rtz);
+        bp_column_sums<KZ, NP, PT>(pt0 + off, (NP > 1) ? pt1 + off : nullptr, nv, R.w, u, sums);
+    }
+    float *sl = slot + (F.rl + 1) * KZ * 64;
+    const float whi = F.whi, wlo = 1.f - whi;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < KZ; ++q) {
+            float *e0 = sl + (p * kPlSlots * KZ + q) * 64, *e1 = sl + ((p * kPlSlots + 1) * KZ + q) * 64;
+            *e0 = fmaf(wlo, sums[p][q], *e0);
+            *e1 = fmaf(whi, sums[p][q], *e1);
+        }
+}
+
+// Walks the set bits of m (increasing), two columns in flight.  The last
+// prefetch repeats the current column (its loads are in bounds) and is
+// dropped.
+template <int KZ, int NP, typename PT>
+__device__ __forceinline__ void bp_walk(unsigned long long m, const PlCol *rec, const PT *pt0, const PT *pt1, int nv,
+                                        const float (&u)[KZ], float *slot) {
+    if (!m) return;
+    int la = __builtin_ctzll(m);
+    m &= m - 1;
+    BpFetch<KZ, NP> A, B;
+    bp_fetch<KZ, NP, PT>(A, rec, la, pt0, pt1, nv, u);
+    while (true) {
+        bool more = m != 0;
+        const int lb = more ? __builtin_ctzll(m) : la;
+        m &= m - 1;
+        bp_fetch<KZ, NP, PT>(B, rec, lb, pt0, pt1, nv, u);
+        bp_finish<KZ, NP, PT>(A, rec, pt0, pt1, nv, u, slot);
+        if (!more) break;
+        more = m != 0;
+        la = more ? __builtin_ctzll(m) : lb;
+        m &= m - 1;
+        bp_fetch<KZ, NP, PT>(A, rec, la, pt0, pt1, nv, u);
+        bp_finish<KZ, NP, PT>(B, rec, pt0, pt1, nv, u, slot);
+        if (!more) break;
+    }
+}
+
+// One group of views [vg0, vg0 + kBpGroup) n [.., vend) at the wave's plane:
+// sums into the slots.
+template <int PART, int KZ, int NP, typename PT, bool ZS>
+__device__ __forceinline__ void bp_plane_group(const SepView *__restrict__ sep, const ColD *__restrict__ cols,
+                                               const PT *__restrict__ pt0, const PT *__restrict__ pt1, int P,
+                                               int r0, int nu, int nv, int vg0, int vend, int view0,
+                                               int view_step, const float (&u)[KZ], double zw0, double zw1,
+                                               float *slot, PlCol *rec) {
     const int lane = threadIdx.x & 63;
-    // The candidate columns go in batches of RB (64, or 32 in the 6-wave
-    // variant): lane l < RB works out column a0 + l at this plane (ray parameter, in-plane position and rows, z
-    // mapping of the detector rows) and whether it reaches the block, and
-    // keeps the result in the wave's LDS records; the wave then walks the
-    // columns that do (the ballot's set bits, in increasing order), reading
-    // each record back with one broadcast load.  The per-column set-up costs
-    // one lane instead of the whole wave.  LDS operations of a wave complete
-    // in order, so a record written by one lane is seen by the next read,
-    // and the next batch's writes follow this batch's reads.
+    // lane g < kBpGroup: the candidate range of view vg0 + g
+    int lo = 0, n = 0;
+    if (lane < kBpGroup && vg0 + lane < vend)
+        bp_view_range<PART, ZS>(sep[view0 + (vg0 + lane) * view_step], P, r0, nu, nv, zw0, zw1, lo, n);
+    // the group's ranges one after the other: candidate c < tot belongs to the
+    // last view g with start[g] <= c, column c + shift[g]
+    int start[kBpGroup], shift[kBpGroup];
+    int tot = 0;
+#pragma unroll
+    for (int g = 0; g < kBpGroup; ++g) {
+        start[g] = tot;
+        shift[g] = __builtin_amdgcn_readlane(lo, g) - tot;
+        tot += __builtin_amdgcn_readlane(n, g);
+    }
+    // Batches of RB candidates (64, or 32 in the 6-wave variant): lane l < RB
+    // works out candidate c0 + l at this plane (ray parameter, in-plane
+    // position and rows, z mapping of the detector rows), whether it reaches
+    // the block, and keeps the result in the wave's LDS records; the wave
+    // then walks the columns that do (the ballot's set bits, in increasing
+    // order), reading each record back with broadcast loads.  LDS operations
+    // of a wave complete in order, so a record written by one lane is seen by
+    // the next read, and the next batch's writes follow this batch's reads.
     constexpr int RB = bp_pl_batch<KZ, NP, ZS>();
-    for (int a0 = alo; a0 <= ahi; a0 += RB) {
-        const int a = a0 + lane;
+    for (int c0 = 0; c0 < tot; c0 += RB) {
+        const int c = c0 + lane;
         bool ok = false;
-        if (lane < RB && a <= ahi) {
-            const ColD &C = cv[a];
-            const double tau = dm * (PART == 0 ? C.rdx : C.rdy);                 // ray parameter at the plane
+        if (lane < RB && c < tot) {
+            int g = 0, sh = shift[0];
+#pragma unroll
+            for (int t = 1; t < kBpGroup; ++t)
+                if (c >= start[t]) {
+                    g = t;
+                    sh = shift[t];
+                }
+            const int vl = vg0 + g;
+            const int v = view0 + vl * view_step;
+            const int a = c + sh;
+            const SepView &S = sep[v];
+            const ColD &C = cols[(long)v * nu + a];
+            const double dm = (double)P - (PART == 0 ? S.sx : S.sy);
+            const double tau = dm * (PART == 0 ? C.rdx : C.rdy);                         // ray parameter at the plane
             const double pos = PART == 0 ? fma(tau, C.dy, S.sy) : fma(tau, C.dx, S.sx);  // in-plane position
             const double fl = fmin(fmax(floor(pos), -1e9), 1e9);
             const double tz = tau * S.vz;             // row spacing along z at the plane
             const double zc = fma(tau, S.dz0, S.sz);  // z of row 0 at the plane
             PlCol R;
             R.rl = (int)fl - r0;
-            R.w = win_col(zc, tz, (PART == 0 ? C.dxv : C.dyv) * inv_dm, zw0);
+            R.w = win_col(zc, tz, (PART == 0 ? C.dxv : C.dyv) / dm, zw0);
             R.whi = (float)(pos - fl);
+            R.off = (uint32_t)(((long)vl * nu + a) * nv);
             ok = C.axis == PART && tau >= 0.0 && tau <= 1.0 && R.rl >= -1 && R.rl < kPlRows;
             if (ZS && ok) {
                 const double zend = fma(tz, (double)(nv - 1), zc);
@@ -1801,12 +1950,20 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
         }
         unsigned long long m = __ballot(ok);
         __builtin_amdgcn_wave_barrier();
+        if (nv >= 4) {
+            bp_walk<KZ, NP, PT>(m, rec, pt0, pt1, nv, u, slot);
+            m = 0;
+        }
         while (m) {
             const int l = __builtin_ctzll(m);
             m &= m - 1;
-            const PlCol R = rec[l];
-            const long ac = a0 + l;
-            float *sl = slot + (R.rl + 1) * KZ * 64;
+            PlCol R = rec[l];
+            // the record is the same in every lane: scalar column address,
+            // slot row and window-width branch
+            const uint32_t off = __builtin_amdgcn_readfirstlane(R.off);
+            const int rl = __builtin_amdgcn_readfirstlane(R.rl);
+            R.w.rtz = uniform_f(R.w.rtz);
+            float *sl = slot + (rl + 1) * KZ * 64;
             float old[NP][2][KZ];
 #pragma unroll
             for (int p = 0; p < NP; ++p)
@@ -1816,8 +1973,8 @@ __device__ __forceinline__ void bp_plane_view(const SepView &S, const ColD *__re
                     old[p][1][q] = sl[((p * kPlSlots + 1) * KZ + q) * 64];
                 }
             const float whi = R.whi, wlo = 1.f - whi;
-            const PT *col0 = base0 + ac * nv;
-            const PT *col1 = (NP > 1) ? base1 + ac * nv : nullptr;
+            const PT *col0 = pt0 + off;
+            const PT *col1 = (NP > 1) ? pt1 + off : nullptr;
             float sums[NP][KZ];
             bp_column_sums<KZ, NP, PT>(col0, col1, nv, R.w, u, sums);
 #pragma unroll
@@ -1839,14 +1996,16 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
                                               int nx, int ny, int nz, int nu, int nv, int nviews_sub, int view0,
                                               int view_step, int per_chunk, int nchunks) {
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int nplanes = PART == 0 ? nx : ny, nrows = PART == 0 ? ny : nx;
     const int nrb = (nrows + kPlRows - 1) / kPlRows;
     const int zchunks = (nz + 64 * KZ - 1) / (64 * KZ);
-    const int zc_id = wave % zchunks;
-    const int rb = (wave / zchunks) % nrb;
-    const int P = wave / zchunks / nrb;
-    if (P >= nplanes) return;  // whole wave; no barrier below
+    // block -> (4 consecutive planes, row block, z chunk); wave -> plane
+    const int zc_id = blockIdx.x % zchunks;
+    const int rb = (blockIdx.x / zchunks) % nrb;
+    const int P0 = blockIdx.x / zchunks / nrb * 4;
+    if (P0 >= nplanes) return;  // whole block, before any barrier
+    const int P = P0 + (threadIdx.x >> 6);
+    const bool live = P < nplanes;
     const int r0 = rb * kPlRows;
     double kd[KZ];
 #pragma unroll
@@ -1866,15 +2025,15 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
             for (int q = 0; q < KZ; ++q) acc[p][r][q] = 0.0;
     const int vbeg = blockIdx.y * per_chunk;
     const int vend = min(nviews_sub, vbeg + per_chunk);
-    for (int vl = vbeg; vl < vend; ++vl) {
-        const int v = view0 + vl * view_step;
-        const SepView S = sep[v];
-        if (!(S.flags & (PART == 0 ? 1 : 2))) continue;
-        const PT *base0 = pt0 + (long)vl * nu * nv;
-        const PT *base1 = (NP > 1) ? pt1 + (long)vl * nu * nv : nullptr;
-        bp_plane_view<PART, KZ, NP, PT, ZS>(S, cols + (long)v * nu, base0, base1, P, r0, nu, nv, u, zw0, zw1, slot,
-                                            rec);
-        // the view's sums into FP64, slots cleared (spare rows too)
+    for (int vg0 = vbeg; vg0 < vend; vg0 += kBpGroup) {
+        // The block's waves (neighbouring planes: nearly the same detector
+        // columns and rows) start each group together, so that their reads
+        // of the group's detector data meet in the caches.
+        __syncthreads();
+        if (!live) continue;
+        bp_plane_group<PART, KZ, NP, PT, ZS>(sep, cols, pt0, pt1, P, r0, nu, nv, vg0, vend, view0, view_step, u, zw0,
+                                             zw1, slot, rec);
+        // the group's sums into FP64, slots cleared (spare rows too)
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -1901,7 +2060,7 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
 #pragma unroll
         for (int q = 0; q < KZ; ++q) {
             const int k = (int)kd[q];
-            if (row < nrows && k < nz) {
+            if (live && row < nrows && k < nz) {
                 const long o = ((long)k * ny + j) * nx + i;
                 out[o] = (float)acc[0][r][q];
                 if (NP > 1) out[np_stride + o] = (float)acc[NP - 1][r][q];
@@ -1910,8 +2069,10 @@ __device__ __forceinline__ void bp_plane_wave(const PT *__restrict__ pt0, const 
     }
 }
 
-// Launch: grid (waves / 4, view chunks, 2 parts); part[] receives 2 x chunks
+// Launch: grid (blocks of 4 planes x row blocks x z chunks, view chunks, 2 parts);
+// part[] receives 2 x chunks
 // partial volumes per output (the second output np_stride floats further).
+// The stack's element offsets must fit 32 bits (checked by the launcher).
 template <int KZ, int NP, typename PT, bool ZS>
 __global__ __launch_bounds__(256, (bp_pl_minw<KZ, NP, ZS>())) void k_backproject_pl(const PT *__restrict__ pt0, const PT *__restrict__ pt1,
                                                         float *__restrict__ part, long np_stride,
@@ -1985,7 +2146,12 @@ static hipError_t launch_bp(const PT *pt0, const PT *pt1, OT *vol0, OT *vol1, fl
     float *part0 = part, *part1 = part ? part + (long)nslices * nvox : nullptr;
     if (nslices > 1 && !part) return hipErrorInvalidValue;
     if (bp_plane(L)) {
-        dim3 grid((unsigned)((waves / 2 + 3) / 4), (unsigned)nchunks, 2);
+        // column records carry 32-bit element offsets into the stack
+        if ((unsigned long long)nviews_sub * L.nu * L.nv > 0xFFFFFFFFull) return hipErrorNotSupported;
+        const long zch = (L.nz + 64 * KZ - 1) / (64 * KZ);
+        const long bx = zch * std::max((long)((L.nx + 3) / 4) * ((L.ny + kPlRows - 1) / kPlRows),
+                                       (long)((L.ny + 3) / 4) * ((L.nx + kPlRows - 1) / kPlRows));
+        dim3 grid((unsigned)bx, (unsigned)nchunks, 2);
         const long nps = (long)nslices * nvox;
 #define MGCT_BPL(K, Z)                                                                                              \
     k_backproject_pl<K, NP, PT, Z><<<grid, 256, 0, s>>>(pt0, pt1, part, nps, L.d_sep, L.d_cols, L.nx, L.ny, L.nz,     \
