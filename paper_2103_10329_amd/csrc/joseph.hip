@@ -601,6 +601,13 @@ hipError_t launch_project_sep_mode(const void *vtx, const void *vty, int vt_dtyp
 #define MGCT_PROJ_LDS_WAVES 6
 #endif
 
+// zp += zs on 64-bit fixed-point z positions, as one VALU instruction: written
+// out so that the compiler keeps one induction variable (left to itself it
+// splits the low word into a second one and adds a compare per step).
+__device__ __forceinline__ void z_advance(uint64_t &zp, uint64_t zs) {
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(zp) : "v"(zp), "v"(zs));
+}
+
 // ------------------------------------------ LDS-staged separable projector --
 //
 // The Joseph sums of k_project_sep with the four bilinear taps of every sample
@@ -763,16 +770,18 @@ __global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_ld
     const int lz0 = act ? (int)zlo : 0x7fffffff, lz1 = act ? (int)zhi : -1;
     const float scale = (float)(h * len / fabs(D[m]));
     const double szp = V.s[2] + kVolPad;
-    int zi = 0, bi = 0;
-    uint32_t zf = 0, bfr = 0;
+    // z position in 32.32 fixed point (integer part in the high word: the
+    // copy's z index; fraction in the low word) and its step per plane, as
+    // one 64-bit addition (a carry into the high word is the index step)
+    uint64_t zp = 0, zs = 0;
     if (act) {
         const double z0 = fma(((double)lz0 - sm) * rDm, Dz, szp);
         const double g0 = floor(z0), gb = floor(Bz);
-        zi = (int)g0;
-        zf = frac_u32(z0 - g0);
-        bi = (int)gb;
-        bfr = frac_u32(Bz - gb);
+        zp = ((uint64_t)(uint32_t)(int)g0 << 32) | frac_u32(z0 - g0);
+        zs = ((uint64_t)(uint32_t)(int)gb << 32) | frac_u32(Bz - gb);
     }
+    auto zi = [&]() { return (int)(uint32_t)(zp >> 32); };
+    auto zf = [&]() { return (uint32_t)zp; };
     // planes on which every active lane of this wave samples: no per-sample test there
     int f_lo = act ? lz0 : -0x7fffffff, f_hi = act ? lz1 : 0x7fffffff;
 #pragma unroll
@@ -887,20 +896,18 @@ __global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_ld
                 auto lds_sample = [&](int l) {
                     const int j = l - tb;
                     const float wa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wa), j));
-                    const int o = sb + __builtin_amdgcn_readlane(my_off, j) + zi;
+                    const int o = sb + __builtin_amdgcn_readlane(my_off, j) + zi();
                     const float x00 = S[o], x01 = S[o + 1], x10 = S[o + kLdsZW], x11 = S[o + kLdsZW + 1];
-                    const float wz = (float)zf * 0x1p-32f;
+                    const float wz = (float)zf() * 0x1p-32f;
                     const float q0 = fmaf(wz, x01 - x00, x00), q1 = fmaf(wz, x11 - x10, x10);
                     acc += fmaf(wa, q1 - q0, q0);
-                    const uint32_t nf = zf + bfr;
-                    zi += bi + (nf < zf ? 1 : 0);
-                    zf = nf;
+                    z_advance(zp, zs);
                 };
                 auto direct_sample = [&](int l) {
                     const int j = l - tb;
                     const float wa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_wa), j));
                     const int ai = __builtin_amdgcn_readlane(my_ai, j);
-                    const long g = (long)(l + kVolPad) * Sm + (long)ai * Sa + zi;
+                    const long g = (long)(l + kVolPad) * Sm + (long)ai * Sa + zi();
                     float2 p0, p1;
                     if (WIDE) {
                         p0 = load_pair(vt + g, 0u);
@@ -909,12 +916,10 @@ __global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_ld
                         p0 = load_pair(vt, (uint32_t)g);
                         p1 = load_pair(vt, (uint32_t)(g + Sa));
                     }
-                    const float wz = (float)zf * 0x1p-32f;
+                    const float wz = (float)zf() * 0x1p-32f;
                     const float q0 = fmaf(wz, p0.y - p0.x, p0.x), q1 = fmaf(wz, p1.y - p1.x, p1.x);
                     acc += fmaf(wa, q1 - q0, q0);
-                    const uint32_t nf = zf + bfr;
-                    zi += bi + (nf < zf ? 1 : 0);
-                    zf = nf;
+                    z_advance(zp, zs);
                 };
                 // planes where every active lane samples need no per-lane test
                 const int f0 = max(cs, f_lo), f1 = min(ce, f_hi);
@@ -949,7 +954,7 @@ __global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_ld
                     // next plane are read while this plane is blended (two
                     // register sets in turn; past f1 the last address is read
                     // again and the values are not used)
-                    int o = sb + __builtin_amdgcn_readlane(my_off, f0 - tb) + zi;
+                    int o = sb + __builtin_amdgcn_readlane(my_off, f0 - tb) + zi();
                     float a00 = S[o], a01 = S[o + 1], a10 = S[o + kLdsZW], a11 = S[o + kLdsZW + 1];
                     float b00, b01, b10, b11;
                     auto blend = [&](int l, float x00, float x01, float x10, float x11, float wz) {
@@ -958,30 +963,31 @@ __global__ __launch_bounds__(64 * kLdsTC, MGCT_PROJ_LDS_WAVES) void k_project_ld
                         acc += fmaf(wa, q1 - q0, q0);
                     };
                     auto step = [&]() {
-                        const float wz = (float)zf * 0x1p-32f;
-                        const uint32_t nf = zf + bfr;
-                        zi += bi + (nf < zf ? 1 : 0);
-                        zf = nf;
+                        const float wz = (float)zf() * 0x1p-32f;
+                        z_advance(zp, zs);
                         return wz;
                     };
-                    for (int l = f0;;) {
+                    // two samples per trip (the a-set is carried to the next
+                    // trip, the b-set is used within it); one sample left over
+                    int l = f0;
+                    for (; l + 1 <= f1; l += 2) {
                         float wz = step();
-                        if (l < f1) o = sb + __builtin_amdgcn_readlane(my_off, l + 1 - tb) + zi;
+                        o = sb + __builtin_amdgcn_readlane(my_off, l + 1 - tb) + zi();
                         b00 = S[o];
                         b01 = S[o + 1];
                         b10 = S[o + kLdsZW];
                         b11 = S[o + kLdsZW + 1];
                         blend(l, a00, a01, a10, a11, wz);
-                        if (++l > f1) break;
                         wz = step();
-                        if (l < f1) o = sb + __builtin_amdgcn_readlane(my_off, l + 1 - tb) + zi;
+                        const int on = sb + __builtin_amdgcn_readlane(my_off, min(l + 2, f1) - tb) + zi();
+                        o = l + 2 <= f1 ? on : o;
                         a00 = S[o];
                         a01 = S[o + 1];
                         a10 = S[o + kLdsZW];
                         a11 = S[o + kLdsZW + 1];
-                        blend(l, b00, b01, b10, b11, wz);
-                        if (++l > f1) break;
+                        blend(l + 1, b00, b01, b10, b11, wz);
                     }
+                    if (l == f1) blend(l, a00, a01, a10, a11, step());
                     for (int l = f1 + 1; l <= ce; ++l)
                         if (l <= lz1) lds_sample(l);
                 }
@@ -1726,7 +1732,7 @@ constexpr int kBpBI = MGCT_BP_BI, kBpBJ = MGCT_BP_BJ;
 #define MGCT_BP_PLROWS 8
 #endif
 #ifndef MGCT_BP_GROUP
-#define MGCT_BP_GROUP 8
+#define MGCT_BP_GROUP 16
 #endif
 constexpr int kPlRows = MGCT_BP_PLROWS;
 constexpr int kPlSlots = kPlRows + 2;
@@ -1788,8 +1794,9 @@ __device__ __forceinline__ void bp_view_range(const SepView &S, int P, int r0, i
 // so each wave keeps two columns' loads in flight.  Columns whose rows lie at
 // least half a voxel apart along z (|1/tz| < 2, the usual case) take a fixed
 // window of 4 rows (it holds every row within one voxel of z; the hat weights
-// of the others are 0); the others re-read their record and take the
-// variable window of bp_column_sums.  Needs nv >= 4.
+// of the others are 0; a 3-row window where |1/tz| < 1.5 measured slower); the
+// others re-read their record and take the variable window of
+// bp_column_sums.  Needs nv >= 4.
 template <int KZ, int NP> struct BpFetch {
     float v[NP][KZ][4];  // the window's rows
     float d0[KZ];        // hat argument of the window's first row
