@@ -181,6 +181,7 @@ def main():
                        cfg.n_ellipsoids, " + %g%% cubes" % (100 * cfg.cube_fraction) if cfg.cube_fraction else "",
                        cfg.noise_level)},
         "roofline": roofline,
+        "in_cone_fraction": in_cone_fraction(views, n, n, n, cfg.h, nu, nv),
         "a_plus_at_kernels_gvox_views_s": a_at,
         "a_plus_at_hbm_frac": 2 * bytes_per_launch / ((tA + tB) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms": kt,
@@ -205,11 +206,24 @@ def main():
 
 
 # HBM-side traffic of the dominant kernels from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE passes, scaled by the same counters on a plain copy of known
-# size, per launch, with their VALU and LDS issue fractions (wave-instructions
-# per CU cycle) and L2 hit rates from the counter passes; valid only for the
-# kernel source they were measured on.
-TRAFFIC = {}
+# WRITE_SIZE passes (KiB per dispatch), scaled by the same counters on a plain
+# 1 GiB copy (fetch x2.0, write x1.0), per launch, with their VALU and LDS
+# issue fractions (wave-instructions per CU cycle), L2 hit rates and VALU
+# instructions per voxel*view from the SQ/TCC pass; valid only for the kernel
+# source they were measured on (the fine grid of the 512^3 workload, one
+# Algorithm 1 step: A with the residual epilogue, A^T from the FP32 stack).
+TRAFFIC = {
+    ("k_project_lds", "c2"): {
+        "source_sha256": "ff4f43306cd8b186b525d0e6aa2f445fb1d3e779d9ed18c6a63258f4eb869efb",
+        "bytes_per_launch": 1.446e12, "fetch_kib": 6.813e8, "write_kib": 4.927e7,
+        "valu_issue": 0.789, "lds_issue": 0.106, "l2_hit": 0.126, "valu_insts_per_voxel_view": 35.4,
+        "profile": "profiles/project_backproject_512cube_1440x768_counters.md"},
+    ("k_backproject_pl", "c2"): {
+        "source_sha256": "ff4f43306cd8b186b525d0e6aa2f445fb1d3e779d9ed18c6a63258f4eb869efb",
+        "bytes_per_launch": 5.18e11, "fetch_kib": 2.462e8, "write_kib": 1.348e7,
+        "valu_issue": 0.931, "lds_issue": 0.120, "l2_hit": 0.115, "valu_insts_per_voxel_view": 37.8,
+        "profile": "profiles/project_backproject_512cube_1440x768_counters.md"},
+}
 
 
 def measured_counters(kernel, workload):
@@ -226,10 +240,11 @@ def measured_counters(kernel, workload):
     return t
 
 
-# Algorithmic FP32 operations per voxel*view (SURVEY-style count of the
-# kernels' arithmetic per Joseph sample times the measured samples per
-# voxel*view of these trajectories, 1.45): A 12 per sample (bilinear blend
-# 7, z step 3, weight 2); A^T about 3 weight pairs per voxel*view of 8.
+# Algorithmic FP32 operations per voxel*view, FMA counted as two: A does
+# about 12 per Joseph sample (two z interpolations and the in-plane blend with
+# the fixed-point step) at 1.45 samples per voxel*view on these trajectories;
+# A^T forms about 6 non-zero (ray, voxel) weights per voxel*view, each a hat
+# product and a multiply-add (about 24 in all).
 ALG_OPS = {"project@0": 1.45 * 12, "backproject@0": 24.0}
 
 
@@ -250,7 +265,8 @@ def make_roofline(dom, ms_avg, bytes_per_launch, voxel_views, workload):
     if cnt:
         hbm_util = cnt["bytes_per_launch"] / t / 1e9 / HBM_PEAK_GBS
         r.update({"valu_issue": cnt["valu_issue"], "lds_issue": cnt.get("lds_issue"), "l2_hit": cnt["l2_hit"],
-                  "hbm_util_measured": hbm_util})
+                  "hbm_util_measured": hbm_util, "valu_insts_per_voxel_view": cnt["valu_insts_per_voxel_view"],
+                  "counters": cnt["profile"]})
         if cnt["valu_issue"] > hbm_util:
             ops = ALG_OPS[dom] * voxel_views
             ach = ops / t / 1e12
@@ -536,7 +552,9 @@ def paper_shaped():
     del counts, b_true
     torch.cuda.synchronize()
     log("paper-shaped data %.1fs" % (time.time() - t0))
-    out = {"workload": "paper-shaped 640x640x2304, 3600 views of 760^2, FP32", "voxel_views": nx * nx * nz * V}
+    frac_in = in_cone_fraction(views, nx, nx, nz, cfg.h, cfg.nu, cfg.nv)
+    out = {"workload": "paper-shaped 640x640x2304, 3600 views of 760^2, FP32", "voxel_views": nx * nx * nz * V,
+           "in_cone_fraction": frac_in, "voxel_views_in_cone": nx * nx * nz * V * frac_in}
     # one A and one A^T (after a warm-up of each), HIP-event kernel times
     vol = truth.clone()
     p = ctx.project(vol)
@@ -549,7 +567,7 @@ def paper_shaped():
     ctx.kernel_timing(False)
     tA = ctx.kernel_time(mg.MGCT_OP_PROJECT, 0)[0]
     tB = ctx.kernel_time(mg.MGCT_OP_BACKPROJECT, 0)[0]
-    n4 = nx * nx * nz * V
+    n4 = out["voxel_views_in_cone"]  # rates count in-cone voxel*views only
     out["A_ms"], out["At_ms"] = tA, tB
     out["A_gvox_views_s"] = n4 / (tA * 1e-3) / 1e9
     out["At_gvox_views_s"] = n4 / (tB * 1e-3) / 1e9
@@ -592,6 +610,32 @@ def paper_shaped():
     out["pmg_iterations"] = iters
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def in_cone_fraction(views, nx, ny, nz, h, nu, nv, sub=4, chunk=8):
+    """Fraction of (voxel, view) pairs whose voxel centre projects onto the
+    detector (inside the outer pixel edges), on every sub-th voxel per axis,
+    evaluated on the device.  views: (V, 12) rows s, d, u, v as the library
+    takes them (pixel (a, b) centred at d + (a - (nu-1)/2) u + (b - (nv-1)/2) v)."""
+    import torch
+    dev = "cuda"
+    ax = [(torch.arange(0, m, sub, device=dev, dtype=torch.float64) - (m - 1) / 2.0) * h for m in (nx, ny, nz)]
+    X, Y, Z = torch.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    P = torch.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], 1)  # [n, 3]
+    vw = torch.from_numpy(np.ascontiguousarray(views)).to(dev)
+    inside = 0
+    for v0 in range(0, len(views), chunk):
+        w = vw[v0:v0 + chunk]
+        s, d, u, v = w[:, 0:3], w[:, 3:6], w[:, 6:9], w[:, 9:12]
+        nrm = torch.linalg.cross(u, v)
+        r = P[None, :, :] - s[:, None, :]                                   # [c, n, 3]
+        t = ((d - s) * nrm).sum(1)[:, None] / (r * nrm[:, None, :]).sum(2)  # ray parameter at the detector
+        q = s[:, None, :] + t[..., None] * r - d[:, None, :]
+        a = (q * u[:, None, :]).sum(2) / (u * u).sum(1)[:, None] + (nu - 1) / 2.0
+        b = (q * v[:, None, :]).sum(2) / (v * v).sum(1)[:, None] + (nv - 1) / 2.0
+        ok = (t > 0) & (a >= -0.5) & (a <= nu - 0.5) & (b >= -0.5) & (b <= nv - 0.5)
+        inside += int(ok.sum())
+    return inside / (P.shape[0] * len(views))
 
 
 def copy_calibration(size_mib=1024, reps=5):
