@@ -377,6 +377,18 @@ int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const
 int mgct_learned_stats(void *ctx, int *accepted, int *rejected);
 
 /*
+ * The two squared residual norms the learned step's judge compared last:
+ * r0 = ||b - A mu||^2 before the finest-grid update, r1 = ||b - A (mu + f(u))||^2
+ * with the network's refinement f(u); the refinement was kept iff r1 < r0.
+ * On scans of 720 views or more with the staged projector both run over every
+ * view_step-th view (view_step = n_views / 360; about 360 views, which spares
+ * the judge a full projection), otherwise over all views (view_step 1).
+ * Host pointers (view_step may be NULL).  MGCT_ERR_INVALID_ARG before any
+ * learned step.  Synchronises the device.
+ */
+int mgct_learned_judge(void *ctx, double *r0, double *r1, int *view_step);
+
+/*
  * Synthetic data on the device (training-set generation for the learned
  * preconditioner): exact line integrals through a phantom of K ellipsoids and
  * J axis-aligned boxes for every ray of the finest grid's geometry, and the

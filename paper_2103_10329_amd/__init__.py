@@ -98,6 +98,7 @@ SIGNATURES = {
     "mgct_geometry_param_grad": (_ci, [_ci, _dp, _dp, _cd, _cd, _cd, _cd, _dp]),
     "mgct_cnn_set_weights": (_ci, [_vp, ctypes.POINTER(ctypes.c_float), _ci]),
     "mgct_cnn_get_weights": (_ci, [_vp, ctypes.POINTER(ctypes.c_float), _ci]),
+    "mgct_learned_judge": (_ci, [_vp, _dp, _dp, ctypes.POINTER(ctypes.c_int)]),
     "mgct_cnn_forward": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
     "mgct_cnn_gradients": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.POINTER(ctypes.c_float), _dp, _vp]),
     "mgct_cnn_train_step": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _cd, _dp, _vp]),
@@ -455,6 +456,15 @@ class Context:
         n = ctypes.c_int()
         check(mgct_kernel_time(self.handle, op, level, ctypes.byref(ms), ctypes.byref(n)), "mgct_kernel_time")  # noqa: F821
         return ms.value, n.value
+
+    def learned_judge(self):
+        """(r0, r1, view_step) of the last learned step's judge: squared
+        residual norms before and after the network's refinement, over every
+        view_step-th view."""
+        r0, r1, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        check(mgct_learned_judge(self.handle, ctypes.byref(r0), ctypes.byref(r1), ctypes.byref(k)),  # noqa: F821
+              "mgct_learned_judge")
+        return r0.value, r1.value, k.value
 
     def learned_stats(self):
         a, r = ctypes.c_int(), ctypes.c_int()

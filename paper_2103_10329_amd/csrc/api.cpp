@@ -343,6 +343,22 @@ int do_landweber(Ctx &c, Level &L, int g, float *vol, const void *b, int b_dtype
     return MGCT_OK;
 }
 
+// ||b - A vol||^2 over the judge's views (every L.judge_step-th view, in the
+// staged projector's order; L.d_order_judge must exist)
+int do_residual_norm2_judge(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out,
+                            hipStream_t s) {
+    const size_t nblk = project_lds_blocks_judge(L);
+    WS(pp, double, "judge_partials", nblk * 8, false);
+    WS(pp2, double, "proj_partials2", 256 * 8, false);
+    void *vt;
+    MGCHK(plain_copy(c, L, g, vol, MGCT_F32, MGCT_F32, &vt, s));
+    KernelTimer t(c, MGCT_OP_PROJECT, g, s);
+    HIPCHK(launch_project_lds_mode(vt, MGCT_F32, 3, nullptr, MGCT_F32, b, MGCT_F32, pp, L, s, L.d_order_judge,
+                                   L.n_t_judge));
+    HIPCHK(launch_finish_sum_wide(pp, (int)nblk, pp2, norm2_out, s));
+    return MGCT_OK;
+}
+
 int do_residual_norm2(Ctx &c, Level &L, int g, const float *vol, const float *b, double *norm2_out, hipStream_t s) {
     if (L.separable) {
         const bool lds = project_lds_ok(L, L.nviews, c.proj_variant);
@@ -586,6 +602,21 @@ int mgct_learned_stats(void *ctx, int *accepted, int *rejected) {
     HIPCHK(hipMemset(cnt, 0, 8));
     if (accepted) *accepted = (int)h[0];
     if (rejected) *rejected = (int)h[1];
+    return MGCT_OK;
+}
+
+int mgct_learned_judge(void *ctx, double *r0, double *r1, int *view_step) {
+    if (!ctx || !r0 || !r1) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    auto it = c.ws.find("mg_judge");
+    if (it == c.ws.end() || c.judge_step_used == 0) return MGCT_ERR_INVALID_ARG;
+    double h[2];
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(h, it->second.first, 16, hipMemcpyDeviceToHost));
+    *r0 = h[0];
+    *r1 = h[1];
+    if (view_step) *view_step = c.judge_step_used;
     return MGCT_OK;
 }
 
@@ -1209,16 +1240,38 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
             if (p->capture_update) HIPCHK(launch_copy(u, p->capture_update, L.vox(), s));
             if (p->capture_iterate) HIPCHK(launch_copy(mu[0], p->capture_iterate, L.vox(), s));
             if (p->learned) {
+                // The judge keeps the network's refinement only if it lowers
+                // ||b - A mu||^2 below its value before the update.  On scans
+                // of 720 views or more it compares both over every
+                // judge_step-th view (about 360): the value before the update
+                // is then the sum of the Landweber projection's block
+                // partials over those views, and the one after it one staged
+                // projection of those views.  Otherwise over all views.
                 WS(cu, float, "mg_cnn_out", L.vox() * 4, false);
                 WS(try_mu, float, "mg_try", L.vox() * 4, false);
-                WS(r1, double, "mg_r1", 8, false);
+                WS(jr, double, "mg_judge", 16, false);  // the two squared norms compared
                 WS(cnt, unsigned, "learned_counters", 8, true);
+                const bool sub = L.judge_step > 1 && L.d_order_judge && project_lds_ok(L, L.nviews, c.proj_variant);
+                if (sub) {
+                    const size_t nblk = project_lds_blocks(L);
+                    const int n_t = L.n_rt * L.nviews;
+                    WS(pp, double, "proj_partials", nblk * 8, false);
+                    WS(pp2, double, "proj_partials2", 256 * 8, false);
+                    HIPCHK(launch_finish_sum_views(pp, L.d_order, (int)(nblk / n_t), n_t, L.n_rt, L.judge_step, pp2,
+                                                   jr, s));
+                } else {
+                    HIPCHK(hipMemcpyAsync(jr, r0, 8, hipMemcpyDeviceToDevice, s));
+                }
                 CnnBuffers B;
                 MGCHK(cnn_buffers(c, (long)L.vox(), false, B));
                 HIPCHK(cnn_forward(c.cnn, B, u, cu, L.nx, L.ny, L.nz, false, s));
                 HIPCHK(launch_add(mu[0], cu, try_mu, L.vox(), s));
-                MGCHK(do_residual_norm2(c, L, 0, try_mu, data[0], r1, s));
-                HIPCHK(launch_select_update(mu[0], u, try_mu, L.vox(), r0, r1, cnt, s));
+                if (sub)
+                    MGCHK(do_residual_norm2_judge(c, L, 0, try_mu, data[0], jr + 1, s));
+                else
+                    MGCHK(do_residual_norm2(c, L, 0, try_mu, data[0], jr + 1, s));
+                HIPCHK(launch_select_update(mu[0], u, try_mu, L.vox(), jr, jr + 1, cnt, s));
+                c.judge_step_used = sub ? L.judge_step : 1;
             } else {
                 HIPCHK(launch_axpy(mu[0], u, 1.0, L.vox(), s));
             }

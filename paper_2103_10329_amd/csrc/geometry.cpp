@@ -219,6 +219,19 @@ int build_level(Ctx &c, int g, Level &L) {
             if (hipMalloc(&L.d_order, sizeof(int) * order.size()) != hipSuccess) return MGCT_ERR_OOM;
             if (hipMemcpy(L.d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice) != hipSuccess)
                 return MGCT_ERR_HIP;
+            // the learned step's judge: every judge_step-th view (about 360
+            // views) once a scan has 720 views or more, in the same order
+            L.judge_step = V >= 720 ? V / 360 : 1;
+            if (L.judge_step > 1) {
+                std::vector<int> jo;
+                for (int e : order)
+                    if ((e / L.n_rt) % L.judge_step == 0) jo.push_back(e);
+                L.n_t_judge = (int)jo.size();
+                if (hipMalloc(&L.d_order_judge, sizeof(int) * jo.size()) != hipSuccess) return MGCT_ERR_OOM;
+                if (hipMemcpy(L.d_order_judge, jo.data(), sizeof(int) * jo.size(), hipMemcpyHostToDevice) !=
+                    hipSuccess)
+                    return MGCT_ERR_HIP;
+            }
         }
     }
     return MGCT_OK;
@@ -230,7 +243,11 @@ void free_level(Level &L) {
     if (L.d_cols) (void)hipFree(L.d_cols);
     if (L.d_axis) (void)hipFree(L.d_axis);
     if (L.d_order) (void)hipFree(L.d_order);
+    if (L.d_order_judge) (void)hipFree(L.d_order_judge);
     L.d_order = nullptr;
+    L.d_order_judge = nullptr;
+    L.judge_step = 1;
+    L.n_t_judge = 0;
     L.d_views = nullptr;
     L.d_sep = nullptr;
     L.d_cols = nullptr;

@@ -1036,18 +1036,28 @@ size_t project_lds_blocks(const Level &L) {
     return (size_t)n_ct * L.n_rt * L.nviews;
 }
 
+size_t project_lds_blocks_judge(const Level &L) {
+    const int n_ct = (L.nu + kLdsTC - 1) / kLdsTC;
+    return (size_t)n_ct * L.n_t_judge;
+}
+
 size_t plain_copy_elems(const Level &L) { return L.padded_vox(); }
 
 hipError_t launch_project_lds_mode(const void *vt, int vt_dtype, int mode, void *out, int out_dtype, const void *y,
-                                   int y_dtype, double *partials, const Level &L, hipStream_t s) {
+                                   int y_dtype, double *partials, const Level &L, hipStream_t s, const int *order,
+                                   int n_t) {
     const int n_ct = (L.nu + kLdsTC - 1) / kLdsTC;
-    const int n_t = L.n_rt * L.nviews;
+    if (!order) {
+        order = L.d_order;
+        n_t = L.n_rt * L.nviews;
+    }
+    if (!order || n_t <= 0) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)n_ct * (unsigned)n_t;
     const size_t copy_bytes = L.padded_vox() * (vt_dtype == MGCT_F32 ? 4 : 2);
     const bool wide = copy_bytes > 0xFFFFFFF0ull;
 #define MGCT_LDS_W(VT, PT, MODE, TB, W)                                                                           \
     k_project_lds<VT, PT, MODE, TB, W><<<nblk, 64 * kLdsTC, 0, s>>>(                                             \
-        (const VT *)vt, (PT *)out, (const TB *)y, partials, L.d_views, L.d_cols, L.d_order, n_ct, n_t, L.n_rt, L.nx, \
+        (const VT *)vt, (PT *)out, (const TB *)y, partials, L.d_views, L.d_cols, order, n_ct, n_t, L.n_rt, L.nx,     \
         L.ny, L.nz, L.nu, L.nv, L.h)
 #define MGCT_LDS(VT, PT, MODE, TB)                                \
     do {                                                          \

@@ -58,6 +58,10 @@ struct Level {
     uint8_t *d_axis = nullptr;       // [view][nu] (separable) or [view][nv][nu]: 0 = x, 1 = y
     int *d_order = nullptr;          // (separable) LDS projector's (view, row tile) order, view * n_rt + tile
     int n_rt = 0;                    // row tiles of 64 rows
+    // the learned step's judge views (every judge_step-th view; judge_step 1: all views) as a sub-list of
+    // d_order, n_t_judge entries (null when judge_step is 1)
+    int judge_step = 1, n_t_judge = 0;
+    int *d_order_judge = nullptr;
     long axis_row_stride = 0;        // 0 (separable) or nu
     size_t vox() const { return (size_t)nx * ny * nz; }
     size_t rays() const { return (size_t)nviews * nu * nv; }
@@ -120,6 +124,7 @@ struct Ctx {
     // volume copy (F32 or BF16) and the data/residual stacks (F32 or F16)
     int vt_dtype = MGCT_F32, stack_dtype = MGCT_F32;
     int proj_variant = MGCT_PROJECTOR_AUTO;  // mgct_set_projector
+    int judge_step_used = 0;                 // view step of the last learned step's judge (0: none yet)
     // divergence status: a Landweber step whose input residual exceeds the
     // previous step's (same grid, data, step size and filter) by more than
     // this factor, or a multigrid solve whose fine-grid residual grows by it
@@ -172,11 +177,15 @@ hipError_t launch_project(const void *vt, int vt_dtype, void *proj, int proj_dty
                           int view0, int view_step, int nviews_sub, hipStream_t s);
 // separable geometry, all views: the LDS-staged projector reading the plain
 // padded copy (launch_transpose_volume's layout); mode as for
-// launch_project_sep_mode (no OS-EMTR terms); partials: project_lds_blocks()
+// launch_project_sep_mode (no OS-EMTR terms); partials: project_lds_blocks().
+// order / n_t: another (view, row tile) list than L.d_order (the judge's
+// views), whose blocks then fill n_ct x n_t partials.
 bool project_lds_ok(const Level &L, int nviews_sub, int variant);
 size_t project_lds_blocks(const Level &L);
+size_t project_lds_blocks_judge(const Level &L);
 hipError_t launch_project_lds_mode(const void *vt, int vt_dtype, int mode, void *out, int out_dtype, const void *y,
-                                   int y_dtype, double *partials, const Level &L, hipStream_t s);
+                                   int y_dtype, double *partials, const Level &L, hipStream_t s,
+                                   const int *order = nullptr, int n_t = -1);
 // separable geometry: pair-expanded copies for x-major and y-major rays
 size_t pair_copy_elems(const Level &L);
 hipError_t launch_transpose_pairs(const void *vol, int vol_dtype, void *vtx, void *vty, int vt_dtype, const Level &L,
@@ -224,6 +233,10 @@ hipError_t launch_sumsq(const float *x, size_t n, double *partials, int nblocks,
 hipError_t launch_finish_sum(const double *partials, int n, double *out, hipStream_t s);
 // The same for many partials (two fixed-order stages; tmp holds 256 doubles).
 hipError_t launch_finish_sum_wide(const double *partials, int n, double *tmp, double *out, hipStream_t s);
+// the sum of the LDS projector's block partials (n_t x n_ct, block t of view
+// order[t] / n_rt) over the views with v % step == 0
+hipError_t launch_finish_sum_views(const double *partials, const int *order, int n_ct, int n_t, int n_rt, int step,
+                                   double *tmp, double *out, hipStream_t s);
 hipError_t launch_axpy(float *y, const float *x, double alpha, size_t n, hipStream_t s);
 hipError_t launch_scale_by_inv_sqrt(float *x, size_t n, const double *sumsq, double *lambda_out,
                                     hipStream_t s);

@@ -125,6 +125,28 @@ hipError_t launch_finish_sum_wide(const double *partials, int n, double *tmp, do
     return hipGetLastError();
 }
 
+// Stage one of the sum over a view subset: block b takes the (view, row tile)
+// entries [b*per, (b+1)*per) in order and adds the n_ct partials of those
+// whose view is a multiple of step.
+__global__ __launch_bounds__(256) void k_sum_stage_views(const double *partials, const int *order, int n_ct, int n_t,
+                                                         int n_rt, int step, int per, double *tmp) {
+    double acc = 0.0;
+    const int beg = blockIdx.x * per, end = min(n_t, beg + per);
+    for (int t = beg; t < end; ++t) {
+        if ((order[t] / n_rt) % step) continue;  // block-uniform
+        for (int ct = threadIdx.x; ct < n_ct; ct += 256) acc += partials[(long)t * n_ct + ct];
+    }
+    double r = block_sum(acc);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = r;
+}
+hipError_t launch_finish_sum_views(const double *partials, const int *order, int n_ct, int n_t, int n_rt, int step,
+                                   double *tmp, double *out, hipStream_t s) {
+    const int nb = 256, per = (n_t + nb - 1) / nb;
+    k_sum_stage_views<<<nb, 256, 0, s>>>(partials, order, n_ct, n_t, n_rt, step, per, tmp);
+    k_finish_sum<<<1, 256, 0, s>>>(tmp, nb, out);
+    return hipGetLastError();
+}
+
 __global__ void k_axpy(float *y, const float *x, float alpha, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         y[i] = fmaf(alpha, x[i], y[i]);

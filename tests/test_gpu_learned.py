@@ -171,3 +171,43 @@ def test_trained_weights_at_512_mixed_precision():
         del v
     say("512^3 (rel residual, masked error, seconds, (accepted, rejected)) plain", out[False], "learned", out[True])
     assert out[True][0] <= out[False][0] * 1.01
+
+
+def test_judge_over_view_subset():
+    """On a scan of 720 views (256^3, 384^2 detector) the judge compares the
+    residual before and after the network's refinement over every second view
+    (the staged projector's view-subset order; the value before the update
+    summed from the Landweber projection's block partials).  With two grids
+    and no coarse passes one iteration is one fine-grid step from the given
+    volume, so both values can be formed independently: full projections of
+    mu and of mu + f(u) (u captured from the solve, f the network), squared
+    residuals summed in FP64 over the even views.  The kept iterate follows
+    r1 < r0."""
+    import torch
+    from paper_2103_10329_amd import learned as L
+    cfg = synth.CONFIGS["c3"]
+    n = cfg.n
+    ctx = L.make_context(cfg, synth.trajectory(cfg.n_views, cfg.z_levels, cfg.pixel))
+    ph = synth.random_phantom(cfg, 1031)
+    gen = torch.Generator(device="cuda").manual_seed(2031)
+    b = L.poisson_data(ctx.synth_line_integrals(ph), cfg.noise_level, gen)
+    mu0 = 0.5 * ctx.synth_voxelize(ph, ss=1)
+    t, r = mg.ramp_table(n)
+    filt = mg.filter_radial(t, r)
+    alpha = ctx.estimate_step(filt, level=0, iters=20)
+    ctx.cnn_set_weights(L.load_weights())
+    u = torch.empty_like(mu0)
+    v = mu0.clone()
+    ctx.learned_stats()
+    ctx.multigrid_solve(v, b, 2, 1, filt, alphas=[alpha], coarse_passes=0, want_hist=False, learned=True,
+                        capture_update=u)
+    acc, rej = ctx.learned_stats()
+    r0, r1, k = ctx.learned_judge()
+    even = torch.arange(cfg.n_views, device="cuda") % 2 == 0
+    ref0 = float(((b - ctx.project(mu0)).double() ** 2)[even].sum())
+    ref1 = float(((b - ctx.project(mu0 + ctx.cnn_forward(u))).double() ** 2)[even].sum())
+    say("judge over every %d-th view: r0 %.9e (ref %.9e), r1 %.9e (ref %.9e), kept %d rejected %d"
+        % (k, r0, ref0, r1, ref1, acc, rej))
+    assert k == 2
+    assert abs(r0 - ref0) <= 1e-9 * ref0 and abs(r1 - ref1) <= 1e-9 * ref1
+    assert (acc, rej) == ((1, 0) if r1 < r0 else (0, 1))
