@@ -668,7 +668,7 @@ int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
     if (!S.master) {
         void *p = nullptr;
         const size_t fb = kCnnParams * 4;
-        if (hipMalloc(&p, 4 * fb + 2 * (size_t)27 * 32 * 16 + 3 * 2 * (size_t)27 * 32 * 32) != hipSuccess)
+        if (hipMalloc(&p, 4 * fb + 2 * (size_t)27 * 32 * 16 + 3 * 2 * (size_t)27 * 32 * 32 + 2 * 6144) != hipSuccess)
             return MGCT_ERR_OOM;
         char *q = (char *)p;
         S.master = (float *)q; q += fb;
@@ -678,7 +678,8 @@ int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
         S.p2f = (uint16_t *)q; q += 2 * 27 * 32 * 16;
         S.p3f = (uint16_t *)q; q += 2 * 27 * 32 * 32;
         S.p3d = (uint16_t *)q; q += 2 * 27 * 32 * 32;
-        S.p2d = (uint16_t *)q;
+        S.p2d = (uint16_t *)q; q += 2 * 27 * 32 * 32;
+        S.p4 = (uint16_t *)q;
     }
     HIPCHK(hipMemcpy(S.master, w, kCnnParams * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(S.adam_m, 0, kCnnParams * 4));

@@ -34,7 +34,24 @@ __device__ __forceinline__ uint16_t to_bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+// GELU x Phi(x) for the forward activations, without branches: Phi(x) =
+// 1 - erfc(y) / 2 for x >= 0 and erfc(y) / 2 below, y = |x| / sqrt(2), with
+// erfc(y) = (a1 t + ... + a5 t^5) exp(-y^2), t = 1 / (1 + p y), the rational
+// approximation of Abramowitz & Stegun, Handbook of Mathematical Functions,
+// 7.1.26 (|error| <= 1.5e-7 on erf).  The result is stored in BF16 (relative
+// step 2^-8), so the difference to the exact erf shows only as a rare
+// rounding flip; the backward pass keeps the exact derivative.
+__device__ __forceinline__ float gelu(float x) {
+    const float y = fabsf(x) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, y, 1.f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    q *= t * __expf(-y * y);  // erfc(y)
+    const float phi = x >= 0.f ? fmaf(-0.5f, q, 1.f) : 0.5f * q;
+    return x * phi;
+}
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
@@ -68,6 +85,25 @@ __global__ void k_pack_weights(const float *__restrict__ w, uint16_t *P2f, uint1
     }
 }
 
+// Layer 4 on the matrix cores (k_conv4_ym): P4[hl][dz][kc][j][16] holds, for
+// slot j = (dx, dy) (j = 3 (dy + 1) + dx + 1 < 9; zero for j >= 9), input
+// channels kc*16 .. kc*16 + 15 of W4[ci][tap (dx, dy, dz)] split into a BF16
+// high part (hl = 0) and the BF16 rounding of the remainder (hl = 1): the two
+// products together carry 16 bits of each FP32 weight.
+__global__ void k_pack_weights4(const float *__restrict__ w, uint16_t *P4) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * 3 * 2 * 32 * 16) return;
+    const int hl = i / 3072, dz = (i / 1024) % 3, kc = (i / 512) % 2, j = (i / 16) % 32, ci = kc * 16 + i % 16;
+    uint16_t r = 0;
+    if (j < 9) {
+        const int t = dz * 9 + (j / 3) * 3 + j % 3;  // kz*9 + ky*3 + kx
+        const float x = w[kW4 + ci * 27 + t];
+        const uint16_t hi = to_bf(x);
+        r = hl ? to_bf(x - bf(hi)) : hi;
+    }
+    P4[i] = r;
+}
+
 // ------------------------------------------------------ VALU layers ----
 
 // z1[v][16] = b1 + sum_t W1[co][t] u[v + off_t]; h1 = GELU(z1) (BF16).
@@ -84,14 +120,25 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ u, 
         long q;
         in[t] = tap_voxel(d, x, y, z, t, q) ? u[q] : 0.f;
     }
-#pragma unroll 4
-    for (int co = 0; co < 16; ++co) {
-        float acc = w[kB1 + co];
+    // the 16 outputs of a voxel leave as two 16-byte stores (and four for z1)
+    uint32_t pk[8];
 #pragma unroll
-        for (int t = 0; t < 27; ++t) acc = fmaf(w[kW1 + co * 27 + t], in[t], acc);
-        if (z1) z1[v * 16 + co] = acc;
-        h1[v * 16 + co] = to_bf(gelu(acc));
+    for (int c2 = 0; c2 < 8; ++c2) {
+        float acc[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int co = 2 * c2 + e;
+            float a = w[kB1 + co];
+#pragma unroll
+            for (int t = 0; t < 27; ++t) a = fmaf(w[kW1 + co * 27 + t], in[t], a);
+            acc[e] = a;
+        }
+        if (z1) *reinterpret_cast<float2 *>(z1 + v * 16 + 2 * c2) = make_float2(acc[0], acc[1]);
+        pk[c2] = (uint32_t)to_bf(gelu(acc[0])) | ((uint32_t)to_bf(gelu(acc[1])) << 16);
     }
+    uint4 *dst = reinterpret_cast<uint4 *>(h1 + v * 16);
+    dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
 }
 
 // out[v] = u[v] + b4 + sum_{t, ci} W4[ci][t] h3[v + off_t][ci]
@@ -431,13 +478,248 @@ __global__ __launch_bounds__(256) void k_conv_mfma_lds(const uint16_t *__restric
     }
 }
 
+// Forward convolution of the two 32-output layers on large grids:
+// persistent and weight-stationary.  A wave holds all 27 x CI/16 weight
+// fragments of the layer (the B operands) in registers, loaded once, and
+// owns one 32-voxel x tile at one z at a time, marching up y: the A fragment
+// of an input row at one (dx, dz) shift and channel chunk serves the three
+// output rows it reaches (dy = -1, 0, 1), whose accumulators rotate as the
+// march goes on, so every input fragment is loaded once for three MFMAs.
+// A block's 4 waves take 4 consecutive z (their input rows overlap in the
+// vector cache) and blocks loop over (x tile, z quad) items.  The products
+// are those of k_conv_mfma; per output the taps are summed grouped by input
+// row (dy, then dz, dx) rather than in tap order, so results agree to FP32
+// rounding.  nx % 32 == 0.
+template <int CI> struct ConvW {
+    bf16x8 f[27][CI / 16];
+};
+// One dz slice of an input row's A fragments: [dx][channel chunk].
+template <int CI> struct ConvSlice {
+    bf16x8 a[3][CI / 16];
+};
+
+// 32 zero channels: lanes whose shifted voxel lies outside the volume read
+// their A fragment from here (the address is chosen before the load, so no
+// select waits for it).
+__device__ const uint16_t kConvZeros[32] = {};
+
+// slice dz (0..2 for z - 1 .. z + 1) of input row yi
+template <int CI>
+__device__ __forceinline__ void conv_ym_load(ConvSlice<CI> &S, const uint16_t *__restrict__ X, const Dims &d,
+                                             int x0, int z, int yi, int dz, int m, int kh) {
+    const int zz = z + dz - 1;
+    const bool zok = yi >= 0 && yi < d.ny && zz >= 0 && zz < d.nz;
+    const long rowbase = zok ? ((long)zz * d.ny + yi) * d.nx : 0;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const int xx = x0 + m + dx - 1;
+        const bool ok = zok && xx >= 0 && xx < d.nx;
+        const uint16_t *src = (ok ? X + (rowbase + xx) * CI : kConvZeros) + kh * 8;
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc)
+            S.a[dx][kc] = *reinterpret_cast<const bf16x8 *>(src + (ok ? kc * 16 : 0));
+    }
+}
+
+// aP: output row yi - 1 (tap dy = +1), a0: yi (dy = 0), aN: yi + 1 (dy = -1)
+template <int CI, int DZ>
+__device__ __forceinline__ void conv_ym_mfma(const ConvSlice<CI> &S, const ConvW<CI> &W, floatx16 &aP,
+                                             floatx16 &a0, floatx16 &aN) {
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc) {
+            const int tb = DZ * 9 + dx;
+            aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a[dx][kc], W.f[tb][kc], aN, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a[dx][kc], W.f[tb + 3][kc], a0, 0, 0, 0);
+            aP = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a[dx][kc], W.f[tb + 6][kc], aP, 0, 0, 0);
+        }
+}
+
+// output row yo of the wave's tile: bias, GELU, BF16 (and the FP32 pre-activation)
+__device__ __forceinline__ void conv_ym_store(floatx16 &acc, const float *__restrict__ bias, float *zout,
+                                              uint16_t *__restrict__ hout, const Dims &d, int x0, int yo, int z,
+                                              int m, int kh) {
+    if (yo >= 0 && yo < d.ny) {
+        const long v0 = ((long)z * d.ny + yo) * d.nx + x0;
+        const float bc = bias[m];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            const float zv = acc[r] + bc;
+            if (zout) zout[v * 32 + m] = zv;
+            hout[v * 32 + m] = to_bf(gelu(zv));
+        }
+    }
+    acc = floatx16{};
+}
+
+// One input row: its three slices from buffers 0, 1, 2 (slices 0 and 1
+// already loaded on entry), the loads running two slices ahead (on exit
+// buffers 0 and 1 hold the next row's slices 0 and 1), then the completed
+// output row yi - 1.
+template <int CI>
+__device__ __forceinline__ void conv_ym_step(ConvSlice<CI> (&B)[3], const uint16_t *__restrict__ X,
+                                             const ConvW<CI> &W, const Dims &d, int x0, int z, int yi, int m,
+                                             int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN,
+                                             const float *__restrict__ bias, float *zout,
+                                             uint16_t *__restrict__ hout) {
+    conv_ym_load<CI>(B[2], X, d, x0, z, yi, 2, m, kh);
+    conv_ym_mfma<CI, 0>(B[0], W, aP, a0, aN);
+    conv_ym_load<CI>(B[0], X, d, x0, z, yi + 1, 0, m, kh);
+    conv_ym_mfma<CI, 1>(B[1], W, aP, a0, aN);
+    conv_ym_load<CI>(B[1], X, d, x0, z, yi + 1, 1, m, kh);
+    conv_ym_mfma<CI, 2>(B[2], W, aP, a0, aN);
+    conv_ym_store(aP, bias, zout, hout, d, x0, yi - 1, z, m, kh);
+}
+
+template <int CI>
+__global__ __launch_bounds__(256, 1) void k_conv_ym(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
+                                                    const float *__restrict__ bias, float *__restrict__ zout,
+                                                    uint16_t *__restrict__ hout, Dims d, int n_items) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 31, kh = lane >> 5;
+    ConvW<CI> W;
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc)
+            W.f[t][kc] = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + m) * CI + kc * 16 + kh * 8);
+    const int nxt = d.nx / 32;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int x0 = (it % nxt) * 32, z = (it / nxt) * 4 + w;
+        if (z >= d.nz) continue;  // whole wave; no barrier in this kernel
+        // input rows -1 .. ny (row yi completes output row yi - 1); the
+        // three accumulators rotate, three rows per trip
+        floatx16 A0{}, A1{}, A2{};
+        ConvSlice<CI> B[3];
+        conv_ym_load<CI>(B[0], X, d, x0, z, -1, 0, m, kh);
+        conv_ym_load<CI>(B[1], X, d, x0, z, -1, 1, m, kh);
+        for (int yi = -1; yi <= d.ny; yi += 3) {
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi, m, kh, A0, A1, A2, bias, zout, hout);
+            if (yi + 1 > d.ny) break;
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 1, m, kh, A1, A2, A0, bias, zout, hout);
+            if (yi + 2 > d.ny) break;
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 2, m, kh, A2, A0, A1, bias, zout, hout);
+        }
+    }
+}
+
+// Layer 4 (32 channels -> 1) on the matrix cores.  For an input row the
+// products of every input voxel with the weights of all nine in-plane taps
+// (dx, dy) are one small GEMM: E[m][j] = sum over dz and channels of
+// h3[x0 + m, yi, z + dz][c] W4[c][tap(j, dz)] (K = 3 x 32 in 16-channel
+// chunks, N = 9 of 32 columns, each weight as a BF16 pair so that 16 bits of
+// it are kept), whose result goes to LDS; output (x, yo) then adds
+// E[x - x0 + dx][(dx, dy)] over dx for the row yo = yi - dy.  A wave's 32
+// input voxels x0 .. x0 + 31 serve the 30 outputs x0 + 1 .. x0 + 30 (tiles at
+// stride 30), marching up y with three output rows in flight; a block's 4
+// waves take 4 consecutive z.  The next row's A fragments load while the
+// current row is worked on.
+struct Conv4Row {
+    bf16x8 a[3][2];  // [dz][channel chunk]
+};
+
+__device__ __forceinline__ void conv4_load(Conv4Row &R, const uint16_t *__restrict__ h3, const Dims &d, int x,
+                                           int z, int yi, int kh) {
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+        const int zz = z + dz - 1;
+        const bool ok = yi >= 0 && yi < d.ny && zz >= 0 && zz < d.nz && x >= 0 && x < d.nx;
+        const uint16_t *src = (ok ? h3 + (((long)zz * d.ny + yi) * d.nx + x) * 32 : kConvZeros) + kh * 8;
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) R.a[dz][kc] = *reinterpret_cast<const bf16x8 *>(src + (ok ? kc * 16 : 0));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ P4,
+                                                  const float *__restrict__ w, const float *__restrict__ u,
+                                                  float *__restrict__ out, Dims d) {
+    __shared__ float E[4][32 * 9];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 31, kh = lane >> 5;
+    const int ntile = (d.nx + 29) / 30;
+    const int x0 = (blockIdx.x % ntile) * 30 - 1, z = (blockIdx.x / ntile) * 4 + wv;
+    if (z >= d.nz) return;  // whole wave; no barrier in this kernel
+    bf16x8 Bf[2][3][2];
+#pragma unroll
+    for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+                Bf[hl][dz][kc] =
+                    *reinterpret_cast<const bf16x8 *>(P4 + ((((hl * 3 + dz) * 2 + kc) * 32 + m) * 16 + kh * 8));
+    const float b4 = w[kB4];
+    float *Ew = E[wv];
+    const int xo = x0 + 1 + m;                   // this lane's output x (lanes m < 30, kh = 0)
+    const bool gather = kh == 0 && m < 30 && xo < d.nx;
+    float oP = 0.f, o0 = 0.f, oN = 0.f;          // output rows yi - 1, yi, yi + 1
+    // one input row from buffer C (the next row's loads already in flight)
+    auto row = [&](const Conv4Row &C, int yi) {
+        floatx16 acc{};
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+                for (int hl = 0; hl < 2; ++hl)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.a[dz][kc], Bf[hl][dz][kc], acc, 0, 0, 0);
+        if (m < 9) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Ew[(8 * (r >> 2) + 4 * kh + (r & 3)) * 9 + m] = acc[r];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (gather) {
+            // slot j = 3 (dy + 1) + dx + 1 of input m + 1 + dx
+            const float *e = Ew + (m + 1) * 9;
+            oN += e[-9 + 0] + e[1] + e[9 + 2];   // dy = -1 -> output row yi + 1
+            o0 += e[-9 + 3] + e[4] + e[9 + 5];   // dy = 0
+            oP += e[-9 + 6] + e[7] + e[9 + 8];   // dy = +1 -> output row yi - 1
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (gather && yi - 1 >= 0) {
+            const long v = ((long)z * d.ny + (yi - 1)) * d.nx + xo;
+            out[v] = u[v] + (oP + b4);
+        }
+        oP = o0;
+        o0 = oN;
+        oN = 0.f;
+    };
+    Conv4Row RA, RB;
+    conv4_load(RA, h3, d, x0 + m, z, -1, kh);
+    for (int yi = -1; yi <= d.ny; yi += 2) {
+        conv4_load(RB, h3, d, x0 + m, z, yi + 1, kh);
+        row(RA, yi);
+        if (yi + 1 > d.ny) break;
+        conv4_load(RA, h3, d, x0 + m, z, yi + 2, kh);
+        row(RB, yi + 1);
+    }
+}
+
 #ifndef MGCT_CONV_LDS
 #define MGCT_CONV_LDS 1
 #endif
 // launch of either convolution kernel
+#ifndef MGCT_CONV_YM_MIN_VOX
+#define MGCT_CONV_YM_MIN_VOX (128L * 128 * 128)  // forward on the marching kernel from this many voxels
+#endif
 template <int CI, int MODE>
 static void launch_conv(const uint16_t *X, const uint16_t *P, const float *bias, const float *zprev, float *zout,
                         uint16_t *hout, int nout, Dims d, hipStream_t s) {
+    if (MODE == 0 && (long)d.nx * d.ny * d.nz >= MGCT_CONV_YM_MIN_VOX) {
+        static int n_cu = 0;
+        if (!n_cu) {
+            int dev = 0;
+            hipDeviceProp_t prop;
+            n_cu = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                       ? prop.multiProcessorCount
+                       : 256;
+        }
+        const int n_items = (d.nx / 32) * ((d.nz + 3) / 4);
+        k_conv_ym<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        return;
+    }
     if (MGCT_CONV_LDS) {
         constexpr int YB = 4 * kConvLdsRows;
         const unsigned nb = (unsigned)((long)(d.nx / 32) * ((d.ny + YB - 1) / YB) * d.nz);
@@ -573,6 +855,7 @@ static unsigned blocks(long n, int per = 256) { return (unsigned)((n + per - 1) 
 
 hipError_t cnn_pack(CnnState &S, hipStream_t s) {
     k_pack_weights<<<blocks(27 * 32 * 32), 256, 0, s>>>(S.master, S.p2f, S.p3f, S.p3d, S.p2d);
+    k_pack_weights4<<<blocks(2 * 3 * 2 * 32 * 16), 256, 0, s>>>(S.master, S.p4);
     return hipGetLastError();
 }
 
@@ -584,7 +867,10 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
     k_conv1_fwd<<<vb, 256, 0, s>>>(u, S.master, keep ? B.z1 : nullptr, B.h1, d);
     launch_conv<16, 0>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d, s);
     launch_conv<32, 0>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d, s);
-    k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
+    if (n >= MGCT_CONV_YM_MIN_VOX)
+        k_conv4_ym<<<(unsigned)(((nx + 29) / 30) * ((nz + 3) / 4)), 256, 0, s>>>(B.h3, S.p4, S.master, u, out, d);
+    else
+        k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
     return hipGetLastError();
 }
 

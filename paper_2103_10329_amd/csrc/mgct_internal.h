@@ -77,6 +77,7 @@ struct CnnState {
     float *master = nullptr;  // FP32 parameters [W1 b1 W2 b2 W3 b3 W4 b4]
     float *adam_m = nullptr, *adam_v = nullptr, *grads = nullptr;
     uint16_t *p2f = nullptr, *p3f = nullptr, *p3d = nullptr, *p2d = nullptr;  // packed BF16 operands
+    uint16_t *p4 = nullptr;  // layer 4's weights as BF16 pairs for the matrix-core kernel
     int adam_t = 0;
     bool ready = false;
 };

@@ -68,6 +68,21 @@ def test_forward_matches_oracle():
     assert e_plain <= 2e-2
 
 
+def test_forward_large_grid_marching_kernel():
+    """From 128^3 voxels up the two 32-output layers run on the persistent,
+    weight-stationary kernel that marches along y (and the activations use
+    the branch-free GELU).  A ragged grid above that size (z not a multiple of
+    the 4-z block, y not a multiple of 3) against the same storage model."""
+    ctx, params, u, _ = _setup(shape=(102, 136, 160), seed=7)
+    out = to_host(ctx.cnn_forward(to_dev(u)))
+    sref, _ = cnn_storage.forward(u, params)
+    u32 = cnn_storage.f32(u)
+    e = rel_l2(out - u32, sref - u32)
+    emax = _max_rel(out - u32, sref - u32)
+    say("cnn forward 160x136x102: rel L2 vs storage model %.3e (max %.3e)" % (e, emax))
+    assert e <= FWD_L2 and emax <= FWD_MAX
+
+
 def test_gradients_match_oracle():
     ctx, params, u, target = _setup()
     g, loss = ctx.cnn_gradients(to_dev(u), to_dev(target))
