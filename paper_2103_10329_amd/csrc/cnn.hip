@@ -536,13 +536,12 @@ __device__ __forceinline__ void conv_ym_mfma(const ConvSlice<CI> &S, const ConvW
         }
 }
 
-// output row yo of the wave's tile: bias, GELU, BF16 (and the FP32 pre-activation)
-__device__ __forceinline__ void conv_ym_store(floatx16 &acc, const float *__restrict__ bias, float *zout,
-                                              uint16_t *__restrict__ hout, const Dims &d, int x0, int yo, int z,
-                                              int m, int kh) {
+// output row yo of the wave's tile: bias bc (this lane's channel), GELU, BF16
+// (and the FP32 pre-activation)
+__device__ __forceinline__ void conv_ym_store(floatx16 &acc, float bc, float *zout, uint16_t *__restrict__ hout,
+                                              const Dims &d, int x0, int yo, int z, int m, int kh) {
     if (yo >= 0 && yo < d.ny) {
         const long v0 = ((long)z * d.ny + yo) * d.nx + x0;
-        const float bc = bias[m];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -561,16 +560,15 @@ __device__ __forceinline__ void conv_ym_store(floatx16 &acc, const float *__rest
 template <int CI>
 __device__ __forceinline__ void conv_ym_step(ConvSlice<CI> (&B)[3], const uint16_t *__restrict__ X,
                                              const ConvW<CI> &W, const Dims &d, int x0, int z, int yi, int m,
-                                             int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN,
-                                             const float *__restrict__ bias, float *zout,
-                                             uint16_t *__restrict__ hout) {
+                                             int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN, float bc,
+                                             float *zout, uint16_t *__restrict__ hout) {
     conv_ym_load<CI>(B[2], X, d, x0, z, yi, 2, m, kh);
     conv_ym_mfma<CI, 0>(B[0], W, aP, a0, aN);
     conv_ym_load<CI>(B[0], X, d, x0, z, yi + 1, 0, m, kh);
     conv_ym_mfma<CI, 1>(B[1], W, aP, a0, aN);
     conv_ym_load<CI>(B[1], X, d, x0, z, yi + 1, 1, m, kh);
     conv_ym_mfma<CI, 2>(B[2], W, aP, a0, aN);
-    conv_ym_store(aP, bias, zout, hout, d, x0, yi - 1, z, m, kh);
+    conv_ym_store(aP, bc, zout, hout, d, x0, yi - 1, z, m, kh);
 }
 
 template <int CI>
@@ -591,17 +589,148 @@ __global__ __launch_bounds__(256, 1) void k_conv_ym(const uint16_t *__restrict__
         if (z >= d.nz) continue;  // whole wave; no barrier in this kernel
         // input rows -1 .. ny (row yi completes output row yi - 1); the
         // three accumulators rotate, three rows per trip
+        const float bc = bias[m];
         floatx16 A0{}, A1{}, A2{};
         ConvSlice<CI> B[3];
         conv_ym_load<CI>(B[0], X, d, x0, z, -1, 0, m, kh);
         conv_ym_load<CI>(B[1], X, d, x0, z, -1, 1, m, kh);
         for (int yi = -1; yi <= d.ny; yi += 3) {
-            conv_ym_step<CI>(B, X, W, d, x0, z, yi, m, kh, A0, A1, A2, bias, zout, hout);
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi, m, kh, A0, A1, A2, bc, zout, hout);
             if (yi + 1 > d.ny) break;
-            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 1, m, kh, A1, A2, A0, bias, zout, hout);
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 1, m, kh, A1, A2, A0, bc, zout, hout);
             if (yi + 2 > d.ny) break;
-            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 2, m, kh, A2, A0, A1, bias, zout, hout);
+            conv_ym_step<CI>(B, X, W, d, x0, z, yi + 2, m, kh, A2, A0, A1, bc, zout, hout);
         }
+    }
+}
+
+// The same layers with the input rows staged in LDS by the data mover: a
+// block's 4 waves (4 consecutive z) share a ring of kConvRing input rows
+// (the 6 z rows z0 - 1 .. z0 + 4 times the 34 x of the tile and its two
+// neighbours, every channel), filled by global-to-LDS loads three rows ahead
+// of the row being worked on, so that the latency of memory is covered by
+// three rows of MFMAs instead of two dz slices.  Each wave issues the same
+// number of 16-byte transfers per row (positions past the row's data fill
+// the slot's padding from the zero array), waits for its own transfers of
+// the row it is about to read (the row's transfers were issued before the
+// later rows', and loads complete in order), then all waves meet at a
+// barrier.  The 16-byte chunks of a voxel are stored XOR-swizzled by x so
+// that a fragment read (16 lanes, consecutive x, one chunk each) touches 16
+// different groups of banks.  Accumulator of output row o: A[o mod 4].
+constexpr int kConvRing = 4;
+template <int CI> struct ConvLds {
+    static constexpr int C = CI / 8;           // 16-byte chunks per voxel
+    static constexpr int P = 6 * 34 * C;       // chunks of one staged row
+    static constexpr int L = (P + 255) / 256;  // transfers per wave per row
+    static constexpr int SLOT = L * 256;       // chunks per ring slot (padded)
+};
+template <int CI> __device__ __forceinline__ int conv_swz(int xi, int q) {
+    return CI == 32 ? (q ^ ((xi >> 2) & 3)) : (q ^ ((xi >> 3) & 1));
+}
+
+// wait until at most n vector-memory operations of this wave are outstanding
+template <int N> __device__ __forceinline__ void wait_vm() {
+    static_assert(N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// One 16-byte global-to-LDS transfer per lane: lane i's 16 bytes from src go
+// to LDS byte address lds + 16 i.  Written out (the builtin makes the
+// compiler wait for every transfer in flight before any LDS read, which
+// would undo the prefetch); the kernel orders it itself with wait_vm and a
+// barrier.  It has no register result.
+__device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds) : "memory", "m0");
+}
+
+template <int CI>
+__device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X, const Dims &d, int x0,
+                                             int z0, int yi, int w, int lane) {
+    using G = ConvLds<CI>;
+#pragma unroll
+    for (int i = 0; i < G::L; ++i) {
+        const int k = i * 4 + w, p = k * 64 + lane;
+        const int zi = p / (34 * G::C), xi = (p / G::C) % 34, q = conv_swz<CI>(xi, p % G::C);
+        const int zz = z0 - 1 + zi, xx = x0 - 1 + xi;
+        const bool ok = p < G::P && yi >= 0 && yi < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
+        const uint16_t *src = ok ? X + (((long)zz * d.ny + yi) * d.nx + xx) * CI + q * 8 : kConvZeros;
+        dma16(src, slot + (uint32_t)(k * 1024));
+    }
+}
+
+// the MFMAs of one staged row for the wave's z (slot row w + dz)
+template <int CI>
+__device__ __forceinline__ void conv_lds_mfma(const uint16_t (&slot)[ConvLds<CI>::SLOT * 8], const ConvW<CI> &W, int w,
+                                              int m, int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN) {
+    using G = ConvLds<CI>;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int xi = m + dx, base = ((w + dz) * 34 + xi) * G::C;
+#pragma unroll
+            for (int kc = 0; kc < CI / 16; ++kc) {
+                const int q = kc * 2 + kh;
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(slot + (base + conv_swz<CI>(xi, q)) * 8);
+                const int tb = dz * 9 + dx;
+                aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], aN, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 3][kc], a0, 0, 0, 0);
+                aP = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 6][kc], aP, 0, 0, 0);
+            }
+        }
+}
+
+template <int CI>
+__global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
+                                                     const float *__restrict__ bias, float *__restrict__ zout,
+                                                     uint16_t *__restrict__ hout, Dims d, int n_items) {
+    using G = ConvLds<CI>;
+    __shared__ __align__(16) uint16_t ring0[G::SLOT * 8], ring1[G::SLOT * 8], ring2[G::SLOT * 8],
+        ring3[G::SLOT * 8];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = lane & 31, kh = lane >> 5;
+    // the slots' LDS byte addresses (a __shared__ address is its LDS offset in the low 32 bits)
+    const uint32_t l0 = (uint32_t)(uintptr_t)ring0, l1 = (uint32_t)(uintptr_t)ring1,
+                   l2 = (uint32_t)(uintptr_t)ring2, l3 = (uint32_t)(uintptr_t)ring3;
+    ConvW<CI> W;
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc)
+            W.f[t][kc] = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + m) * CI + kc * 16 + kh * 8);
+    const float bc = bias[m];
+    wait_vm<0>();  // weights and bias in registers before the first transfer
+    const int nxt = d.nx / 32;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // block-uniform
+        const int x0 = (it % nxt) * 32, z0 = (it / nxt) * 4, z = z0 + w;
+        const bool live = z < d.nz;  // a wave past the grid still moves data and meets the barriers
+        floatx16 A0{}, A1{}, A2{}, A3{};
+        __syncthreads();  // the previous item's reads of the ring are done
+        conv_dma_row<CI>(l0, X, d, x0, z0, -1, w, lane);
+        conv_dma_row<CI>(l1, X, d, x0, z0, 0, w, lane);
+        conv_dma_row<CI>(l2, X, d, x0, z0, 1, w, lane);
+        // row yi from its slot; the row three ahead into the slot freed by row yi - 1
+#define MGCT_CONV_STEP(RS, RN, YI, AP, A0_, AN, AF)                                                              \
+    {                                                                                                            \
+        wait_vm<2 * G::L>();                                                                                     \
+        __syncthreads();                                                                                         \
+        conv_dma_row<CI>(RN, X, d, x0, z0, (YI) + 3, w, lane);                                                   \
+        if (live) {                                                                                              \
+            conv_lds_mfma<CI>(RS, W, w, m, kh, AP, A0_, AN);                                                     \
+            conv_ym_store(AP, bc, zout, hout, d, x0, (YI) - 1, z, m, kh);                                        \
+        }                                                                                                        \
+    }
+        for (int yi = -1; yi <= d.ny; yi += 4) {
+            MGCT_CONV_STEP(ring0, l3, yi, A2, A3, A0, A1)
+            if (yi + 1 > d.ny) break;
+            MGCT_CONV_STEP(ring1, l0, yi + 1, A3, A0, A1, A2)
+            if (yi + 2 > d.ny) break;
+            MGCT_CONV_STEP(ring2, l1, yi + 2, A0, A1, A2, A3)
+            if (yi + 3 > d.ny) break;
+            MGCT_CONV_STEP(ring3, l2, yi + 3, A1, A2, A3, A0)
+        }
+#undef MGCT_CONV_STEP
+        wait_vm<0>();  // no transfer into the ring stays in flight past the item
     }
 }
 
@@ -701,6 +830,9 @@ __global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h
 #define MGCT_CONV_LDS 1
 #endif
 // launch of either convolution kernel
+#ifndef MGCT_CONV_DMA
+#define MGCT_CONV_DMA 1  // large-grid forward: input rows staged in LDS by global-to-LDS loads
+#endif
 #ifndef MGCT_CONV_YM_MIN_VOX
 #define MGCT_CONV_YM_MIN_VOX (128L * 128 * 128)  // forward on the marching kernel from this many voxels
 #endif
@@ -717,7 +849,10 @@ static void launch_conv(const uint16_t *X, const uint16_t *P, const float *bias,
                        : 256;
         }
         const int n_items = (d.nx / 32) * ((d.nz + 3) / 4);
-        k_conv_ym<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        if (MGCT_CONV_DMA)
+            k_conv_lds<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        else
+            k_conv_ym<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
         return;
     }
     if (MGCT_CONV_LDS) {
