@@ -34,23 +34,27 @@ __device__ __forceinline__ uint16_t to_bf(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-// GELU x Phi(x) for the forward activations, without branches: Phi(x) =
-// 1 - erfc(y) / 2 for x >= 0 and erfc(y) / 2 below, y = |x| / sqrt(2), with
-// erfc(y) = (a1 t + ... + a5 t^5) exp(-y^2), t = 1 / (1 + p y), the rational
-// approximation of Abramowitz & Stegun, Handbook of Mathematical Functions,
-// 7.1.26 (|error| <= 1.5e-7 on erf).  The result is stored in BF16 (relative
-// step 2^-8), so the difference to the exact erf shows only as a rare
-// rounding flip; the backward pass keeps the exact derivative.
+// FP32 -> BF16 bits, round to nearest even in one conversion instruction
+// (same as to_bf for every finite value)
+__device__ __forceinline__ uint16_t to_bf_cvt(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// GELU x Phi(x) for the forward activations, without branches, written as
+// max(x, 0) - |x| erfc(y) / 2 with y = |x| / sqrt(2) (equal to x Phi(x) for
+// either sign), erfc(y) = (a1 t + ... + a5 t^5) exp(-y^2), t = 1 / (1 + p y):
+// the rational approximation of Abramowitz & Stegun, Handbook of
+// Mathematical Functions, 7.1.26 (|error| <= 1.5e-7 on erf); exp(-x^2 / 2) as
+// exp2(-x^2 / (2 ln 2)).  The result is stored in BF16 (relative step 2^-8),
+// so the difference to the exact erf shows only as a rare rounding flip; the
+// backward pass keeps the exact derivative.  Finite inputs.
 __device__ __forceinline__ float gelu(float x) {
-    const float y = fabsf(x) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, y, 1.f));
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, ax, 1.f));
     float q = fmaf(1.061405429f, t, -1.453152027f);
     q = fmaf(q, t, 1.421413741f);
     q = fmaf(q, t, -0.284496736f);
     q = fmaf(q, t, 0.254829592f);
-    q *= t * __expf(-y * y);  // erfc(y)
-    const float phi = x >= 0.f ? fmaf(-0.5f, q, 1.f) : 0.5f * q;
-    return x * phi;
+    q *= t * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x);  // erfc(y)
+    return fmaf(-0.5f * ax, q, fmaxf(x, 0.f));
 }
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
@@ -643,18 +647,35 @@ __device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
     asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds) : "memory", "m0");
 }
 
+// This lane's source element offsets for the transfers of one staged row at
+// row 0 of the item's tile (the row yi adds yi nx CI), -1 where the position
+// is padding or its voxel lies outside the volume in x or z.
+template <int CI> struct ConvDmaOff {
+    long off[ConvLds<CI>::L];
+};
 template <int CI>
-__device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X, const Dims &d, int x0,
-                                             int z0, int yi, int w, int lane) {
+__device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI> &O, const Dims &d, int x0, int z0, int w, int lane) {
     using G = ConvLds<CI>;
 #pragma unroll
     for (int i = 0; i < G::L; ++i) {
         const int k = i * 4 + w, p = k * 64 + lane;
         const int zi = p / (34 * G::C), xi = (p / G::C) % 34, q = conv_swz<CI>(xi, p % G::C);
         const int zz = z0 - 1 + zi, xx = x0 - 1 + xi;
-        const bool ok = p < G::P && yi >= 0 && yi < d.ny && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
-        const uint16_t *src = ok ? X + (((long)zz * d.ny + yi) * d.nx + xx) * CI + q * 8 : kConvZeros;
-        dma16(src, slot + (uint32_t)(k * 1024));
+        const bool ok = p < G::P && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
+        O.off[i] = ok ? ((long)zz * d.ny * d.nx + xx) * CI + q * 8 : -1;
+    }
+}
+
+template <int CI>
+__device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X, const ConvDmaOff<CI> &O,
+                                             const Dims &d, int yi, int w) {
+    using G = ConvLds<CI>;
+    const bool yok = yi >= 0 && yi < d.ny;  // wave-uniform
+    const long yoff = (long)yi * d.nx * CI;
+#pragma unroll
+    for (int i = 0; i < G::L; ++i) {
+        const uint16_t *src = yok && O.off[i] >= 0 ? X + (O.off[i] + yoff) : kConvZeros;
+        dma16(src, slot + (uint32_t)((i * 4 + w) * 1024));
     }
 }
 
@@ -680,7 +701,70 @@ __device__ __forceinline__ void conv_lds_mfma(const uint16_t (&slot)[ConvLds<CI>
         }
 }
 
-template <int CI>
+// The MFMAs of one staged row for the wave's z (slot row w + dz) with the
+// epilogue of the row completed one step earlier (accumulator aF, output
+// row yo) interleaved between them: its bias, GELU, BF16 conversion and
+// stores issue while the matrix pipe works on this row.  aF is cleared after
+// (also without STORE: the rows -1 and -2 above the grid collect products of
+// real input rows through their dy taps).
+template <int CI, bool ZOUT, bool STORE>
+__device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds<CI>::SLOT * 8], const ConvW<CI> &W,
+                                                  int w, int m, int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN,
+                                                  floatx16 &aF, float bc, float *__restrict__ zout,
+                                                  uint16_t *__restrict__ hout, const Dims &d, int x0, int yo,
+                                                  int z) {
+    using G = ConvLds<CI>;
+    const long v0 = ((long)z * d.ny + yo) * d.nx + x0;
+#pragma unroll
+    for (int g = 0; g < 9; ++g) {
+        const int dz = g / 3, dx = g % 3;
+        const int xi = m + dx, base = ((w + dz) * 34 + xi) * G::C;
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc) {
+            const int q = kc * 2 + kh;
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(slot + (base + conv_swz<CI>(xi, q)) * 8);
+            const int tb = dz * 9 + dx;
+            aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], aN, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 3][kc], a0, 0, 0, 0);
+            aP = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 6][kc], aP, 0, 0, 0);
+        }
+        if (STORE) {
+#pragma unroll
+            for (int r = g * 16 / 9; r < (g + 1) * 16 / 9; ++r) {
+                const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                const float zv = aF[r] + bc;
+                if (ZOUT) zout[v * 32 + m] = zv;
+                hout[v * 32 + m] = to_bf_cvt(gelu(zv));
+            }
+        }
+    }
+    aF = floatx16{};  // also when not stored: rows above the grid collect real products
+    if (STORE) {
+        // one MFMA, then up to seven vector instructions, in turn: the vector
+        // work runs in the shadow of the matrix instruction before it
+#pragma unroll
+        for (int i = 0; i < 27 * (CI / 16); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // VALU
+        }
+    }
+}
+
+template <bool ZOUT>
+__device__ __forceinline__ void conv_lds_flush(const floatx16 &acc, float bc, float *__restrict__ zout,
+                                               uint16_t *__restrict__ hout, const Dims &d, int x0, int yo, int z,
+                                               int m, int kh) {
+    const long v0 = ((long)z * d.ny + yo) * d.nx + x0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const float zv = acc[r] + bc;
+        if (ZOUT) zout[v * 32 + m] = zv;
+        hout[v * 32 + m] = to_bf_cvt(gelu(zv));
+    }
+}
+
+template <int CI, bool ZOUT>
 __global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
                                                      const float *__restrict__ bias, float *__restrict__ zout,
                                                      uint16_t *__restrict__ hout, Dims d, int n_items) {
@@ -704,32 +788,50 @@ __global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict_
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // block-uniform
         const int x0 = (it % nxt) * 32, z0 = (it / nxt) * 4, z = z0 + w;
         const bool live = z < d.nz;  // a wave past the grid still moves data and meets the barriers
+        // accumulator of output row o: A[o mod 4]; ring slot of input row r: (r + 1) mod 4
         floatx16 A0{}, A1{}, A2{}, A3{};
+        ConvDmaOff<CI> O;
+        conv_dma_prep<CI>(O, d, x0, z0, w, lane);
         __syncthreads();  // the previous item's reads of the ring are done
-        conv_dma_row<CI>(l0, X, d, x0, z0, -1, w, lane);
-        conv_dma_row<CI>(l1, X, d, x0, z0, 0, w, lane);
-        conv_dma_row<CI>(l2, X, d, x0, z0, 1, w, lane);
-        // row yi from its slot; the row three ahead into the slot freed by row yi - 1
-#define MGCT_CONV_STEP(RS, RN, YI, AP, A0_, AN, AF)                                                              \
+        conv_dma_row<CI>(l0, X, O, d, -1, w);
+        conv_dma_row<CI>(l1, X, O, d, 0, w);
+        conv_dma_row<CI>(l2, X, O, d, 1, w);
+        // step YI: its row from slot RS, the row three ahead into slot RN,
+        // MFMAs into rows YI - 1 (AP), YI (A0_), YI + 1 (AN), the epilogue of
+        // row YI - 2 (AF) interleaved
+#define MGCT_CONV_STEP(RS, RN, YI, AP, A0_, AN, AF, STORE)                                                       \
     {                                                                                                            \
         wait_vm<2 * G::L>();                                                                                     \
         __syncthreads();                                                                                         \
-        conv_dma_row<CI>(RN, X, d, x0, z0, (YI) + 3, w, lane);                                                   \
-        if (live) {                                                                                              \
-            conv_lds_mfma<CI>(RS, W, w, m, kh, AP, A0_, AN);                                                     \
-            conv_ym_store(AP, bc, zout, hout, d, x0, (YI) - 1, z, m, kh);                                        \
-        }                                                                                                        \
+        conv_dma_row<CI>(RN, X, O, d, (YI) + 3, w);                                                              \
+        if (live)                                                                                                \
+            conv_lds_mfma_epi<CI, ZOUT, STORE>(RS, W, w, m, kh, AP, A0_, AN, AF, bc, zout, hout, d, x0, (YI) - 2, \
+                                                z);                                                              \
     }
-        for (int yi = -1; yi <= d.ny; yi += 4) {
-            MGCT_CONV_STEP(ring0, l3, yi, A2, A3, A0, A1)
+        MGCT_CONV_STEP(ring0, l3, -1, A2, A3, A0, A1, false)
+        if (0 <= d.ny) MGCT_CONV_STEP(ring1, l0, 0, A3, A0, A1, A2, false)
+        if (1 <= d.ny) MGCT_CONV_STEP(ring2, l1, 1, A0, A1, A2, A3, false)
+        if (2 <= d.ny) MGCT_CONV_STEP(ring3, l2, 2, A1, A2, A3, A0, true)
+        for (int yi = 3; yi <= d.ny; yi += 4) {
+            MGCT_CONV_STEP(ring0, l3, yi, A2, A3, A0, A1, true)
             if (yi + 1 > d.ny) break;
-            MGCT_CONV_STEP(ring1, l0, yi + 1, A3, A0, A1, A2)
+            MGCT_CONV_STEP(ring1, l0, yi + 1, A3, A0, A1, A2, true)
             if (yi + 2 > d.ny) break;
-            MGCT_CONV_STEP(ring2, l1, yi + 2, A0, A1, A2, A3)
+            MGCT_CONV_STEP(ring2, l1, yi + 2, A0, A1, A2, A3, true)
             if (yi + 3 > d.ny) break;
-            MGCT_CONV_STEP(ring3, l2, yi + 3, A1, A2, A3, A0)
+            MGCT_CONV_STEP(ring3, l2, yi + 3, A1, A2, A3, A0, true)
         }
 #undef MGCT_CONV_STEP
+        // the last row, ny - 1, completed in the last step
+        if (live) {
+            const int o = d.ny - 1;
+            switch (o & 3) {
+                case 0: conv_lds_flush<ZOUT>(A0, bc, zout, hout, d, x0, o, z, m, kh); break;
+                case 1: conv_lds_flush<ZOUT>(A1, bc, zout, hout, d, x0, o, z, m, kh); break;
+                case 2: conv_lds_flush<ZOUT>(A2, bc, zout, hout, d, x0, o, z, m, kh); break;
+                default: conv_lds_flush<ZOUT>(A3, bc, zout, hout, d, x0, o, z, m, kh); break;
+            }
+        }
         wait_vm<0>();  // no transfer into the ring stays in flight past the item
     }
 }
@@ -849,8 +951,11 @@ static void launch_conv(const uint16_t *X, const uint16_t *P, const float *bias,
                        : 256;
         }
         const int n_items = (d.nx / 32) * ((d.nz + 3) / 4);
-        if (MGCT_CONV_DMA)
-            k_conv_lds<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        const unsigned nb = (unsigned)std::min(n_items, n_cu);
+        if (MGCT_CONV_DMA && zout)
+            k_conv_lds<CI, true><<<nb, 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        else if (MGCT_CONV_DMA)
+            k_conv_lds<CI, false><<<nb, 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
         else
             k_conv_ym<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
         return;
