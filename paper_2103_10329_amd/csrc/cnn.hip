@@ -38,23 +38,36 @@ __device__ __forceinline__ uint16_t to_bf(float f) {
 // (same as to_bf for every finite value)
 __device__ __forceinline__ uint16_t to_bf_cvt(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
+// Two FP32 values -> two BF16 (round to nearest even) packed low, high, in
+// one conversion instruction.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){lo, hi}, bf16x2));
+}
+
 // GELU x Phi(x) for the forward activations, without branches, written as
 // max(x, 0) - |x| erfc(y) / 2 with y = |x| / sqrt(2) (equal to x Phi(x) for
 // either sign), erfc(y) = (a1 t + ... + a5 t^5) exp(-y^2), t = 1 / (1 + p y):
 // the rational approximation of Abramowitz & Stegun, Handbook of
-// Mathematical Functions, 7.1.26 (|error| <= 1.5e-7 on erf); exp(-x^2 / 2) as
-// exp2(-x^2 / (2 ln 2)).  The result is stored in BF16 (relative step 2^-8),
-// so the difference to the exact erf shows only as a rare rounding flip; the
-// backward pass keeps the exact derivative.  Finite inputs.
+// Mathematical Functions, 7.1.26 (|error| <= 1.5e-7 on erf), its
+// coefficients halved (exactly) to give erfc(y) / 2; exp(-x^2 / 2) as
+// exp2(-x^2 / (2 ln 2)); max(x, 0) as an integer maximum of the bit pattern
+// (a float with the sign bit set is a negative integer).  The result is
+// stored in BF16 (relative step 2^-8), so the difference to the exact erf
+// shows only as a rare rounding flip (the coarser 7.1.28, one reciprocal and
+// no exponential, measurably raised the flips in the negative tail, where
+// GELU is small and its relative error large); the backward pass keeps the
+// exact derivative.  Finite inputs.
 __device__ __forceinline__ float gelu(float x) {
     const float ax = fabsf(x);
     const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, ax, 1.f));
-    float q = fmaf(1.061405429f, t, -1.453152027f);
-    q = fmaf(q, t, 1.421413741f);
-    q = fmaf(q, t, -0.284496736f);
-    q = fmaf(q, t, 0.254829592f);
-    q *= t * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x);  // erfc(y)
-    return fmaf(-0.5f * ax, q, fmaxf(x, 0.f));
+    float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    q = fmaf(q, t, 0.5f * 1.421413741f);
+    q = fmaf(q, t, 0.5f * -0.284496736f);
+    q = fmaf(q, t, 0.5f * 0.254829592f);
+    q *= t * __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x);  // erfc(y) / 2
+    return fmaf(-ax, q, __int_as_float(max(__float_as_int(x), 0)));
 }
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
@@ -618,24 +631,71 @@ __global__ __launch_bounds__(256, 1) void k_conv_ym(const uint16_t *__restrict__
 // the slot's padding from the zero array), waits for its own transfers of
 // the row it is about to read (the row's transfers were issued before the
 // later rows', and loads complete in order), then all waves meet at a
-// barrier.  The 16-byte chunks of a voxel are stored XOR-swizzled by x so
-// that a fragment read (16 lanes, consecutive x, one chunk each) touches 16
+// barrier.  The 16-byte chunks of a voxel are laid out (conv_slot) so that
+// a fragment read (16 lanes, consecutive x, one chunk each) touches 16
 // different groups of banks.  Accumulator of output row o: A[o mod 4].
 constexpr int kConvRing = 4;
-template <int CI> struct ConvLds {
-    static constexpr int C = CI / 8;           // 16-byte chunks per voxel
-    static constexpr int P = 6 * 34 * C;       // chunks of one staged row
-    static constexpr int L = (P + 255) / 256;  // transfers per wave per row
-    static constexpr int SLOT = L * 256;       // chunks per ring slot (padded)
+#ifndef MGCT_CONV16_BLOCKS
+#define MGCT_CONV16_BLOCKS 2
+#endif
+#ifndef MGCT_CONV32_PAD
+#define MGCT_CONV32_PAD 0
+#endif
+template <int CI, int NW = 4> struct ConvLds {
+    static constexpr int C = CI / 8;                                  // 16-byte chunks per voxel
+    static constexpr int CP = CI == 32 && MGCT_CONV32_PAD ? C + 1 : C;  // chunk slots per voxel in LDS
+    static constexpr int P = 6 * 34 * CP;                             // chunk slots of one staged row
+    static constexpr int L = (P + 64 * NW - 1) / (64 * NW);           // transfers per wave per row (NW waves)
+    static constexpr int SLOT = L * 64 * NW;                          // chunks per ring slot (padded)
 };
-template <int CI> __device__ __forceinline__ int conv_swz(int xi, int q) {
-    return CI == 32 ? (q ^ ((xi >> 2) & 3)) : (q ^ ((xi >> 3) & 1));
+// LDS chunk slot of channel chunk q of voxel xi in a staged z row: the
+// chunks of a voxel are permuted by an XOR with bits of xi (its own
+// inverse), chosen with the LDS bank-conflict counter so that the fragment
+// reads (every dx, row and voxel half) run at the conflict-free rate: for
+// the 32-voxel fragments (lane = voxel + 32 chunk-of-pair) bits 2-3 of xi
+// with 32 channels, bit 3 with 16; for the 16-voxel fragments of the
+// eight-wave kernel (lane = voxel + 16 chunk) bits 1-2 (bits 2-3 there
+// double the read time).
+template <int CI, int NW = 4> __device__ __forceinline__ int conv_perm(int xi, int q) {
+    if (CI == 16) return q ^ ((xi >> 3) & 1);
+    if (NW == 8) return q ^ ((xi >> 1) & 3);
+    return MGCT_CONV32_PAD ? q : q ^ ((xi >> 2) & 3);
+}
+template <int CI, int NW = 4> __device__ __forceinline__ int conv_slot(int xi, int q) {
+    return xi * ConvLds<CI, NW>::CP + conv_perm<CI, NW>(xi, q);
 }
 
 // wait until at most n vector-memory operations of this wave are outstanding
 template <int N> __device__ __forceinline__ void wait_vm() {
     static_assert(N < 64, "vmcnt field");
     __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+#ifndef MGCT_CONV_WAIT_STORES
+#define MGCT_CONV_WAIT_STORES 1
+#endif
+constexpr int vm_cap(int n) { return n < 63 ? n : 63; }
+// Wait before input row yi of the ring is read.  Its L transfers per wave
+// were issued three steps earlier (or before the first step); issued after
+// them are the two later rows' transfers and the output stores of the three
+// steps in between (S per step; a step stores from yi = 2 on, and only in a
+// wave whose z lies in the grid).  Vector-memory operations of a wave are
+// counted off in issue order, so leaving that many outstanding waits for the
+// row's own transfers and not for the stores behind them.
+template <int L, int S> __device__ __forceinline__ void conv_row_wait(int yi, bool live) {
+#if MGCT_CONV_WAIT_STORES
+    const int ns = live ? (yi < 2 ? 0 : yi > 5 ? 3 : yi - 2) : 0;  // wave-uniform
+    if (ns == 3)
+        wait_vm<vm_cap(2 * L + 3 * S)>();
+    else if (ns == 2)
+        wait_vm<vm_cap(2 * L + 2 * S)>();
+    else if (ns == 1)
+        wait_vm<vm_cap(2 * L + S)>();
+    else
+        wait_vm<2 * L>();
+#else
+    wait_vm<2 * L>();
+#endif
 }
 
 // One 16-byte global-to-LDS transfer per lane: lane i's 16 bytes from src go
@@ -650,63 +710,43 @@ __device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
 // This lane's source element offsets for the transfers of one staged row at
 // row 0 of the item's tile (the row yi adds yi nx CI), -1 where the position
 // is padding or its voxel lies outside the volume in x or z.
-template <int CI> struct ConvDmaOff {
-    long off[ConvLds<CI>::L];
+template <int CI, int NW = 4> struct ConvDmaOff {
+    long off[ConvLds<CI, NW>::L];
 };
-template <int CI>
-__device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI> &O, const Dims &d, int x0, int z0, int w, int lane) {
-    using G = ConvLds<CI>;
+template <int CI, int NW = 4>
+__device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI, NW> &O, const Dims &d, int x0, int z0, int w,
+                                              int lane) {
+    using G = ConvLds<CI, NW>;
 #pragma unroll
     for (int i = 0; i < G::L; ++i) {
-        const int k = i * 4 + w, p = k * 64 + lane;
-        const int zi = p / (34 * G::C), xi = (p / G::C) % 34, q = conv_swz<CI>(xi, p % G::C);
+        const int k = i * NW + w, p = k * 64 + lane;
+        const int zi = p / (34 * G::CP), xi = (p / G::CP) % 34, qs = p % G::CP;
+        const int q = conv_perm<CI, NW>(xi, qs);  // the chunk that slot holds
         const int zz = z0 - 1 + zi, xx = x0 - 1 + xi;
-        const bool ok = p < G::P && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
+        const bool ok = p < G::P && q < G::C && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
         O.off[i] = ok ? ((long)zz * d.ny * d.nx + xx) * CI + q * 8 : -1;
     }
 }
 
-template <int CI>
-__device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X, const ConvDmaOff<CI> &O,
-                                             const Dims &d, int yi, int w) {
-    using G = ConvLds<CI>;
+template <int CI, int NW = 4>
+__device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X,
+                                             const ConvDmaOff<CI, NW> &O, const Dims &d, int yi, int w) {
+    using G = ConvLds<CI, NW>;
     const bool yok = yi >= 0 && yi < d.ny;  // wave-uniform
     const long yoff = (long)yi * d.nx * CI;
 #pragma unroll
     for (int i = 0; i < G::L; ++i) {
         const uint16_t *src = yok && O.off[i] >= 0 ? X + (O.off[i] + yoff) : kConvZeros;
-        dma16(src, slot + (uint32_t)((i * 4 + w) * 1024));
+        dma16(src, slot + (uint32_t)((i * NW + w) * 1024));
     }
-}
-
-// the MFMAs of one staged row for the wave's z (slot row w + dz)
-template <int CI>
-__device__ __forceinline__ void conv_lds_mfma(const uint16_t (&slot)[ConvLds<CI>::SLOT * 8], const ConvW<CI> &W, int w,
-                                              int m, int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN) {
-    using G = ConvLds<CI>;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            const int xi = m + dx, base = ((w + dz) * 34 + xi) * G::C;
-#pragma unroll
-            for (int kc = 0; kc < CI / 16; ++kc) {
-                const int q = kc * 2 + kh;
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(slot + (base + conv_swz<CI>(xi, q)) * 8);
-                const int tb = dz * 9 + dx;
-                aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], aN, 0, 0, 0);
-                a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 3][kc], a0, 0, 0, 0);
-                aP = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 6][kc], aP, 0, 0, 0);
-            }
-        }
 }
 
 // The MFMAs of one staged row for the wave's z (slot row w + dz) with the
 // epilogue of the row completed one step earlier (accumulator aF, output
-// row yo) interleaved between them: its bias, GELU, BF16 conversion and
-// stores issue while the matrix pipe works on this row.  aF is cleared after
-// (also without STORE: the rows -1 and -2 above the grid collect products of
-// real input rows through their dy taps).
+// row yo) interleaved between them: its GELU, BF16 conversion and stores
+// issue while the matrix pipe works on this row.  The accumulator of row
+// YI + 1 (the one stored a step earlier) is not cleared: its first MFMA
+// takes the bias (the lane's output channel m) as the addend instead.
 template <int CI, bool ZOUT, bool STORE>
 __device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds<CI>::SLOT * 8], const ConvW<CI> &W,
                                                   int w, int m, int kh, floatx16 &aP, floatx16 &a0, floatx16 &aN,
@@ -715,16 +755,28 @@ __device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds
                                                   int z) {
     using G = ConvLds<CI>;
     const long v0 = ((long)z * d.ny + yo) * d.nx + x0;
+    // fragments of tap group g = (dz, dx), the next group's read while this one's MFMAs run
+    auto frag = [&](int g, int kc) {
+        const int dz = g / 3, dx = g % 3;
+        return *reinterpret_cast<const bf16x8 *>(slot + (((w + dz) * 34) * G::CP + conv_slot<CI>(m + dx, kc * 2 + kh)) * 8);
+    };
+    bf16x8 fr[2][CI / 16];
+#pragma unroll
+    for (int kc = 0; kc < CI / 16; ++kc) fr[0][kc] = frag(0, kc);
 #pragma unroll
     for (int g = 0; g < 9; ++g) {
         const int dz = g / 3, dx = g % 3;
-        const int xi = m + dx, base = ((w + dz) * 34 + xi) * G::C;
+        if (g < 8) {
+#pragma unroll
+            for (int kc = 0; kc < CI / 16; ++kc) fr[(g + 1) & 1][kc] = frag(g + 1, kc);
+        }
 #pragma unroll
         for (int kc = 0; kc < CI / 16; ++kc) {
-            const int q = kc * 2 + kh;
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(slot + (base + conv_swz<CI>(xi, q)) * 8);
+            const bf16x8 a = fr[g & 1][kc];
             const int tb = dz * 9 + dx;
-            aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], aN, 0, 0, 0);
+            // row YI + 1 starts here: its first product adds to the bias
+            aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], g == 0 && kc == 0 ? (floatx16)bc : aN, 0,
+                                                         0, 0);
             a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 3][kc], a0, 0, 0, 0);
             aP = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb + 6][kc], aP, 0, 0, 0);
         }
@@ -732,13 +784,12 @@ __device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds
 #pragma unroll
             for (int r = g * 16 / 9; r < (g + 1) * 16 / 9; ++r) {
                 const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                const float zv = aF[r] + bc;
+                const float zv = aF[r];
                 if (ZOUT) zout[v * 32 + m] = zv;
                 hout[v * 32 + m] = to_bf_cvt(gelu(zv));
             }
         }
     }
-    aF = floatx16{};  // also when not stored: rows above the grid collect real products
     if (STORE) {
         // one MFMA, then up to seven vector instructions, in turn: the vector
         // work runs in the shadow of the matrix instruction before it
@@ -758,14 +809,18 @@ __device__ __forceinline__ void conv_lds_flush(const floatx16 &acc, float bc, fl
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const long v = v0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const float zv = acc[r] + bc;
+        const float zv = acc[r];
         if (ZOUT) zout[v * 32 + m] = zv;
         hout[v * 32 + m] = to_bf_cvt(gelu(zv));
     }
 }
 
+// The 16-channel variant without the pre-activation output fits two blocks
+// per CU (registers and LDS); the others hold more and run one.
+template <int CI, bool ZOUT> constexpr int conv_lds_blocks() { return CI == 16 && !ZOUT ? MGCT_CONV16_BLOCKS : 1; }
+
 template <int CI, bool ZOUT>
-__global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
+__global__ __launch_bounds__(256, (conv_lds_blocks<CI, ZOUT>())) void k_conv_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
                                                      const float *__restrict__ bias, float *__restrict__ zout,
                                                      uint16_t *__restrict__ hout, Dims d, int n_items) {
     using G = ConvLds<CI>;
@@ -801,7 +856,7 @@ __global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict_
         // row YI - 2 (AF) interleaved
 #define MGCT_CONV_STEP(RS, RN, YI, AP, A0_, AN, AF, STORE)                                                       \
     {                                                                                                            \
-        wait_vm<2 * G::L>();                                                                                     \
+        conv_row_wait<G::L, (ZOUT ? 32 : 16)>((YI), live);                                                      \
         __syncthreads();                                                                                         \
         conv_dma_row<CI>(RN, X, O, d, (YI) + 3, w);                                                              \
         if (live)                                                                                                \
@@ -831,6 +886,148 @@ __global__ __launch_bounds__(256, 1) void k_conv_lds(const uint16_t *__restrict_
                 case 2: conv_lds_flush<ZOUT>(A2, bc, zout, hout, d, x0, o, z, m, kh); break;
                 default: conv_lds_flush<ZOUT>(A3, bc, zout, hout, d, x0, o, z, m, kh); break;
             }
+        }
+        wait_vm<0>();  // no transfer into the ring stays in flight past the item
+    }
+}
+
+// Layer 3 (32 -> 32 channels) on large grids with eight waves per block.
+// The same ring of staged input rows as k_conv_lds, but waves w and w + 4
+// take the same z row (w mod 4), the first the output channels 0..15 and the
+// second 16..31: each holds half the weights, so two waves fit on every SIMD
+// and one issues while the other waits.  The products are 16x16x32 MFMAs,
+// D[c][x] = sum over the 32 input channels of W[c][ci] X[ci][x] for the
+// wave's 16 channels and 16 voxels of one half (hx) of the 32-voxel tile:
+// lane (n, kg) = (lane mod 16, lane / 16) holds row n of a weight fragment
+// (channel c0 + n, inputs 8 kg .. 8 kg + 7), column n of an input fragment
+// (voxel hx 16 + n, the same inputs, chunk kg of the voxel in LDS), and of
+// the result the channels c0 + 4 kg .. c0 + 4 kg + 3 of voxel hx 16 + n,
+// which leave as one 8-byte store.  Accumulators of output row o: A[o mod 4],
+// one 4-vector per half.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kHwWaves = 8;
+using ConvHwLds = ConvLds<32, kHwWaves>;
+
+// The accumulator already holds the bias (the row's first MFMA starts from it).
+template <bool ZOUT>
+__device__ __forceinline__ void conv_hw_store(const floatx4 &zv, float *__restrict__ zout, uint16_t *__restrict__ hout,
+                                              long e) {
+    if (ZOUT) *reinterpret_cast<floatx4 *>(zout + e) = zv;
+    *reinterpret_cast<uint2 *>(hout + e) =
+        make_uint2(pack_bf16x2(gelu(zv[0]), gelu(zv[1])), pack_bf16x2(gelu(zv[2]), gelu(zv[3])));
+}
+
+// The MFMAs of one staged row for the wave's z (slot row wz + dz) into the
+// rows YI - 1 (aP), YI (a0) and YI + 1 (aN, which starts here from the
+// bias), with the epilogue of row yo = YI - 2 (aF) interleaved.
+template <bool ZOUT, bool STORE>
+__device__ __forceinline__ void conv_hw_mfma_epi(const uint16_t (&slot)[ConvHwLds::SLOT * 8], const bf16x8 (&W)[27],
+                                                 int wz, int n, int kg, floatx4 (&aP)[2], floatx4 (&a0)[2],
+                                                 floatx4 (&aN)[2], const floatx4 (&aF)[2], const floatx4 &bc,
+                                                 float *__restrict__ zout, uint16_t *__restrict__ hout,
+                                                 const Dims &d, int x0, int yo, int z, int c0) {
+    auto frag = [&](int g, int hx) {
+        const int dz = g / 3, dx = g % 3, xi = hx * 16 + n + dx;
+        return *reinterpret_cast<const bf16x8 *>(slot + ((wz + dz) * 34 * 4 + conv_slot<32, kHwWaves>(xi, kg)) * 8);
+    };
+    const long e0 = (((long)z * d.ny + yo) * d.nx + x0 + n) * 32 + c0 + 4 * kg;
+    // fragments two tap groups ahead of the MFMAs that use them
+    bf16x8 fr[3][2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        fr[g][0] = frag(g, 0);
+        fr[g][1] = frag(g, 1);
+    }
+#pragma unroll
+    for (int g = 0; g < 9; ++g) {
+        const int dz = g / 3, dx = g % 3, tb = dz * 9 + dx;
+        if (g < 7) {
+            fr[(g + 2) % 3][0] = frag(g + 2, 0);
+            fr[(g + 2) % 3][1] = frag(g + 2, 1);
+        }
+#pragma unroll
+        for (int hx = 0; hx < 2; ++hx) {
+            const bf16x8 b = fr[g % 3][hx];
+            aN[hx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[tb], b, g == 0 ? bc : aN[hx], 0, 0, 0);
+            a0[hx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[tb + 3], b, a0[hx], 0, 0, 0);
+            aP[hx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[tb + 6], b, aP[hx], 0, 0, 0);
+        }
+        if (STORE && (g == 2 || g == 6)) conv_hw_store<ZOUT>(aF[g / 4], zout, hout, e0 + (g / 4) * 16 * 32);
+    }
+    // order: the first two groups' fragment reads; then per group the reads
+    // for two groups ahead and its six MFMAs, each followed by up to three
+    // vector instructions of the epilogue
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
+#pragma unroll
+    for (int g = 0; g < 9; ++g) {
+        if (g < 7) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // MFMA
+            if (STORE) __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+        }
+    }
+}
+
+template <bool ZOUT>
+__global__ __launch_bounds__(512, 1) void k_conv32_hw(const uint16_t *__restrict__ X, const uint16_t *__restrict__ P,
+                                                      const float *__restrict__ bias, float *__restrict__ zout,
+                                                      uint16_t *__restrict__ hout, Dims d, int n_items) {
+    using G = ConvHwLds;
+    __shared__ __align__(16) uint16_t ring0[G::SLOT * 8], ring1[G::SLOT * 8], ring2[G::SLOT * 8],
+        ring3[G::SLOT * 8];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wz = w & 3, c0 = (w >> 2) * 16, n = lane & 15, kg = lane >> 4;
+    const uint32_t l0 = (uint32_t)(uintptr_t)ring0, l1 = (uint32_t)(uintptr_t)ring1,
+                   l2 = (uint32_t)(uintptr_t)ring2, l3 = (uint32_t)(uintptr_t)ring3;
+    bf16x8 W[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) W[t] = *reinterpret_cast<const bf16x8 *>(P + ((long)t * 32 + c0 + n) * 32 + kg * 8);
+    floatx4 bc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bc[r] = bias[c0 + 4 * kg + r];
+    wait_vm<0>();  // weights and bias in registers before the first transfer
+    const int nxt = d.nx / 32;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // block-uniform
+        const int x0 = (it % nxt) * 32, z0 = (it / nxt) * 4, z = z0 + wz;
+        const bool live = z < d.nz;  // a wave past the grid still moves data and meets the barriers
+        floatx4 A0[2] = {}, A1[2] = {}, A2[2] = {}, A3[2] = {};
+        ConvDmaOff<32, kHwWaves> O;
+        conv_dma_prep<32, kHwWaves>(O, d, x0, z0, w, lane);
+        __syncthreads();  // the previous item's reads of the ring are done
+        conv_dma_row<32, kHwWaves>(l0, X, O, d, -1, w);
+        conv_dma_row<32, kHwWaves>(l1, X, O, d, 0, w);
+        conv_dma_row<32, kHwWaves>(l2, X, O, d, 1, w);
+#define MGCT_CONV_HW_STEP(RS, RN, YI, AP, A0_, AN, AF, STORE)                                                      \
+    {                                                                                                            \
+        conv_row_wait<G::L, (ZOUT ? 4 : 2)>((YI), live);                                                        \
+        __syncthreads();                                                                                         \
+        conv_dma_row<32, kHwWaves>(RN, X, O, d, (YI) + 3, w);                                                    \
+        if (live)                                                                                                \
+            conv_hw_mfma_epi<ZOUT, STORE>(RS, W, wz, n, kg, AP, A0_, AN, AF, bc, zout, hout, d, x0, (YI) - 2, z,  \
+                                          c0);                                                                   \
+    }
+        MGCT_CONV_HW_STEP(ring0, l3, -1, A2, A3, A0, A1, false)
+        if (0 <= d.ny) MGCT_CONV_HW_STEP(ring1, l0, 0, A3, A0, A1, A2, false)
+        if (1 <= d.ny) MGCT_CONV_HW_STEP(ring2, l1, 1, A0, A1, A2, A3, false)
+        if (2 <= d.ny) MGCT_CONV_HW_STEP(ring3, l2, 2, A1, A2, A3, A0, true)
+        for (int yi = 3; yi <= d.ny; yi += 4) {
+            MGCT_CONV_HW_STEP(ring0, l3, yi, A2, A3, A0, A1, true)
+            if (yi + 1 > d.ny) break;
+            MGCT_CONV_HW_STEP(ring1, l0, yi + 1, A3, A0, A1, A2, true)
+            if (yi + 2 > d.ny) break;
+            MGCT_CONV_HW_STEP(ring2, l1, yi + 2, A0, A1, A2, A3, true)
+            if (yi + 3 > d.ny) break;
+            MGCT_CONV_HW_STEP(ring3, l2, yi + 3, A1, A2, A3, A0, true)
+        }
+#undef MGCT_CONV_HW_STEP
+        // the last row, ny - 1, completed in the last step
+        if (live) {
+            const int o = d.ny - 1;
+            const long e0 = (((long)z * d.ny + o) * d.nx + x0 + n) * 32 + c0 + 4 * kg;
+            const floatx4 *F = (o & 3) == 0 ? A0 : (o & 3) == 1 ? A1 : (o & 3) == 2 ? A2 : A3;
+            conv_hw_store<ZOUT>(F[0], zout, hout, e0);
+            conv_hw_store<ZOUT>(F[1], zout, hout, e0 + 16 * 32);
         }
         wait_vm<0>();  // no transfer into the ring stays in flight past the item
     }
@@ -935,6 +1132,9 @@ __global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h
 #ifndef MGCT_CONV_DMA
 #define MGCT_CONV_DMA 1  // large-grid forward: input rows staged in LDS by global-to-LDS loads
 #endif
+#ifndef MGCT_CONV32_HW
+#define MGCT_CONV32_HW 1  // the 32-channel layer on large grids: eight waves, half the channels each
+#endif
 #ifndef MGCT_CONV_YM_MIN_VOX
 #define MGCT_CONV_YM_MIN_VOX (128L * 128 * 128)  // forward on the marching kernel from this many voxels
 #endif
@@ -951,11 +1151,18 @@ static void launch_conv(const uint16_t *X, const uint16_t *P, const float *bias,
                        : 256;
         }
         const int n_items = (d.nx / 32) * ((d.nz + 3) / 4);
-        const unsigned nb = (unsigned)std::min(n_items, n_cu);
-        if (MGCT_CONV_DMA && zout)
-            k_conv_lds<CI, true><<<nb, 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        if (CI == 32 && MGCT_CONV32_HW) {
+            const unsigned nb = (unsigned)std::min(n_items, n_cu);
+            if (zout)
+                k_conv32_hw<true><<<nb, 512, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+            else
+                k_conv32_hw<false><<<nb, 512, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+        } else if (MGCT_CONV_DMA && zout)
+            k_conv_lds<CI, true><<<(unsigned)std::min(n_items, n_cu * conv_lds_blocks<CI, true>()), 256, 0, s>>>(
+                X, P, bias, zout, hout, d, n_items);
         else if (MGCT_CONV_DMA)
-            k_conv_lds<CI, false><<<nb, 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
+            k_conv_lds<CI, false><<<(unsigned)std::min(n_items, n_cu * conv_lds_blocks<CI, false>()), 256, 0, s>>>(
+                X, P, bias, zout, hout, d, n_items);
         else
             k_conv_ym<CI><<<(unsigned)std::min(n_items, n_cu), 256, 0, s>>>(X, P, bias, zout, hout, d, n_items);
         return;

@@ -68,19 +68,46 @@ def test_forward_matches_oracle():
     assert e_plain <= 2e-2
 
 
-def test_forward_large_grid_marching_kernel():
+@pytest.fixture(scope="module")
+def large_grid():
+    """A ragged grid above 128^3 voxels (z not a multiple of the 4-z block, y
+    not a multiple of 3) and its storage-model forward pass, shared by the
+    two large-grid tests."""
+    ctx, params, u, target = _setup(shape=(102, 136, 160), seed=7)
+    sref, cache = cnn_storage.forward(u, params)
+    return ctx, params, u, target, sref, cache
+
+
+def test_forward_large_grid_marching_kernel(large_grid):
     """From 128^3 voxels up the two 32-output layers run on the persistent,
-    weight-stationary kernel that marches along y (and the activations use
-    the branch-free GELU).  A ragged grid above that size (z not a multiple of
-    the 4-z block, y not a multiple of 3) against the same storage model."""
-    ctx, params, u, _ = _setup(shape=(102, 136, 160), seed=7)
+    weight-stationary kernels that march along y (and the activations use
+    the branch-free GELU), against the same storage model."""
+    ctx, params, u, _, sref, _ = large_grid
     out = to_host(ctx.cnn_forward(to_dev(u)))
-    sref, _ = cnn_storage.forward(u, params)
     u32 = cnn_storage.f32(u)
     e = rel_l2(out - u32, sref - u32)
     emax = _max_rel(out - u32, sref - u32)
     say("cnn forward 160x136x102: rel L2 vs storage model %.3e (max %.3e)" % (e, emax))
     assert e <= FWD_L2 and emax <= FWD_MAX
+
+
+def test_gradients_large_grid(large_grid):
+    """The training forward pass on a large grid keeps every layer's FP32
+    pre-activations besides the BF16 activations (the marching kernels'
+    second output); the gradients built from them against the storage
+    model's."""
+    ctx, params, u, target, sref, cache = large_grid
+    g, loss = ctx.cnn_gradients(to_dev(u), to_dev(target))
+    gg = mg.cnn_unflatten(g)
+    lref, dout = cnn.mse(sref, target)
+    gref = cnn_storage.backward(cache, dout, params)
+    say("cnn loss 160x136x102", loss, lref)
+    assert abs(loss - lref) / lref <= 1e-5
+    for li in range(4):
+        for pi in range(2):
+            e = rel_l2(gg[li][pi], gref[li][pi])
+            say("  layer %d %s rel L2 %.3e" % (li + 1, "W" if pi == 0 else "b", e))
+            assert e <= GRAD_L2, (li, pi, e)
 
 
 def test_gradients_match_oracle():
