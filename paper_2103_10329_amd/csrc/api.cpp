@@ -544,12 +544,14 @@ int do_estimate(Ctx &c, Level &L, int g, const mgct_filter *f, int iters, uint64
     return MGCT_OK;
 }
 
-int cnn_buffers(Ctx &c, long n, bool train, CnnBuffers &B) {
+int cnn_buffers(Ctx &c, int nx, int ny, int nz, bool train, CnnBuffers &B) {
     auto get = [&](const char *name, size_t bytes, bool zero = false) { return workspace(c, name, bytes, zero); };
+    const long n = (long)nx * ny * nz;
+    B.up = (float *)get("cnn_up", (size_t)(nx + 2) * (ny + 2) * (nz + 2) * 4);
     B.h1 = (uint16_t *)get("cnn_h1", n * 16 * 2);
     B.h2 = (uint16_t *)get("cnn_h2", n * 32 * 2);
     B.h3 = (uint16_t *)get("cnn_h3", n * 32 * 2);
-    if (!B.h1 || !B.h2 || !B.h3) return MGCT_ERR_OOM;
+    if (!B.up || !B.h1 || !B.h2 || !B.h3) return MGCT_ERR_OOM;
     if (!train) return MGCT_OK;
     B.z1 = (float *)get("cnn_z1", n * 16 * 4);
     B.z2 = (float *)get("cnn_z2", n * 32 * 4);
@@ -668,7 +670,8 @@ int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
     if (!S.master) {
         void *p = nullptr;
         const size_t fb = kCnnParams * 4;
-        if (hipMalloc(&p, 4 * fb + 2 * (size_t)27 * 32 * 16 + 3 * 2 * (size_t)27 * 32 * 32 + 2 * 6144) != hipSuccess)
+        if (hipMalloc(&p, 4 * fb + 2 * (size_t)27 * 32 * 16 + 3 * 2 * (size_t)27 * 32 * 32 + 2 * 6144 + 2 * 1536) !=
+            hipSuccess)
             return MGCT_ERR_OOM;
         char *q = (char *)p;
         S.master = (float *)q; q += fb;
@@ -679,7 +682,8 @@ int mgct_cnn_set_weights(void *ctx, const float *w, int n) {
         S.p3f = (uint16_t *)q; q += 2 * 27 * 32 * 32;
         S.p3d = (uint16_t *)q; q += 2 * 27 * 32 * 32;
         S.p2d = (uint16_t *)q; q += 2 * 27 * 32 * 32;
-        S.p4 = (uint16_t *)q;
+        S.p4 = (uint16_t *)q; q += 2 * 6144;
+        S.p1 = (uint16_t *)q;
     }
     HIPCHK(hipMemcpy(S.master, w, kCnnParams * 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(S.adam_m, 0, kCnnParams * 4));
@@ -707,7 +711,7 @@ int mgct_cnn_forward(void *ctx, int nx, int ny, int nz, const float *u, float *o
     HIPCHK(hipSetDevice(c.device));
     MGCHK(cnn_check(c, nx, ny, nz));
     CnnBuffers B;
-    MGCHK(cnn_buffers(c, (long)nx * ny * nz, false, B));
+    MGCHK(cnn_buffers(c, nx, ny, nz, false, B));
     HIPCHK(cnn_forward(c.cnn, B, u, out, nx, ny, nz, false, s));
     return MGCT_OK;
 }
@@ -716,7 +720,7 @@ static int cnn_fwd_bwd(Ctx &c, int nx, int ny, int nz, const float *u, const flo
                        hipStream_t s) {
     const long n = (long)nx * ny * nz;
     CnnBuffers B;
-    MGCHK(cnn_buffers(c, n, true, B));
+    MGCHK(cnn_buffers(c, nx, ny, nz, true, B));
     MGCHK(cnn_train_scratch(c, nx, ny, nz, B));
     WS(out, float, "cnn_out", n * 4, false);
     WS(part, double, "red_partials", kRedBlocks * 8, false);
@@ -1264,7 +1268,7 @@ int mgct_multigrid_solve(void *ctx, float *vol, const void *b, int b_dtype, cons
                     HIPCHK(hipMemcpyAsync(jr, r0, 8, hipMemcpyDeviceToDevice, s));
                 }
                 CnnBuffers B;
-                MGCHK(cnn_buffers(c, (long)L.vox(), false, B));
+                MGCHK(cnn_buffers(c, L.nx, L.ny, L.nz, false, B));
                 HIPCHK(cnn_forward(c.cnn, B, u, cu, L.nx, L.ny, L.nz, false, s));
                 HIPCHK(launch_add(mu[0], cu, try_mu, L.vox(), s));
                 if (sub)

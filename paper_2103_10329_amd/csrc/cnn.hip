@@ -22,6 +22,7 @@ namespace mgct {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // offsets into the FP32 master parameter vector ([co][ci][kz][ky][kx] per layer)
 constexpr int kW1 = 0, kB1 = 432, kW2 = 448, kB2 = 14272, kW3 = 14304, kB3 = 41952, kW4 = 41984, kB4 = 42848;
@@ -121,42 +122,109 @@ __global__ void k_pack_weights4(const float *__restrict__ w, uint16_t *P4) {
     P4[i] = r;
 }
 
-// ------------------------------------------------------ VALU layers ----
-
-// z1[v][16] = b1 + sum_t W1[co][t] u[v + off_t]; h1 = GELU(z1) (BF16).
-__global__ __launch_bounds__(256) void k_conv1_fwd(const float *__restrict__ u, const float *__restrict__ w,
-                                                   float *__restrict__ z1, uint16_t *__restrict__ h1, Dims d) {
-    const long n = (long)d.nx * d.ny * d.nz;
-    const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int x, y, z;
-    split3(v, d.nx, d.ny, x, y, z);
-    float in[27];
-#pragma unroll
-    for (int t = 0; t < 27; ++t) {
-        long q;
-        in[t] = tap_voxel(d, x, y, z, t, q) ? u[q] : 0.f;
-    }
-    // the 16 outputs of a voxel leave as two 16-byte stores (and four for z1)
-    uint32_t pk[8];
-#pragma unroll
-    for (int c2 = 0; c2 < 8; ++c2) {
-        float acc[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int co = 2 * c2 + e;
-            float a = w[kB1 + co];
-#pragma unroll
-            for (int t = 0; t < 27; ++t) a = fmaf(w[kW1 + co * 27 + t], in[t], a);
-            acc[e] = a;
-        }
-        if (z1) *reinterpret_cast<float2 *>(z1 + v * 16 + 2 * c2) = make_float2(acc[0], acc[1]);
-        pk[c2] = (uint32_t)to_bf(gelu(acc[0])) | ((uint32_t)to_bf(gelu(acc[1])) << 16);
-    }
-    uint4 *dst = reinterpret_cast<uint4 *>(h1 + v * 16);
-    dst[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-    dst[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+// P1[p][c][k]: the three BF16 pieces (p = 0, 1, 2: top, middle and low 8 bits
+// of the significand, by truncation, so that w = sum of the pieces exactly)
+// of W1[c][tap k] for k < 27, zero for k = 27..31 (the MFMA's K of 32).
+__device__ __forceinline__ void split_bf16x3(float x, float &p0, float &p1, float &p2) {
+    p0 = __uint_as_float(__float_as_uint(x) & 0xffff0000u);
+    const float r = x - p0;  // exact
+    p1 = __uint_as_float(__float_as_uint(r) & 0xffff0000u);
+    p2 = r - p1;  // exact, at most 8 significant bits
 }
+__global__ void k_pack_weights1(const float *__restrict__ w, uint16_t *P1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * 16 * 32) return;
+    const int p = i / 512, c = (i / 32) % 16, k = i % 32;
+    float q[3] = {0.f, 0.f, 0.f};
+    if (k < 27) split_bf16x3(w[kW1 + c * 27 + k], q[0], q[1], q[2]);
+    P1[i] = (uint16_t)(__float_as_uint(q[p]) >> 16);
+}
+
+// the input with a zero border of one voxel: up[(z+1)][(y+1)][(x+1)] =
+// u[z][y][x]; one block per padded row (zp, yp)
+__global__ __launch_bounds__(256) void k_pad_input(const float *__restrict__ u, float *__restrict__ up, Dims d) {
+    const int PX = d.nx + 2, PY = d.ny + 2;
+    const int yp = blockIdx.x % PY, zp = blockIdx.x / PY;
+    const bool rin = yp >= 1 && yp <= d.ny && zp >= 1 && zp <= d.nz;  // block-uniform
+    const float *srow = rin ? u + ((long)(zp - 1) * d.ny + (yp - 1)) * d.nx - 1 : u;
+    float *drow = up + (long)blockIdx.x * PX;
+    for (int xp = threadIdx.x; xp < PX; xp += blockDim.x)
+        drow[xp] = rin && xp >= 1 && xp <= d.nx ? srow[xp] : 0.f;
+}
+
+// Layer 1 (1 -> 16 channels) on the matrix cores.  A wave takes one row of
+// voxels along x, 16 at a time, and computes per group D[c][x] = b1[c] +
+// sum over the taps t of W1[c][t] U[t][x] as 16x16x32 MFMAs (K: the 27 taps
+// and 5 zero weights).  The FP32 operands are split exactly into three BF16
+// pieces (split_bf16x3), and the six piece products of combined order <= 2
+// are accumulated in FP32: the three left out are below 2^-24 of the terms,
+// so the sums keep FP32 accuracy.  The taps read the zero-bordered copy of
+// u, none needs a bounds check; the next group's taps load while the
+// current one is worked on.  Lane (n, kg) = (lane mod 16, lane / 16) holds
+// row n of the weight fragments (channel n, taps 8 kg .. 8 kg + 7), column n
+// of the input fragments (voxel x + n, the same taps) and of the result the
+// channels 4 kg .. 4 kg + 3 of voxel x + n.
+__global__ __launch_bounds__(256) void k_conv1_mfma(const float *__restrict__ up, const uint16_t *__restrict__ P1,
+                                                    const float *__restrict__ w, float *__restrict__ z1,
+                                                    uint16_t *__restrict__ h1, Dims d) {
+    const long row = blockIdx.x * 4L + (threadIdx.x >> 6);  // z ny + y
+    if (row >= (long)d.ny * d.nz) return;                      // whole wave; no barrier in this kernel
+    const int lane = threadIdx.x & 63, n = lane & 15, kg = lane >> 4;
+    const int y = (int)(row % d.ny), z = (int)(row / d.ny);
+    const int PX = d.nx + 2, PYX = (d.ny + 2) * PX;
+    bf16x8 W[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) W[p] = *reinterpret_cast<const bf16x8 *>(P1 + (p * 16 + n) * 32 + kg * 8);
+    floatx4 bc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bc[r] = w[kB1 + 4 * kg + r];
+    // tap t = 9 kz + 3 ky + kx (t / 9 and r / 3 by multiply and shift, exact
+    // for t < 32) reads up at the voxel's padded base + kz PYX + ky PX + kx;
+    // the zero-weight slots 27..31 read the base itself
+    int off[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int t = kg * 8 + s, kz = (t * 57) >> 9, r = t - 9 * kz, ky = (r * 11) >> 5, kx = r - 3 * ky;
+        off[s] = t < 27 ? kz * PYX + ky * PX + kx : 0;
+    }
+    const float *src = up + ((long)z * (d.ny + 2) + y) * PX + n;
+    uint2 *dst = reinterpret_cast<uint2 *>(h1 + (row * d.nx + n) * 16 + 4 * kg);
+    floatx4 *zdst = z1 ? reinterpret_cast<floatx4 *>(z1 + (row * d.nx + n) * 16 + 4 * kg) : nullptr;
+    float uu[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) uu[s] = src[off[s]];
+    for (int x = 0; x < d.nx; x += 16) {
+        uint32_t b[3][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float a0, a1, a2, c0, c1, c2;
+            split_bf16x3(uu[2 * j], a0, a1, a2);
+            split_bf16x3(uu[2 * j + 1], c0, c1, c2);
+            // the upper halves of the two pieces, slot 2j low
+            b[0][j] = __builtin_amdgcn_perm(__float_as_uint(c0), __float_as_uint(a0), 0x07060302u);
+            b[1][j] = __builtin_amdgcn_perm(__float_as_uint(c1), __float_as_uint(a1), 0x07060302u);
+            b[2][j] = __builtin_amdgcn_perm(__float_as_uint(c2), __float_as_uint(a2), 0x07060302u);
+        }
+        if (x + 16 < d.nx) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) uu[s] = src[x + 16 + off[s]];
+        }
+        bf16x8 B[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) B[p] = __builtin_bit_cast(bf16x8, make_uint4(b[p][0], b[p][1], b[p][2], b[p][3]));
+        // smallest products first
+        floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[2], B[0], bc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[1], B[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[0], B[2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[1], B[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[0], B[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W[0], B[0], acc, 0, 0, 0);
+        if (zdst) zdst[x * 4] = acc;
+        dst[x * 4] = make_uint2(pack_bf16x2(gelu(acc[0]), gelu(acc[1])), pack_bf16x2(gelu(acc[2]), gelu(acc[3])));
+    }
+}
+
+// ------------------------------------------------------ VALU layers ----
 
 // out[v] = u[v] + b4 + sum_{t, ci} W4[ci][t] h3[v + off_t][ci]
 __global__ __launch_bounds__(256) void k_conv4_fwd(const uint16_t *__restrict__ h3, const float *__restrict__ w,
@@ -760,19 +828,22 @@ __device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds
         const int dz = g / 3, dx = g % 3;
         return *reinterpret_cast<const bf16x8 *>(slot + (((w + dz) * 34) * G::CP + conv_slot<CI>(m + dx, kc * 2 + kh)) * 8);
     };
-    bf16x8 fr[2][CI / 16];
+    // fragments two tap groups ahead of the MFMAs that use them
+    bf16x8 fr[3][CI / 16];
 #pragma unroll
-    for (int kc = 0; kc < CI / 16; ++kc) fr[0][kc] = frag(0, kc);
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int kc = 0; kc < CI / 16; ++kc) fr[g][kc] = frag(g, kc);
 #pragma unroll
     for (int g = 0; g < 9; ++g) {
         const int dz = g / 3, dx = g % 3;
-        if (g < 8) {
+        if (g < 7) {
 #pragma unroll
-            for (int kc = 0; kc < CI / 16; ++kc) fr[(g + 1) & 1][kc] = frag(g + 1, kc);
+            for (int kc = 0; kc < CI / 16; ++kc) fr[(g + 2) % 3][kc] = frag(g + 2, kc);
         }
 #pragma unroll
         for (int kc = 0; kc < CI / 16; ++kc) {
-            const bf16x8 a = fr[g & 1][kc];
+            const bf16x8 a = fr[g % 3][kc];
             const int tb = dz * 9 + dx;
             // row YI + 1 starts here: its first product adds to the bias
             aN = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, W.f[tb][kc], g == 0 && kc == 0 ? (floatx16)bc : aN, 0,
@@ -790,13 +861,18 @@ __device__ __forceinline__ void conv_lds_mfma_epi(const uint16_t (&slot)[ConvLds
             }
         }
     }
-    if (STORE) {
-        // one MFMA, then up to seven vector instructions, in turn: the vector
-        // work runs in the shadow of the matrix instruction before it
+    // order: the first two groups' fragment reads; then per group the reads
+    // for two groups ahead and its MFMAs, each followed by up to seven
+    // vector instructions of the epilogue (they run in the shadow of the
+    // matrix instruction before them)
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * (CI / 16), 0);  // LDS reads
 #pragma unroll
-        for (int i = 0; i < 27 * (CI / 16); ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // VALU
+    for (int g = 0; g < 9; ++g) {
+        if (g < 7) __builtin_amdgcn_sched_group_barrier(0x100, CI / 16, 0);
+#pragma unroll
+        for (int i = 0; i < 3 * (CI / 16); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);             // MFMA
+            if (STORE) __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // VALU
         }
     }
 }
@@ -904,7 +980,6 @@ __global__ __launch_bounds__(256, (conv_lds_blocks<CI, ZOUT>())) void k_conv_lds
 // the result the channels c0 + 4 kg .. c0 + 4 kg + 3 of voxel hx 16 + n,
 // which leave as one 8-byte store.  Accumulators of output row o: A[o mod 4],
 // one 4-vector per half.
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kHwWaves = 8;
 using ConvHwLds = ConvLds<32, kHwWaves>;
 
@@ -1042,8 +1117,9 @@ __global__ __launch_bounds__(512, 1) void k_conv32_hw(const uint16_t *__restrict
 // E[x - x0 + dx][(dx, dy)] over dx for the row yo = yi - dy.  A wave's 32
 // input voxels x0 .. x0 + 31 serve the 30 outputs x0 + 1 .. x0 + 30 (tiles at
 // stride 30), marching up y with three output rows in flight; a block's 4
-// waves take 4 consecutive z.  The next row's A fragments load while the
-// current row is worked on.
+// waves take 4 consecutive z (8 per block, or blocks ordered so that z
+// neighbours share a die's L2, read fewer bytes but ran slower).  The next
+// row's A fragments load while the current row is worked on.
 struct Conv4Row {
     bf16x8 a[3][2];  // [dz][channel chunk]
 };
@@ -1060,14 +1136,18 @@ __device__ __forceinline__ void conv4_load(Conv4Row &R, const uint16_t *__restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ P4,
-                                                  const float *__restrict__ w, const float *__restrict__ u,
-                                                  float *__restrict__ out, Dims d) {
-    __shared__ float E[4][32 * 9];
+constexpr int kConv4Waves = 4;  // z planes per block
+
+__global__ __launch_bounds__(64 * kConv4Waves) void k_conv4_ym(const uint16_t *__restrict__ h3,
+                                                               const uint16_t *__restrict__ P4,
+                                                               const float *__restrict__ w,
+                                                               const float *__restrict__ u, float *__restrict__ out,
+                                                               Dims d) {
+    __shared__ float E[kConv4Waves][32 * 9];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 31, kh = lane >> 5;
     const int ntile = (d.nx + 29) / 30;
-    const int x0 = (blockIdx.x % ntile) * 30 - 1, z = (blockIdx.x / ntile) * 4 + wv;
+    const int x0 = (blockIdx.x % ntile) * 30 - 1, z = (blockIdx.x / ntile) * kConv4Waves + wv;
     if (z >= d.nz) return;  // whole wave; no barrier in this kernel
     bf16x8 Bf[2][3][2];
 #pragma unroll
@@ -1303,6 +1383,7 @@ static unsigned blocks(long n, int per = 256) { return (unsigned)((n + per - 1) 
 hipError_t cnn_pack(CnnState &S, hipStream_t s) {
     k_pack_weights<<<blocks(27 * 32 * 32), 256, 0, s>>>(S.master, S.p2f, S.p3f, S.p3d, S.p2d);
     k_pack_weights4<<<blocks(2 * 3 * 2 * 32 * 16), 256, 0, s>>>(S.master, S.p4);
+    k_pack_weights1<<<blocks(3 * 16 * 32), 256, 0, s>>>(S.master, S.p1);
     return hipGetLastError();
 }
 
@@ -1311,11 +1392,13 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
     const unsigned vb = blocks(n);
-    k_conv1_fwd<<<vb, 256, 0, s>>>(u, S.master, keep ? B.z1 : nullptr, B.h1, d);
+    k_pad_input<<<(unsigned)((long)(ny + 2) * (nz + 2)), 256, 0, s>>>(u, B.up, d);
+    k_conv1_mfma<<<blocks((long)ny * nz, 4), 256, 0, s>>>(B.up, S.p1, S.master, keep ? B.z1 : nullptr, B.h1, d);
     launch_conv<16, 0>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d, s);
     launch_conv<32, 0>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d, s);
     if (n >= MGCT_CONV_YM_MIN_VOX)
-        k_conv4_ym<<<(unsigned)(((nx + 29) / 30) * ((nz + 3) / 4)), 256, 0, s>>>(B.h3, S.p4, S.master, u, out, d);
+        k_conv4_ym<<<(unsigned)(((nx + 29) / 30) * ((nz + kConv4Waves - 1) / kConv4Waves)), 64 * kConv4Waves, 0, s>>>(
+            B.h3, S.p4, S.master, u, out, d);
     else
         k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
     return hipGetLastError();

@@ -78,6 +78,7 @@ struct CnnState {
     float *adam_m = nullptr, *adam_v = nullptr, *grads = nullptr;
     uint16_t *p2f = nullptr, *p3f = nullptr, *p3d = nullptr, *p2d = nullptr;  // packed BF16 operands
     uint16_t *p4 = nullptr;  // layer 4's weights as BF16 pairs for the matrix-core kernel
+    uint16_t *p1 = nullptr;  // layer 1's weights as three exact BF16 pieces
     int adam_t = 0;
     bool ready = false;
 };
@@ -90,6 +91,7 @@ struct CnnBuffers {
     uint16_t *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
     uint16_t *gT = nullptr, *xT = nullptr;                  // channels-first copies for weight gradients
     float *partial = nullptr;
+    float *up = nullptr;  // the input with a zero border, (nx + 2)(ny + 2)(nz + 2)
 };
 
 hipError_t cnn_pack(CnnState &S, hipStream_t s);
