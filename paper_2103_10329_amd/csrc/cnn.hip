@@ -1116,39 +1116,48 @@ __global__ __launch_bounds__(512, 1) void k_conv32_hw(const uint16_t *__restrict
 // it are kept), whose result goes to LDS; output (x, yo) then adds
 // E[x - x0 + dx][(dx, dy)] over dx for the row yo = yi - dy.  A wave's 32
 // input voxels x0 .. x0 + 31 serve the 30 outputs x0 + 1 .. x0 + 30 (tiles at
-// stride 30), marching up y with three output rows in flight; a block's 4
-// waves take 4 consecutive z (8 per block, or blocks ordered so that z
-// neighbours share a die's L2, read fewer bytes but ran slower).  The next
-// row's A fragments load while the current row is worked on.
-struct Conv4Row {
-    bf16x8 a[3][2];  // [dz][channel chunk]
+// stride 30), marching up y with three output rows in flight.  A wave takes
+// ZW consecutive output planes, whose ZW + 2 input slices per row it loads
+// once; a block's 4 waves take 4 ZW consecutive z.  The kernel waits on
+// memory latency, so it runs fastest with one plane per wave at 3 waves per
+// SIMD: two planes per wave, a block of 8 one-plane waves, blocks ordered so
+// that z neighbours share a die's L2 (all read fewer bytes) and register
+// caps for more waves (they spill) each ran slower.  The next row's A fragments load while the
+// current row is worked on.
+
+// the input slices z0 - 1 .. z0 + ZW of one row for the wave's ZW output planes
+template <int ZW> struct Conv4Row {
+    bf16x8 a[ZW + 2][2];  // [slice][channel chunk]
 };
 
-__device__ __forceinline__ void conv4_load(Conv4Row &R, const uint16_t *__restrict__ h3, const Dims &d, int x,
-                                           int z, int yi, int kh) {
+template <int ZW>
+__device__ __forceinline__ void conv4_load(Conv4Row<ZW> &R, const uint16_t *__restrict__ h3, const Dims &d, int x,
+                                           int z0, int yi, int kh) {
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-        const int zz = z + dz - 1;
+    for (int sl = 0; sl < ZW + 2; ++sl) {
+        const int zz = z0 + sl - 1;
         const bool ok = yi >= 0 && yi < d.ny && zz >= 0 && zz < d.nz && x >= 0 && x < d.nx;
         const uint16_t *src = (ok ? h3 + (((long)zz * d.ny + yi) * d.nx + x) * 32 : kConvZeros) + kh * 8;
 #pragma unroll
-        for (int kc = 0; kc < 2; ++kc) R.a[dz][kc] = *reinterpret_cast<const bf16x8 *>(src + (ok ? kc * 16 : 0));
+        for (int kc = 0; kc < 2; ++kc) R.a[sl][kc] = *reinterpret_cast<const bf16x8 *>(src + (ok ? kc * 16 : 0));
     }
 }
 
-constexpr int kConv4Waves = 4;  // z planes per block
+#ifndef MGCT_CONV4_ZW
+#define MGCT_CONV4_ZW 1
+#endif
+constexpr int kConv4Zw = MGCT_CONV4_ZW;  // output planes per wave; a block's 4 waves take 4 kConv4Zw planes
 
-__global__ __launch_bounds__(64 * kConv4Waves) void k_conv4_ym(const uint16_t *__restrict__ h3,
-                                                               const uint16_t *__restrict__ P4,
-                                                               const float *__restrict__ w,
-                                                               const float *__restrict__ u, float *__restrict__ out,
-                                                               Dims d) {
-    __shared__ float E[kConv4Waves][32 * 9];
+template <int ZW>
+__global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ P4,
+                                                  const float *__restrict__ w, const float *__restrict__ u,
+                                                  float *__restrict__ out, Dims d) {
+    __shared__ float E[4][ZW][32 * 9];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 31, kh = lane >> 5;
     const int ntile = (d.nx + 29) / 30;
-    const int x0 = (blockIdx.x % ntile) * 30 - 1, z = (blockIdx.x / ntile) * kConv4Waves + wv;
-    if (z >= d.nz) return;  // whole wave; no barrier in this kernel
+    const int x0 = (blockIdx.x % ntile) * 30 - 1, z0 = (blockIdx.x / ntile) * 4 * ZW + wv * ZW;
+    if (z0 >= d.nz) return;  // whole wave; no barrier in this kernel
     bf16x8 Bf[2][3][2];
 #pragma unroll
     for (int hl = 0; hl < 2; ++hl)
@@ -1159,48 +1168,58 @@ __global__ __launch_bounds__(64 * kConv4Waves) void k_conv4_ym(const uint16_t *_
                 Bf[hl][dz][kc] =
                     *reinterpret_cast<const bf16x8 *>(P4 + ((((hl * 3 + dz) * 2 + kc) * 32 + m) * 16 + kh * 8));
     const float b4 = w[kB4];
-    float *Ew = E[wv];
     const int xo = x0 + 1 + m;                   // this lane's output x (lanes m < 30, kh = 0)
     const bool gather = kh == 0 && m < 30 && xo < d.nx;
-    float oP = 0.f, o0 = 0.f, oN = 0.f;          // output rows yi - 1, yi, yi + 1
+    float oP[ZW], o0[ZW], oN[ZW];                // per plane: output rows yi - 1, yi, yi + 1
+#pragma unroll
+    for (int q = 0; q < ZW; ++q) oP[q] = o0[q] = oN[q] = 0.f;
     // one input row from buffer C (the next row's loads already in flight)
-    auto row = [&](const Conv4Row &C, int yi) {
-        floatx16 acc{};
+    auto row = [&](const Conv4Row<ZW> &C, int yi) {
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz)
+        for (int q = 0; q < ZW; ++q) {
+            floatx16 acc{};
 #pragma unroll
-            for (int kc = 0; kc < 2; ++kc)
+            for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-                for (int hl = 0; hl < 2; ++hl)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.a[dz][kc], Bf[hl][dz][kc], acc, 0, 0, 0);
-        if (m < 9) {
+                for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) Ew[(8 * (r >> 2) + 4 * kh + (r & 3)) * 9 + m] = acc[r];
+                    for (int hl = 0; hl < 2; ++hl)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.a[q + dz][kc], Bf[hl][dz][kc], acc, 0, 0, 0);
+            if (m < 9) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) E[wv][q][(8 * (r >> 2) + 4 * kh + (r & 3)) * 9 + m] = acc[r];
+            }
         }
         __builtin_amdgcn_wave_barrier();
         if (gather) {
-            // slot j = 3 (dy + 1) + dx + 1 of input m + 1 + dx
-            const float *e = Ew + (m + 1) * 9;
-            oN += e[-9 + 0] + e[1] + e[9 + 2];   // dy = -1 -> output row yi + 1
-            o0 += e[-9 + 3] + e[4] + e[9 + 5];   // dy = 0
-            oP += e[-9 + 6] + e[7] + e[9 + 8];   // dy = +1 -> output row yi - 1
+#pragma unroll
+            for (int q = 0; q < ZW; ++q) {
+                // slot j = 3 (dy + 1) + dx + 1 of input m + 1 + dx
+                const float *e = &E[wv][q][(m + 1) * 9];
+                oN[q] += e[-9 + 0] + e[1] + e[9 + 2];   // dy = -1 -> output row yi + 1
+                o0[q] += e[-9 + 3] + e[4] + e[9 + 5];   // dy = 0
+                oP[q] += e[-9 + 6] + e[7] + e[9 + 8];   // dy = +1 -> output row yi - 1
+            }
         }
         __builtin_amdgcn_wave_barrier();
-        if (gather && yi - 1 >= 0) {
-            const long v = ((long)z * d.ny + (yi - 1)) * d.nx + xo;
-            out[v] = u[v] + (oP + b4);
+#pragma unroll
+        for (int q = 0; q < ZW; ++q) {
+            if (gather && yi - 1 >= 0 && z0 + q < d.nz) {
+                const long v = ((long)(z0 + q) * d.ny + (yi - 1)) * d.nx + xo;
+                out[v] = u[v] + (oP[q] + b4);
+            }
+            oP[q] = o0[q];
+            o0[q] = oN[q];
+            oN[q] = 0.f;
         }
-        oP = o0;
-        o0 = oN;
-        oN = 0.f;
     };
-    Conv4Row RA, RB;
-    conv4_load(RA, h3, d, x0 + m, z, -1, kh);
+    Conv4Row<ZW> RA, RB;
+    conv4_load<ZW>(RA, h3, d, x0 + m, z0, -1, kh);
     for (int yi = -1; yi <= d.ny; yi += 2) {
-        conv4_load(RB, h3, d, x0 + m, z, yi + 1, kh);
+        conv4_load<ZW>(RB, h3, d, x0 + m, z0, yi + 1, kh);
         row(RA, yi);
         if (yi + 1 > d.ny) break;
-        conv4_load(RA, h3, d, x0 + m, z, yi + 2, kh);
+        conv4_load<ZW>(RA, h3, d, x0 + m, z0, yi + 2, kh);
         row(RB, yi + 1);
     }
 }
@@ -1397,7 +1416,7 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
     launch_conv<16, 0>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d, s);
     launch_conv<32, 0>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d, s);
     if (n >= MGCT_CONV_YM_MIN_VOX)
-        k_conv4_ym<<<(unsigned)(((nx + 29) / 30) * ((nz + kConv4Waves - 1) / kConv4Waves)), 64 * kConv4Waves, 0, s>>>(
+        k_conv4_ym<kConv4Zw><<<(unsigned)(((nx + 29) / 30) * ((nz + 4 * kConv4Zw - 1) / (4 * kConv4Zw))), 256, 0, s>>>(
             B.h3, S.p4, S.master, u, out, d);
     else
         k_conv4_fwd<<<vb, 256, 0, s>>>(B.h3, S.master, u, out, d);
