@@ -61,6 +61,9 @@ def main():
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="only run the 640x640x2304 / 3600 x 760^2 workload (prints its own JSON line)")
+    ap.add_argument("--cnn-forward", type=int, metavar="N",
+                    help="only time the learned preconditioner's forward pass on an N^3 grid, --warmup untimed "
+                         "and --steps timed passes (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (the views would shard across "
@@ -72,6 +75,9 @@ def main():
         return
     if args.paper_shaped:
         paper_shaped()
+        return
+    if args.cnn_forward:
+        cnn_forward_timing(args.cnn_forward, args.steps, args.warmup)
         return
 
     import torch
@@ -636,6 +642,40 @@ def in_cone_fraction(views, nx, ny, nz, h, nu, nv, sub=4, chunk=8):
         ok = (t > 0) & (a >= -0.5) & (a <= nu - 0.5) & (b >= -0.5) & (b <= nv - 0.5)
         inside += int(ok.sum())
     return inside / (P.shape[0] * len(views))
+
+
+# multiply-adds per voxel of the learned preconditioner's four 3x3x3 layers
+# (1 -> 16 -> 32 -> 32 -> 1 channels), two operations each
+CNN_FLOPS_PER_VOXEL = 2 * 27 * (1 * 16 + 16 * 32 + 32 * 32 + 32 * 1)
+
+
+def cnn_forward_timing(n, steps, warmup):
+    """The network's forward pass alone on an n^3 grid (trained weights; a
+    seeded random input), timed with HIP events on the library's stream,
+    priced against the dense BF16 matrix-core peak."""
+    import torch
+
+    import paper_2103_10329_amd as mg
+    from paper_2103_10329_amd import learned as lrn
+    ctx = mg.Context(0)
+    ctx.cnn_set_weights(lrn.load_weights())
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    u = torch.randn((n, n, n), device="cuda", generator=gen) * 1e-3
+    out = torch.empty_like(u)
+    for _ in range(max(warmup, 1)):
+        ctx.cnn_forward(u, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ctx.cnn_forward(u, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tflops = CNN_FLOPS_PER_VOXEL * n ** 3 / (ms * 1e-3) / 1e12
+    print(json.dumps({"cnn_forward": {"n": n, "ms": ms, "steps": steps, "tflops": tflops,
+                                      "frac_bf16_dense_peak": tflops / 2500.0,
+                                      "flops_per_voxel": CNN_FLOPS_PER_VOXEL}}), flush=True)
 
 
 def copy_calibration(size_mib=1024, reps=5):
