@@ -61,6 +61,9 @@ def main():
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--paper-shaped", action="store_true",
                     help="only run the 640x640x2304 / 3600 x 760^2 workload (prints its own JSON line)")
+    ap.add_argument("--quality-sweep", action="store_true",
+                    help="only run the 128^3 image-error sweep over the regularisation readings and iteration "
+                         "counts of Algorithm 1 (prints its own JSON line)")
     ap.add_argument("--cnn-forward", type=int, metavar="N",
                     help="only time the learned preconditioner's forward pass on an N^3 grid, --warmup untimed "
                          "and --steps timed passes (prints its own JSON line)")
@@ -78,6 +81,9 @@ def main():
         return
     if args.cnn_forward:
         cnn_forward_timing(args.cnn_forward, args.steps, args.warmup)
+        return
+    if args.quality_sweep:
+        quality_sweep()
         return
 
     import torch
@@ -406,6 +412,53 @@ def quality_c1(args):
     res["value_gvox_views_s"] = n ** 3 * cfg.n_views / (ms * 1e-3) / 1e9
     ctx.close()
     return res
+
+
+def quality_sweep():
+    """Masked image error on the 128^3 workload (the same data, mask and
+    radial filter as quality_c1) of Algorithm 1 from zero after 1, 2, 4 and 10
+    iterations for the soft-threshold weight lambda in {0, 1e-3, 1e-2} with
+    and without the bilateral filter (sigma_s 1, sigma_r 0.05), and of
+    full-resolution OS-EMTR (8 subsets) after 2, 4 and 10 iterations."""
+    import torch
+
+    import paper_2103_10329_amd as mg
+    import synth
+    cfg = synth.CONFIGS["c1"]
+    n = cfg.n
+    d = synth.make_dataset("c1", truth=True)
+    ctx = mg.Context(0)
+    ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, d["views"])
+    b = torch.from_numpy(d["b"].astype(np.float32)).cuda()
+    table = np.maximum(np.linspace(0, np.sqrt(3), 4097), 2.0 / n)
+    filt = mg.filter_radial(table, np.sqrt(3))
+    alphas = [ctx.estimate_step(filt, level=g, iters=30, seed=0) for g in range(cfg.levels - 1)]
+    truth = torch.from_numpy(d["mu"].astype(np.float32)).cuda()
+    mask = torch.from_numpy(synth.evaluation_mask(n, cfg.h)).cuda()
+    tm = truth[mask].double()
+
+    def err(v):
+        return float(torch.linalg.vector_norm(v[mask].double() - tm) / torch.linalg.vector_norm(tm))
+
+    rows = []
+    for lam in (0.0, 1e-3, 1e-2):
+        for bil in (None, (1.0, 0.05)):
+            e = {}
+            for it in (1, 2, 4, 10):
+                v = torch.zeros((n, n, n), device="cuda")
+                ctx.multigrid_solve(v, b, cfg.levels, it, filt, alphas=alphas, lam=lam, bilateral=bil,
+                                    want_hist=False)
+                e[it] = err(v)
+            rows.append({"lambda": lam, "bilateral": list(bil) if bil else None, "masked_error": e})
+    vo = torch.zeros((n, n, n), device="cuda")
+    os_err = {}
+    for k in range(1, 11):
+        ctx.osemtr(vo, b, subsets=8, passes=1, level=0)
+        if k in (2, 4, 10):
+            os_err[k] = err(vo)
+    ctx.close()
+    print(json.dumps({"quality_sweep": {"workload": WORKLOAD_NAMES["c1"], "algorithm1": rows,
+                                        "osemtr_8_subsets": os_err}}), flush=True)
 
 
 def quality(ctx, mg, b, d, step, levels, filt, alphas, lam, bil, args):
