@@ -206,6 +206,9 @@ def main():
     if not args.no_quality:
         out["time_to_residual"] = time_to_residual(ctx, mg, synth, ph, b, cfg, levels, filt, alphas, lam, bil,
                                                    args.sirt_cap)
+        if os.path.exists(lrn.DEFAULT_WEIGHTS):
+            # the learned preconditioner's network alone on this grid (what its step adds)
+            out["cnn_forward"] = time_cnn_forward(ctx, n, 5, 1)
         if wl != "c1":
             ctx.close()
             del b, vol
@@ -706,11 +709,16 @@ def cnn_forward_timing(n, steps, warmup):
     """The network's forward pass alone on an n^3 grid (trained weights; a
     seeded random input), timed with HIP events on the library's stream,
     priced against the dense BF16 matrix-core peak."""
+    import paper_2103_10329_amd as mg
+    ctx = mg.Context(0)
+    print(json.dumps({"cnn_forward": time_cnn_forward(ctx, n, steps, warmup)}), flush=True)
+    ctx.close()
+
+
+def time_cnn_forward(ctx, n, steps, warmup):
     import torch
 
-    import paper_2103_10329_amd as mg
     from paper_2103_10329_amd import learned as lrn
-    ctx = mg.Context(0)
     ctx.cnn_set_weights(lrn.load_weights())
     gen = torch.Generator(device="cuda").manual_seed(3)
     u = torch.randn((n, n, n), device="cuda", generator=gen) * 1e-3
@@ -726,9 +734,10 @@ def cnn_forward_timing(n, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     tflops = CNN_FLOPS_PER_VOXEL * n ** 3 / (ms * 1e-3) / 1e12
-    print(json.dumps({"cnn_forward": {"n": n, "ms": ms, "steps": steps, "tflops": tflops,
-                                      "frac_bf16_dense_peak": tflops / 2500.0,
-                                      "flops_per_voxel": CNN_FLOPS_PER_VOXEL}}), flush=True)
+    del u, out
+    torch.cuda.empty_cache()
+    return {"n": n, "ms": ms, "steps": steps, "tflops": tflops, "frac_bf16_dense_peak": tflops / 2500.0,
+            "flops_per_voxel": CNN_FLOPS_PER_VOXEL}
 
 
 def copy_calibration(size_mib=1024, reps=5):
