@@ -709,10 +709,11 @@ constexpr int kConvRing = 4;
 #ifndef MGCT_CONV32_PAD
 #define MGCT_CONV32_PAD 0
 #endif
-template <int CI, int NW = 4> struct ConvLds {
+template <int CI, int NW = 4, int XW = 34> struct ConvLds {
     static constexpr int C = CI / 8;                                  // 16-byte chunks per voxel
     static constexpr int CP = CI == 32 && MGCT_CONV32_PAD ? C + 1 : C;  // chunk slots per voxel in LDS
-    static constexpr int P = 6 * 34 * CP;                             // chunk slots of one staged row
+    static constexpr int X = XW;                                      // staged voxels per z row
+    static constexpr int P = 6 * XW * CP;                             // chunk slots of one staged row
     static constexpr int L = (P + 64 * NW - 1) / (64 * NW);           // transfers per wave per row (NW waves)
     static constexpr int SLOT = L * 64 * NW;                          // chunks per ring slot (padded)
 };
@@ -778,17 +779,17 @@ __device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
 // This lane's source element offsets for the transfers of one staged row at
 // row 0 of the item's tile (the row yi adds yi nx CI), -1 where the position
 // is padding or its voxel lies outside the volume in x or z.
-template <int CI, int NW = 4> struct ConvDmaOff {
-    long off[ConvLds<CI, NW>::L];
+template <int CI, int NW = 4, int XW = 34> struct ConvDmaOff {
+    long off[ConvLds<CI, NW, XW>::L];
 };
-template <int CI, int NW = 4>
-__device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI, NW> &O, const Dims &d, int x0, int z0, int w,
+template <int CI, int NW = 4, int XW = 34>
+__device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI, NW, XW> &O, const Dims &d, int x0, int z0, int w,
                                               int lane) {
-    using G = ConvLds<CI, NW>;
+    using G = ConvLds<CI, NW, XW>;
 #pragma unroll
     for (int i = 0; i < G::L; ++i) {
         const int k = i * NW + w, p = k * 64 + lane;
-        const int zi = p / (34 * G::CP), xi = (p / G::CP) % 34, qs = p % G::CP;
+        const int zi = p / (XW * G::CP), xi = (p / G::CP) % XW, qs = p % G::CP;
         const int q = conv_perm<CI, NW>(xi, qs);  // the chunk that slot holds
         const int zz = z0 - 1 + zi, xx = x0 - 1 + xi;
         const bool ok = p < G::P && q < G::C && zz >= 0 && zz < d.nz && xx >= 0 && xx < d.nx;
@@ -796,10 +797,10 @@ __device__ __forceinline__ void conv_dma_prep(ConvDmaOff<CI, NW> &O, const Dims 
     }
 }
 
-template <int CI, int NW = 4>
+template <int CI, int NW = 4, int XW = 34>
 __device__ __forceinline__ void conv_dma_row(uint32_t slot, const uint16_t *__restrict__ X,
-                                             const ConvDmaOff<CI, NW> &O, const Dims &d, int yi, int w) {
-    using G = ConvLds<CI, NW>;
+                                             const ConvDmaOff<CI, NW, XW> &O, const Dims &d, int yi, int w) {
+    using G = ConvLds<CI, NW, XW>;
     const bool yok = yi >= 0 && yi < d.ny;  // wave-uniform
     const long yoff = (long)yi * d.nx * CI;
 #pragma unroll
@@ -1224,12 +1225,127 @@ __global__ __launch_bounds__(256) void k_conv4_ym(const uint16_t *__restrict__ h
     }
 }
 
+// Layer 4 on large grids with its input rows staged like layers 2 and 3
+// (k_conv_lds: a 4-slot LDS ring filled by global-to-LDS transfers three
+// rows ahead, one barrier per row): a block takes 30 output x (x0 .. x0 + 29,
+// tiles at stride 30; the ring holds the 32 voxels x0 - 1 .. x0 + 30 of the
+// 6 z rows z0 - 1 .. z0 + 4) and 4 consecutive z, one wave per z.  Per input
+// row a wave forms the tap products E of k_conv4_ym from the ring's fragments,
+// gathers them for its 30 outputs and stores the output row this input row
+// completes.  The wait before a row leaves the two later rows' transfers
+// outstanding (it also waits for the few output loads and stores issued
+// between them, which vector memory completes in order).
+using Conv4Lds = ConvLds<32, 4, 32>;
+
+__device__ __forceinline__ void conv4_lds_row(const uint16_t (&slot)[Conv4Lds::SLOT * 8], const bf16x8 (&Bf)[2][3][2],
+                                              int wv, int m, int kh, bool gather, float *Ew, float &oP, float &o0,
+                                              float &oN) {
+    floatx16 acc{};
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+            const bf16x8 a =
+                *reinterpret_cast<const bf16x8 *>(slot + ((wv + dz) * Conv4Lds::X * 4 + conv_slot<32>(m, kc * 2 + kh)) * 8);
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, Bf[hl][dz][kc], acc, 0, 0, 0);
+        }
+    if (m < 9) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Ew[(8 * (r >> 2) + 4 * kh + (r & 3)) * 9 + m] = acc[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (gather) {
+        // slot j = 3 (dy + 1) + dx + 1 of staged input m + 1 + dx
+        const float *e = Ew + (m + 1) * 9;
+        oN += e[-9 + 0] + e[1] + e[9 + 2];  // dy = -1 -> output row yi + 1
+        o0 += e[-9 + 3] + e[4] + e[9 + 5];  // dy = 0
+        oP += e[-9 + 6] + e[7] + e[9 + 8];  // dy = +1 -> output row yi - 1
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(256) void k_conv4_lds(const uint16_t *__restrict__ h3, const uint16_t *__restrict__ P4,
+                                                   const float *__restrict__ w, const float *__restrict__ u,
+                                                   float *__restrict__ out, Dims d, int n_items) {
+    using G = Conv4Lds;
+    __shared__ __align__(16) uint16_t ring0[G::SLOT * 8], ring1[G::SLOT * 8], ring2[G::SLOT * 8],
+        ring3[G::SLOT * 8];
+    __shared__ float E[4][32 * 9];
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = lane & 31, kh = lane >> 5;
+    const uint32_t l0 = (uint32_t)(uintptr_t)ring0, l1 = (uint32_t)(uintptr_t)ring1,
+                   l2 = (uint32_t)(uintptr_t)ring2, l3 = (uint32_t)(uintptr_t)ring3;
+    bf16x8 Bf[2][3][2];
+#pragma unroll
+    for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc)
+                Bf[hl][dz][kc] =
+                    *reinterpret_cast<const bf16x8 *>(P4 + ((((hl * 3 + dz) * 2 + kc) * 32 + m) * 16 + kh * 8));
+    const float b4 = w[kB4];
+    wait_vm<0>();  // weights in registers before the first transfer
+    float *Ew = E[wv];
+    const int ntile = (d.nx + 29) / 30;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // block-uniform
+        const int x0 = (it % ntile) * 30, z0 = (it / ntile) * 4, z = z0 + wv;
+        const bool live = z < d.nz;  // a wave past the grid still moves data and meets the barriers
+        const int xo = x0 + m;       // this lane's output x (lanes m < 30, kh = 0)
+        const bool gather = kh == 0 && m < 30 && xo < d.nx;
+        float oP = 0.f, o0 = 0.f, oN = 0.f;  // output rows yi - 1, yi, yi + 1
+        ConvDmaOff<32, 4, 32> O;
+        conv_dma_prep<32, 4, 32>(O, d, x0, z0, wv, lane);
+        __syncthreads();  // the previous item's reads of the ring are done
+        conv_dma_row<32, 4, 32>(l0, h3, O, d, -1, wv);
+        conv_dma_row<32, 4, 32>(l1, h3, O, d, 0, wv);
+        conv_dma_row<32, 4, 32>(l2, h3, O, d, 1, wv);
+        // step YI: input row YI from slot RS, row YI + 3 into slot RN; stores
+        // the completed output row YI - 1
+#define MGCT_CONV4_STEP(RS, RN, YI)                                                                              \
+    {                                                                                                            \
+        wait_vm<2 * G::L>();                                                                                     \
+        __syncthreads();                                                                                         \
+        conv_dma_row<32, 4, 32>(RN, h3, O, d, (YI) + 3, wv);                                                     \
+        if (live) {                                                                                              \
+            conv4_lds_row(RS, Bf, wv, m, kh, gather, Ew, oP, o0, oN);                                            \
+            if (gather && (YI) >= 1) {                                                                           \
+                const long v = ((long)z * d.ny + ((YI) - 1)) * d.nx + xo;                                        \
+                out[v] = u[v] + (oP + b4);                                                                       \
+            }                                                                                                    \
+            oP = o0;                                                                                             \
+            o0 = oN;                                                                                             \
+            oN = 0.f;                                                                                            \
+        }                                                                                                        \
+    }
+        MGCT_CONV4_STEP(ring0, l3, -1)
+        for (int yi = 0; yi <= d.ny; yi += 4) {
+            MGCT_CONV4_STEP(ring1, l0, yi)
+            if (yi + 1 > d.ny) break;
+            MGCT_CONV4_STEP(ring2, l1, yi + 1)
+            if (yi + 2 > d.ny) break;
+            MGCT_CONV4_STEP(ring3, l2, yi + 2)
+            if (yi + 3 > d.ny) break;
+            MGCT_CONV4_STEP(ring0, l3, yi + 3)
+        }
+#undef MGCT_CONV4_STEP
+        wait_vm<0>();  // no transfer into the ring stays in flight past the item
+    }
+}
+
 #ifndef MGCT_CONV_LDS
 #define MGCT_CONV_LDS 1
 #endif
 // launch of either convolution kernel
 #ifndef MGCT_CONV_DMA
 #define MGCT_CONV_DMA 1  // large-grid forward: input rows staged in LDS by global-to-LDS loads
+#endif
+#ifndef MGCT_CONV4_LDS
+#define MGCT_CONV4_LDS 1  // layer 4 on large grids from the LDS ring
+#endif
+#ifndef MGCT_CONV4_LDS_BLOCKS
+#define MGCT_CONV4_LDS_BLOCKS 3  // persistent blocks per CU
 #endif
 #ifndef MGCT_CONV32_HW
 #define MGCT_CONV32_HW 1  // the 32-channel layer on large grids: eight waves, half the channels each
@@ -1415,7 +1531,19 @@ hipError_t cnn_forward(CnnState &S, const CnnBuffers &B, const float *u, float *
     k_conv1_mfma<<<blocks((long)ny * nz, 4), 256, 0, s>>>(B.up, S.p1, S.master, keep ? B.z1 : nullptr, B.h1, d);
     launch_conv<16, 0>(B.h1, S.p2f, S.master + kB2, nullptr, keep ? B.z2 : nullptr, B.h2, 32, d, s);
     launch_conv<32, 0>(B.h2, S.p3f, S.master + kB3, nullptr, keep ? B.z3 : nullptr, B.h3, 32, d, s);
-    if (n >= MGCT_CONV_YM_MIN_VOX)
+    if (n >= MGCT_CONV_YM_MIN_VOX && MGCT_CONV4_LDS) {
+        static int n_cu4 = 0;
+        if (!n_cu4) {
+            int dev = 0;
+            hipDeviceProp_t prop;
+            n_cu4 = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                        ? prop.multiProcessorCount
+                        : 256;
+        }
+        const int n_items = ((nx + 29) / 30) * ((nz + 3) / 4);
+        k_conv4_lds<<<(unsigned)std::min(n_items, MGCT_CONV4_LDS_BLOCKS * n_cu4), 256, 0, s>>>(B.h3, S.p4, S.master,
+                                                                                               u, out, d, n_items);
+    } else if (n >= MGCT_CONV_YM_MIN_VOX)
         k_conv4_ym<kConv4Zw><<<(unsigned)(((nx + 29) / 30) * ((nz + 4 * kConv4Zw - 1) / (4 * kConv4Zw))), 256, 0, s>>>(
             B.h3, S.p4, S.master, u, out, d);
     else
