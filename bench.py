@@ -767,7 +767,18 @@ def cpu_baseline(cfg, views, n_sub=8):
     oracle.backproject(g, p)
     t2 = time.perf_counter()
     t = t2 - t0
-    return {"value": n ** 3 * len(sub) / t / 1e9, "unit": "Gvoxel·views/s", "cores": oracle.num_threads(),
+    # the same on one host thread, one view
+    cores = oracle.num_threads()
+    g1 = oracle.Geom(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, np.ascontiguousarray(sub[:1]))
+    oracle.set_num_threads(1)
+    t3 = time.perf_counter()
+    p1 = oracle.project(g1, x)
+    oracle.backproject(g1, p1)
+    t4 = time.perf_counter()
+    oracle.set_num_threads(cores)
+    one = {"value": n ** 3 / (t4 - t3) / 1e9, "seconds": t4 - t3, "threads": 1,
+           "sample": "one A and one A^T of the FP64 oracle on 1 view (the first of the sample)"}
+    return {"value": n ** 3 * len(sub) / t / 1e9, "unit": "Gvoxel·views/s", "cores": cores, "one_thread": one,
             "kind": "oracle", "seconds": t, "A_s": t1 - t0, "At_s": t2 - t1,
             "sample": "one A and one A^T of the FP64 oracle on %d of the %d views (evenly spaced) of the %d^3, "
                       "%dx%d-detector geometry, seeded random volume" % (len(sub), len(views), n, cfg.nv, cfg.nu),

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "Geom", "build", "project", "backproject", "project_rays", "backproject_voxels",
-    "weight", "dense_matrix", "major_axis", "num_threads", "project_geom_grad",
+    "weight", "dense_matrix", "major_axis", "num_threads", "set_num_threads", "project_geom_grad",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -62,6 +62,8 @@ def _load():
         lib.oracle_major_axis.restype = ci
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ci
+        lib.oracle_set_num_threads.argtypes = [ci]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -199,3 +201,9 @@ def major_axis(D) -> int:
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the following oracle calls (timing only; A^T's partial
+    volumes are summed in a different grouping, a rounding-level change)."""
+    _load().oracle_set_num_threads(int(n))

@@ -406,3 +406,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following calls (a timing aid; A^T's partial volumes are then summed in a
+ * different grouping, so its result changes by rounding only). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
