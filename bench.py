@@ -64,6 +64,10 @@ def main():
     ap.add_argument("--quality-sweep", action="store_true",
                     help="only run the 128^3 image-error sweep over the regularisation readings and iteration "
                          "counts of Algorithm 1 (prints its own JSON line)")
+    ap.add_argument("--oracle-solves", action="store_true",
+                    help="only time whole solves of the FP64 oracle on all host threads beside the library: 20 SIRT "
+                         "iterations on the 32^3 workload, 2 iterations of Algorithm 1 on the 128^3 one "
+                         "(prints its own JSON line)")
     ap.add_argument("--cnn-forward", type=int, metavar="N",
                     help="only time the learned preconditioner's forward pass on an N^3 grid, --warmup untimed "
                          "and --steps timed passes (prints its own JSON line)")
@@ -84,6 +88,9 @@ def main():
         return
     if args.quality_sweep:
         quality_sweep()
+        return
+    if args.oracle_solves:
+        oracle_solves()
         return
 
     import torch
@@ -749,6 +756,67 @@ def copy_calibration(size_mib=1024, reps=5):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": size_mib << 20, "reps": reps}), flush=True)
+
+
+def oracle_solves():
+    """Whole solves of the FP64 oracle, as it stands, on all host threads,
+    beside the library's on the same data (the library's step sizes for
+    both): 20 SIRT iterations (eq. 2) on the 32^3 workload, and 2 iterations
+    of Algorithm 1 (3 grids, radial filter, no regularisers) on the 128^3 one.
+    Reports both wall times and the relative L2 difference of the results."""
+    import torch
+
+    import oracle
+    import paper_2103_10329_amd as mg
+    import synth
+    out = {"cores": oracle.num_threads(), "cpu_model": _cpu_model()}
+    for wl, kind in (("c0", "sirt"), ("c1", "pmg")):
+        cfg = synth.CONFIGS[wl]
+        n = cfg.n
+        d = synth.make_dataset(wl, truth=False)
+        ctx = mg.Context(0)
+        ctx.set_geometry(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, d["views"])
+        g = oracle.Geom(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, np.ascontiguousarray(d["views"]))
+        b64 = np.asarray(d["b"], dtype=np.float64)
+        b = torch.from_numpy(b64.astype(np.float32)).cuda()
+        v = torch.zeros((n, n, n), device="cuda")
+        if kind == "sirt":
+            iters = 20
+            alpha = ctx.estimate_step(None, level=0, iters=30, seed=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                ctx.landweber_step(v, b, alpha, None, want_norm=False)
+            torch.cuda.synchronize()
+            t_gpu = time.perf_counter() - t0
+            x = np.zeros((n, n, n))
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                x, _ = oracle.landweber_step(g, x, b64, alpha, None)
+            t_cpu = time.perf_counter() - t0
+            what = "%d SIRT iterations" % iters
+        else:
+            levels = cfg.levels
+            table = np.maximum(np.linspace(0, np.sqrt(3), 4097), 2.0 / n)
+            filt = mg.filter_radial(table, np.sqrt(3))
+            alphas = [ctx.estimate_step(filt, level=k, iters=30, seed=0) for k in range(levels - 1)]
+            ctx.multigrid_solve(v, b, levels, 2, filt, alphas=alphas, want_hist=False)  # warm-up
+            v.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.multigrid_solve(v, b, levels, 2, filt, alphas=alphas, want_hist=False)
+            torch.cuda.synchronize()
+            t_gpu = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            x, _ = oracle.multigrid(g, np.zeros((n, n, n)), b64, levels, 2, oracle.filter_radial(table, np.sqrt(3)),
+                                    alphas)
+            t_cpu = time.perf_counter() - t0
+            what = "2 iterations of Algorithm 1 on %d grids" % levels
+        vh = v.double().cpu().numpy()
+        out[wl] = {"solve": what, "oracle_s": t_cpu, "library_s": t_gpu, "ratio": t_cpu / t_gpu,
+                   "rel_l2_difference": float(np.linalg.norm(vh - x) / np.linalg.norm(x))}
+        ctx.close()
+    print(json.dumps({"oracle_solves": out}), flush=True)
 
 
 def cpu_baseline(cfg, views, n_sub=8):
