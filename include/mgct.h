@@ -368,6 +368,24 @@ int mgct_cnn_gradients(void *ctx, int nx, int ny, int nz, const float *u, const 
 /* forward + backward + one Adam step (beta 0.9/0.999, eps 1e-8) of learning rate lr */
 int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const float *target, double lr,
                         double *loss, hipStream_t stream);
+/*
+ * The network's backward pass for a loss the caller defines: grads (host,
+ * MGCT_CNN_PARAMS values, in the weight vector's layout) = the gradient of
+ * sum over voxels of dout * out with respect to the parameters, at input u
+ * (device F32 [nz][ny][nx]); dout (device F32, same shape) is d loss / d out.
+ * The activations of u are recomputed first.  Synchronises the stream.
+ */
+int mgct_cnn_backward(void *ctx, int nx, int ny, int nz, const float *u, const float *dout, float *grads,
+                      hipStream_t stream);
+/*
+ * One Adam step (Kingma & Ba, beta 0.9/0.999, eps 1e-8, bias-corrected;
+ * the same update as mgct_cnn_train_step's) of learning rate lr on the
+ * context's master weights with caller-supplied gradients (host,
+ * n = MGCT_CNN_PARAMS values); advances the context's Adam state and
+ * re-derives the BF16 operands.  MGCT_ERR_INVALID_ARG without weights set.
+ * Synchronises the stream.
+ */
+int mgct_adam_step(void *ctx, const float *grads, int n, double lr, hipStream_t stream);
 
 /*
  * Learned-step statistics since the last call: finest-grid steps whose

@@ -102,6 +102,8 @@ SIGNATURES = {
     "mgct_cnn_forward": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _vp]),
     "mgct_cnn_gradients": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.POINTER(ctypes.c_float), _dp, _vp]),
     "mgct_cnn_train_step": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, _cd, _dp, _vp]),
+    "mgct_cnn_backward": (_ci, [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp]),
+    "mgct_adam_step": (_ci, [_vp, ctypes.POINTER(ctypes.c_float), _ci, _cd, _vp]),
     "mgct_learned_stats": (_ci, [_vp, ctypes.POINTER(_ci), ctypes.POINTER(_ci)]),
     "mgct_synth_line_integrals": (_ci, [_vp, _dp, _ci, _dp, _ci, _vp, _vp]),
     "mgct_synth_voxelize": (_ci, [_vp, _dp, _ci, _dp, _ci, _ci, _vp, _vp]),
@@ -433,6 +435,20 @@ class Context:
                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss), _stream()),
               "mgct_cnn_gradients")
         return g, loss.value
+
+    def cnn_backward(self, u, dout):
+        """Parameter gradients of sum(dout * f-network output) at input u (device tensors)."""
+        nz, ny, nx = u.shape
+        g = np.zeros(self.CNN_PARAMS, dtype=np.float32)
+        check(mgct_cnn_backward(self.handle, nx, ny, nz, _ptr(u), _ptr(dout),  # noqa: F821
+                                g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()), "mgct_cnn_backward")
+        return g
+
+    def adam_step(self, grads, lr):
+        """One Adam step of the context's weights with the given gradients (host array)."""
+        g = np.ascontiguousarray(np.asarray(grads, dtype=np.float32).reshape(-1))
+        check(mgct_adam_step(self.handle, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), g.size,  # noqa: F821
+                             float(lr), _stream()), "mgct_adam_step")
 
     def cnn_train_step(self, u, target, lr, want_loss=True):
         nz, ny, nx = u.shape

@@ -749,6 +749,37 @@ int mgct_cnn_gradients(void *ctx, int nx, int ny, int nz, const float *u, const 
     return MGCT_OK;
 }
 
+int mgct_cnn_backward(void *ctx, int nx, int ny, int nz, const float *u, const float *dout, float *grads,
+                      hipStream_t s) {
+    if (!ctx || !u || !dout || !grads) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    MGCHK(cnn_check(c, nx, ny, nz));
+    const long n = (long)nx * ny * nz;
+    CnnBuffers B;
+    MGCHK(cnn_buffers(c, nx, ny, nz, true, B));
+    MGCHK(cnn_train_scratch(c, nx, ny, nz, B));
+    WS(out, float, "cnn_out", n * 4, false);
+    // the activations of u (recomputed), then the backward pass from dout
+    HIPCHK(cnn_forward(c.cnn, B, u, out, nx, ny, nz, true, s));
+    HIPCHK(hipMemcpyAsync(B.dout, dout, n * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(cnn_backward(c.cnn, B, u, out, nullptr, c.cnn.grads, nullptr, 0, nx, ny, nz, s));
+    HIPCHK(hipMemcpyAsync(grads, c.cnn.grads, kCnnParams * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MGCT_OK;
+}
+
+int mgct_adam_step(void *ctx, const float *grads, int n, double lr, hipStream_t s) {
+    if (!ctx || !grads || n != kCnnParams || !(lr > 0.0)) return MGCT_ERR_INVALID_ARG;
+    Ctx &c = *as_ctx(ctx);
+    HIPCHK(hipSetDevice(c.device));
+    if (!c.cnn.ready) return MGCT_ERR_INVALID_ARG;
+    HIPCHK(hipMemcpyAsync(c.cnn.grads, grads, kCnnParams * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(cnn_adam(c.cnn, c.cnn.grads, (float)lr, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MGCT_OK;
+}
+
 int mgct_cnn_train_step(void *ctx, int nx, int ny, int nz, const float *u, const float *target, double lr,
                         double *loss, hipStream_t s) {
     if (!ctx || !u || !target || !(lr > 0.0)) return MGCT_ERR_INVALID_ARG;

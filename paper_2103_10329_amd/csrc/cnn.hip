@@ -1557,7 +1557,9 @@ hipError_t cnn_backward(CnnState &S, const CnnBuffers &B, const float *u, const 
     const Dims d{nx, ny, nz};
     const long n = (long)nx * ny * nz;
     const unsigned vb = blocks(n);
-    k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
+    // dout = d loss / d out: from the mean squared error against target, or
+    // (target NULL) already in B.dout
+    if (target) k_mse<<<n_loss_blocks, 256, 0, s>>>(out, target, B.dout, loss_partials, n);
     // layer 4
     // bias gradients: blocks of 512 voxels (at most 4096 blocks), then a wave per channel
     const long vchunk = std::max(512L, (n + 4095) / 4096);

@@ -61,6 +61,8 @@ def test_null_arguments_are_rejected(lib):
     assert mg.mgct_destroy(None) == mg.MGCT_ERR_INVALID_ARG
     assert mg.mgct_project(None, 0, None, 0, None, 0, None) == mg.MGCT_ERR_INVALID_ARG
     assert mg.mgct_filter_eq5(None) == mg.MGCT_ERR_INVALID_ARG
+    assert mg.mgct_cnn_backward(None, 32, 1, 1, None, None, None, None) == mg.MGCT_ERR_INVALID_ARG
+    assert mg.mgct_adam_step(None, None, 0, 1e-3, None) == mg.MGCT_ERR_INVALID_ARG
 
 
 def test_create_without_device_fails_cleanly(lib):
