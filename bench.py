@@ -68,6 +68,10 @@ def main():
                     help="only time whole solves of the FP64 oracle on all host threads beside the library: 20 SIRT "
                          "iterations on the 32^3 workload, 2 iterations of Algorithm 1 on the 128^3 one "
                          "(prints its own JSON line)")
+    ap.add_argument("--view-share", type=int, metavar="K",
+                    help="only time A and A^T on each share of a round-robin split of the 512^3 workload's views "
+                         "into K (what one of K GPUs would run), check that the shares compose to the whole, and "
+                         "model the sum exchange (prints its own JSON line)")
     ap.add_argument("--cnn-forward", type=int, metavar="N",
                     help="only time the learned preconditioner's forward pass on an N^3 grid, --warmup untimed "
                          "and --steps timed passes (prints its own JSON line)")
@@ -85,6 +89,9 @@ def main():
         return
     if args.cnn_forward:
         cnn_forward_timing(args.cnn_forward, args.steps, args.warmup)
+        return
+    if args.view_share:
+        view_share(args.view_share, args.steps)
         return
     if args.quality_sweep:
         quality_sweep()
@@ -679,6 +686,76 @@ def paper_shaped():
     out["pmg_iterations"] = iters
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def view_share(k, steps):
+    """One GPU's part of a K-GPU view sharding of the 512^3 / 1440-view
+    workload, FP32: views r, r + K, r + 2K, ... go to GPU r.  For every share
+    r the fine-grid A and A^T are timed (HIP events, `steps` launches each
+    after one untimed launch) on a context holding only that share's views;
+    the share's A must equal the matching rows of the full A bit for bit and
+    the shares' A^T must add up to the full A^T.  A K-GPU step would then take
+    the slowest share's A + A^T plus one sum exchange of the A^T partial
+    volumes, modelled as a ring all-reduce over xGMI (one 153 GB/s link per
+    direction: 2 (K - 1)/K x volume bytes / 153 GB/s), without overlap."""
+    import torch
+
+    import paper_2103_10329_amd as mg
+    import synth
+    cfg = synth.CONFIGS["c2"]
+    n, V = cfg.n, cfg.n_views
+    views = synth.trajectory(V, cfg.z_levels, cfg.pixel)
+    gen = torch.Generator(device="cuda").manual_seed(31)
+    x = torch.rand((n, n, n), device="cuda", generator=gen)
+    y = torch.rand((V, cfg.nv, cfg.nu), device="cuda", generator=gen)
+    full = mg.Context(0)
+    full.set_geometry(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views)
+    a_full = full.project(x)
+    b_full = full.backproject(y)
+    full.kernel_timing(True, ops=(mg.MGCT_OP_PROJECT, mg.MGCT_OP_BACKPROJECT), levels=(0,))
+    for _ in range(steps):
+        full.project(x, out=a_full)
+        full.backproject(y, out=b_full)
+    torch.cuda.synchronize()
+    full.kernel_timing(False)
+    tA_full = full.kernel_time(mg.MGCT_OP_PROJECT, 0)
+    tB_full = full.kernel_time(mg.MGCT_OP_BACKPROJECT, 0)
+    full.close()
+    acc = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    shares, identical = [], True
+    for r in range(k):
+        c = mg.Context(0)
+        c.set_geometry(n, n, n, cfg.h, (0, 0, 0), cfg.nu, cfg.nv, views[r::k])
+        yr = y[r::k].contiguous()
+        p = c.project(x)
+        q = c.backproject(yr)
+        torch.cuda.synchronize()
+        identical &= bool(torch.equal(p, a_full[r::k]))
+        acc += q.double()
+        c.kernel_timing(True, ops=(mg.MGCT_OP_PROJECT, mg.MGCT_OP_BACKPROJECT), levels=(0,))
+        for _ in range(steps):
+            c.project(x, out=p)
+            c.backproject(yr, out=q)
+        torch.cuda.synchronize()
+        c.kernel_timing(False)
+        tA = c.kernel_time(mg.MGCT_OP_PROJECT, 0)
+        tB = c.kernel_time(mg.MGCT_OP_BACKPROJECT, 0)
+        shares.append({"views": len(views[r::k]), "A_ms": tA[0] / tA[1], "At_ms": tB[0] / tB[1]})
+        log("view share", r, shares[-1])
+        c.close()
+        del p, q, yr
+    err = float(torch.linalg.vector_norm(acc - b_full.double()) / torch.linalg.vector_norm(b_full.double()))
+    vol_bytes = n ** 3 * 4
+    allreduce_ms = 2.0 * (k - 1) / k * vol_bytes / 153e9 * 1e3
+    slowest = max(s["A_ms"] + s["At_ms"] for s in shares)
+    full_ms = tA_full[0] / tA_full[1] + tB_full[0] / tB_full[1]
+    out = {"workload": "pmg-512^3-1440x768^2 view shares, FP32", "shares": k, "share_kernels": shares,
+           "one_gpu_a_plus_at_ms": full_ms, "share_A_rows_identical": identical,
+           "sum_of_share_At_rel_l2": err, "partial_volume_bytes": vol_bytes,
+           "ring_allreduce_ms_model": allreduce_ms, "slowest_share_a_plus_at_ms": slowest,
+           "k_gpu_a_plus_at_ms_model": slowest + allreduce_ms,
+           "k_gpu_speedup_model": full_ms / (slowest + allreduce_ms)}
+    print(json.dumps(out), flush=True)
 
 
 def in_cone_fraction(views, nx, ny, nz, h, nu, nv, sub=4, chunk=8):
