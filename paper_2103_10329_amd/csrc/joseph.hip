@@ -1755,6 +1755,7 @@ struct __align__(16) PlCol {
     float whi;     // in-plane hat weight of the upper row
     int rl;        // block row of the lower tap (-1 .. kPlRows-1)
     uint32_t off;  // element offset of the column's first detector row in the stack
+    int r0;        // w.R0 as an integer
 };
 
 // Column records per batch and the waves per SIMD the registers must allow,
@@ -1818,9 +1819,12 @@ template <int KZ, int NP> struct BpFetch {
 template <int KZ, int NP, typename PT>
 __device__ __forceinline__ void bp_fetch(BpFetch<KZ, NP> &F, const PlCol *rec, int l, const PT *pt0,
                                          const PT *pt1, int nv, const float (&u)[KZ]) {
+    // the record is the same in every lane: the column's address and the
+    // window test go to scalar registers, the slot row stays a vector value
+    // (one lane read fewer); the window's first row as an integer sum
     PlCol R = rec[l];
     const uint32_t off = __builtin_amdgcn_readfirstlane(R.off);
-    F.rl = __builtin_amdgcn_readfirstlane(R.rl);
+    F.rl = R.rl;
     F.l = l;
     R.w.rtz = uniform_f(R.w.rtz);
     F.w4 = fabsf(R.w.rtz) < 2.f;
@@ -1831,7 +1835,7 @@ __device__ __forceinline__ void bp_fetch(BpFetch<KZ, NP> &F, const PlCol *rec, i
     for (int q = 0; q < KZ; ++q) {
         float dl;
         win_start(R.w, u[q], hi, dl, F.d0[q]);
-        const uint32_t bs = (uint32_t)(int)(dl + R.w.R0);
+        const uint32_t bs = (uint32_t)((int)dl + R.r0);  // dl is an integer
         load_win<4>(pt0 + off, bs, F.v[0][q]);
         if (NP > 1) load_win<4>(pt1 + off, bs, F.v[NP - 1][q]);
     }
@@ -1956,6 +1960,7 @@ __device__ __forceinline__ void bp_plane_group(const SepView *__restrict__ sep, 
             PlCol R;
             R.rl = (int)fl - r0;
             R.w = win_col(zc, tz, (PART == 0 ? C.dxv : C.dyv) / dm, zw0);
+            R.r0 = (int)R.w.R0;
             R.whi = (float)(pos - fl);
             R.off = (uint32_t)(((long)vl * nu + a) * nv);
             ok = C.axis == PART && tau >= 0.0 && tau <= 1.0 && R.rl >= -1 && R.rl < kPlRows;
