@@ -243,14 +243,14 @@ def main():
 # Algorithm 1 step: A with the residual epilogue, A^T from the FP32 stack).
 TRAFFIC = {
     ("k_project_lds", "c2"): {
-        "source_sha256": "2f268a90928639eef4f04a176298c56c8c75ac7e58590eb5ae23e76ce5815f83",
+        "source_sha256": "406188f30e88d0bd7c61982b100bcdc435ecdff2f354cafe3be849eccf83db63",
         "bytes_per_launch": 1.447e12, "fetch_kib": 6.818e8, "write_kib": 4.927e7,
-        "valu_issue": 0.777, "lds_issue": 0.104, "l2_hit": 0.125, "valu_insts_per_voxel_view": 35.4,
+        "valu_issue": 0.774, "lds_issue": 0.104, "l2_hit": 0.125, "valu_insts_per_voxel_view": 35.4,
         "profile": "profiles/project_backproject_512cube_1440x768_counters.md"},
     ("k_backproject_pl", "c2"): {
-        "source_sha256": "2f268a90928639eef4f04a176298c56c8c75ac7e58590eb5ae23e76ce5815f83",
-        "bytes_per_launch": 5.18e11, "fetch_kib": 2.462e8, "write_kib": 1.348e7,
-        "valu_issue": 0.915, "lds_issue": 0.118, "l2_hit": 0.115, "valu_insts_per_voxel_view": 37.8,
+        "source_sha256": "406188f30e88d0bd7c61982b100bcdc435ecdff2f354cafe3be849eccf83db63",
+        "bytes_per_launch": 4.983e11, "fetch_kib": 2.424e8, "write_kib": 1.765e6,
+        "valu_issue": 0.877, "lds_issue": 0.119, "l2_hit": 0.077, "valu_insts_per_voxel_view": 35.8,
         "profile": "profiles/project_backproject_512cube_1440x768_counters.md"},
 }
 
