@@ -2,7 +2,7 @@
 // 3-D DFT sized to the grid (circular convolution), for power-of-two edges.
 //
 // Five passes over the volume, each batching whole lines of one axis in LDS
-// (radix-2/4 Stockham, ping-pong buffers, up to 2048 complex values per block,
+// (radix-2/4 Stockham, ping-pong buffers, up to 2048 complex values per block (1024 along x),
 // fewer when that keeps at least 2048 blocks in flight):
 //   1. along x: real input -> complex work array (forward)
 //   2. along y: forward
@@ -21,7 +21,10 @@
 
 namespace mgct {
 
-constexpr int kFftElems = 2048;  // complex values per block (4096: 512^3 filter 8.66 ms, 2048: 7.16, 1024: 8.54)
+// complex values per block: on the strided axes (blocks of 4 lines of 512: 32-byte runs), and on the contiguous
+// x axis (512^3 filter: 8.66 ms with 4096 / 4096, 7.16 with 2048 / 2048, 8.54 with 1024 / 1024, 6.66 with 2048 / 1024)
+constexpr int kFftElems = 2048;
+constexpr int kFftElemsContig = 1024;
 
 bool fft_size_ok(int n) { return n >= 2 && n <= 1024 && (n & (n - 1)) == 0; }
 
@@ -202,7 +205,7 @@ hipError_t launch_radial_filter(const float *in, float *out, float2 *work, int n
     // under 2048 blocks (down to 8 lines on strided axes, so that a block's
     // global accesses still cover 64 contiguous bytes)
     auto pick_B = [&](int n, long lines, bool strided) {
-        long B = kFftElems / n;
+        long B = (strided ? kFftElems : kFftElemsContig) / n;
         if (B > lines) B = lines;
         const long bmin = strided ? 8 : 1;
         while (B > bmin && lines / B < 2048) B >>= 1;
